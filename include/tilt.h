@@ -1,0 +1,195 @@
+/*
+ * tilt.h -- C interface of the MI355X TILT solver (LADMAP with warm starts).
+ *
+ * Problem (Ren & Lin, arXiv 1205.5351, Eq. TILT_2 and Alg. 1): given a
+ * grey-level image D and an initial transform tau0 of an m x n window, find
+ * the transform tau, a low-rank texture A and sparse errors E with
+ *
+ *     min ||A||_* + lambda ||E||_1   s.t.   D o tau = A + E,
+ *
+ * by the outer loop of Alg. 1 (normalise, Jacobian, inner solve, Delta tau
+ * from Eq. Delta_tau, tau += Delta tau) around the LADMAP inner loop of
+ * Sec. 3.2 in the form of Sec. 4.2 (two J_perp products per iteration,
+ * Y kept in span(J_perp)) with the variable warm start of Eq. warm_start and
+ * Eq. warm_start_Y.  The extra constraints Q Delta tau = 0 of Sec. 4.3 fix
+ * the image of the window centre and the area of the image of the window
+ * to first order.
+ *
+ * Conventions shared by every entry point
+ *   - image: row-major float32, pixel centres at integer (x = column,
+ *     y = row); row_stride counts elements.  Height and width >= 2.
+ *   - rectified grid: rows i = 0..m-1, columns j = 0..n-1 with centred
+ *     coordinates u = j - (n-1)/2, v = i - (m-1)/2.
+ *   - a transform is a 3x3 row-major homography H with
+ *     (x, y, 1) ~ H (u, v, 1); H[2][2] = 1.  The affine model requires the
+ *     last row (0, 0, 1).  Inside the solver tau lives in coordinates scaled
+ *     by s = max(m, n)/2 about the image of the window centre; tau0 and the
+ *     returned tau are always pixel homographies.
+ *   - bilinear sampling; outside the image samples are clamped to the
+ *     border and the gradient along the clamped axis is zero.
+ *   - A and E are m x n row-major float32.
+ *
+ * Status codes: 0 = OK, > 0 = warning, < 0 = error.  No entry point throws
+ * or aborts; each returns the worst per-patch status it saw.
+ */
+#ifndef TILT_H
+#define TILT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum tilt_status {
+    TILT_OK = 0,
+    TILT_WARN_MAXITER = 1,     /* an inner loop stopped at max_inner       */
+    TILT_PENDING = 2,          /* tilt_poll: request not finished yet      */
+    TILT_ERR_ARG = -1,         /* invalid argument                         */
+    TILT_ERR_NOMEM = -2,       /* device allocation failed / over budget   */
+    TILT_ERR_DEVICE = -3,      /* HIP runtime error                        */
+    TILT_ERR_SINGULAR = -4,    /* J^T J not positive definite (flat image) */
+    TILT_ERR_NONFINITE = -5,   /* NaN/Inf in the iteration                 */
+    TILT_ERR_TOO_LARGE = -6,   /* patch does not fit the on-chip SVT       */
+    TILT_ERR_NOT_FOUND = -7    /* unknown ticket                           */
+};
+
+enum tilt_model { TILT_AFFINE = 6, TILT_PROJECTIVE = 8 };
+
+/* Solver parameters.  Names follow the paper: lambda (Eq. TILT_2), eps1 and
+ * eps2 (Eqs. Cond1, Cond2, rho), rho0 and mu_max (Eqs. mu, rho).  The paper
+ * gives no values; defaults come from tilt_default_params(). */
+typedef struct {
+    double lambda;      /* <= 0: 1/sqrt(max(m, n))                            */
+    double eps1;        /* Cond1 threshold, default 1e-5                      */
+    double eps2;        /* Cond2 and rho threshold, default 1e-3              */
+    double eps_outer;   /* outer stop when ||Delta tau||_2 < eps_outer
+                           (scaled coordinates), default 1e-5                 */
+    double mu0;         /* <= 0: 1.25 / ||D o tau||_2 at each inner start      */
+    double rho0;        /* >= 1, default 1.5                                  */
+    double mu_max;      /* default 1e10                                       */
+    int max_inner;      /* default 2000                                       */
+    int max_outer;      /* default 50                                         */
+    int fixed_iters;    /* 1: run exactly max_outer x max_inner iterations
+                           (stop tests evaluated but ignored)                 */
+    int svt_mode;       /* 0: cold one-sided Jacobi SVT every iteration       */
+    float jacobi_tol;   /* rotate a pair when |a.b| > tol ||a|| ||b||; 1e-6   */
+    int max_sweeps;     /* Jacobi sweep cap, default 40                       */
+} tilt_params;
+
+/* One window of one image. */
+typedef struct {
+    const float* image;     /* host (tilt_solve) or device (batch) pointer    */
+    int height, width;
+    long long row_stride;   /* elements between rows, >= width                */
+    int m, n;               /* rectified rows, columns (>= 2 each)            */
+    int model;              /* TILT_AFFINE or TILT_PROJECTIVE                 */
+    int reserved;
+    double tau0[9];         /* initial pixel homography                       */
+} tilt_problem;
+
+/* Work counters of one solve (used for roofline accounting). */
+typedef struct {
+    long long inner_iters;      /* LADMAP iterations                          */
+    long long svt_calls;        /* singular value decompositions              */
+    long long jacobi_sweeps;    /* Jacobi sweeps over all SVDs                */
+    long long jacobi_pairs;     /* column pairs examined                      */
+    long long jacobi_rotations; /* column pairs rotated                       */
+    long long recon_rows;       /* sum over SVDs of singular values kept      */
+} tilt_counters;
+
+typedef struct {
+    double tau[9];          /* final pixel homography                         */
+    float* A;               /* out: m*n, caller-owned; may be NULL            */
+    float* E;               /* out: m*n, caller-owned; may be NULL            */
+    int outer_iters;
+    int inner_iters_total;
+    int svt_rank;           /* #singular values of the last M above 1/mu      */
+    int status;
+    double objective;       /* ||A||_* + lambda ||E||_1 of the returned A, E  */
+    double mu;              /* penalty at the end of the last inner loop      */
+    double cond1, cond2;    /* last values of the Cond1 / Cond2 quantities    */
+    double dtau_norm;       /* ||Delta tau||_2 of the last outer iteration    */
+    tilt_counters counters;
+} tilt_result;
+
+/* Fill *p with the defaults listed above. */
+void tilt_default_params(tilt_params* p);
+
+/* Human-readable status. */
+const char* tilt_status_string(int status);
+
+/* Library version string. */
+const char* tilt_version(void);
+
+/* Homography that maps the centred m x n grid onto a quadrilateral given
+ * by its corners TL, TR, BR, BL as (x, y) image pixels (8 doubles).  For
+ * TILT_AFFINE the quad must be a parallelogram (the TL, TR, BL corners are
+ * used).  Returns TILT_ERR_ARG for degenerate quads. */
+int tilt_tau_from_quad(const double quad[8], int m, int n, int model, double tau_out[9]);
+
+/* Plain single-patch path: host pointers in and out, synchronous, on the
+ * current device.  Runs Alg. 1 step by step with one kernel per step and one
+ * device-to-host read of the stop flags per inner iteration.  Allocates and
+ * frees its own device memory. */
+int tilt_solve(const tilt_problem* prob, const tilt_params* prm, tilt_result* res);
+
+/* ------------------------------------------------------------------------
+ * Contexts, batches and serving.
+ * ---------------------------------------------------------------------- */
+typedef struct tilt_ctx tilt_ctx;
+
+/* Create a context on `device` (HIP ordinal).  hbm_budget_bytes bounds the
+ * device workspace the context may hold (0 = 1/2 of free memory). */
+int tilt_ctx_create(tilt_ctx** ctx, int device, size_t hbm_budget_bytes);
+int tilt_ctx_destroy(tilt_ctx* ctx);
+
+/* Bytes of device workspace one problem needs (for admission control). */
+size_t tilt_workspace_bytes(const tilt_problem* prob);
+
+/* Batched path: `count` problems whose image pointers are DEVICE pointers
+ * and whose results' A/E pointers are DEVICE pointers (or NULL).  Runs one
+ * fused persistent kernel in which every workgroup solves whole patches
+ * from a work queue.  `hip_stream` is a hipStream_t (NULL = default
+ * stream).  Returns after the results are on the host (the stream is
+ * synchronised).  Per-patch results equal those of tilt_solve. */
+int tilt_solve_batch(tilt_ctx* ctx, const tilt_problem* probs, int count,
+                     const tilt_params* prm, tilt_result* results, void* hip_stream);
+
+/* Like tilt_solve_batch but forces the step-by-step (plain) kernels for
+ * every patch in turn.  Same results, for timing comparisons. */
+int tilt_solve_batch_plain(tilt_ctx* ctx, const tilt_problem* probs, int count,
+                           const tilt_params* prm, tilt_result* results, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Components of the hot path, exposed for checking and benchmarking.
+ * All pointers are DEVICE pointers unless stated; calls synchronise the
+ * stream before returning.
+ * ---------------------------------------------------------------------- */
+
+/* Singular value shrinkage A_i = S_{eps_i}(M_i) = U T_eps(Sigma) V^T
+ * (Eqs. A_1 and S_operator) of `count` m x n row-major matrices stored back
+ * to back (M + i*m*n), by the same one-sided Jacobi used inside the solver.
+ * eps: HOST array of count non-negative floats.  sigma (count*min(m, n),
+ * unsorted) may be NULL.  ranks (HOST, count) receives #{sigma > eps_i} and
+ * counters (HOST) the summed work counters; both may be NULL.  Only the
+ * Jacobi fields of prm are read. */
+int tilt_svt_batch(tilt_ctx* ctx, const float* M, float* A, float* sigma, int count, int m, int n,
+                   const float* eps, const tilt_params* prm, int* ranks, tilt_counters* counters,
+                   void* hip_stream);
+
+/* Alg. 1 Step 1 on its own: the normalised warp D o tau / ||D o tau||_F
+ * (I_out: count x m x n) and the Jacobian of the normalised warp w.r.t.
+ * the p entries of tau in scaled coordinates (J_out: count x p x m x n,
+ * parameter-major; order h11 h12 h13 h21 h22 h23 [h31 h32]).  The scaled
+ * coordinates are those of the window given by probs[i].tau0; taus (HOST,
+ * count x 9) are the pixel homographies at which to evaluate.  All
+ * problems must share m, n and model. */
+int tilt_warp_jacobian(tilt_ctx* ctx, const tilt_problem* probs, const double* taus, int count,
+                       float* I_out, float* J_out, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TILT_H */

@@ -1,0 +1,91 @@
+// Internal declarations shared by the HIP kernels and the host interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tilt {
+
+constexpr int NT = 256;          // threads per workgroup, every kernel
+constexpr int NWAVE = NT / 64;   // wavefronts per workgroup
+constexpr int MAXP = 8;          // transform parameters (projective)
+constexpr int MAXPP = 5;         // free parameters after the 3 constraints
+constexpr int NPLANES = 6 + MAXP;
+constexpr int LDS_LIMIT = 160 * 1024;
+
+// Per-patch device planes, each nc * ldg floats in "X layout": the matrix
+// is stored with its shorter side as the outer index, so the vectors the
+// one-sided Jacobi orthogonalises (length nr = max(m, n)) are contiguous.
+enum Plane { PL_I = 0, PL_A = 1, PL_E = 2, PL_Y = 3, PL_R = 4, PL_M = 5, PL_Q = 6 };
+
+// Jacobi variants: lanes per column pair and float4 chunks held per lane.
+enum SvtCfg { SVT_L4C4 = 0, SVT_L4C8 = 1, SVT_L8C8 = 2, SVT_L8C16 = 3, SVT_NCFG = 4 };
+
+struct PatchDesc {
+    const float* image;
+    long long stride;
+    int H, W;
+    int m, n, model, pp;      // pp = number of free parameters = model - 3
+    int nc, nr, ldg, colmajor;
+    int ld;                   // LDS row stride of the Jacobi matrix
+    int svt_cfg;
+    int tb;                   // rows per reconstruction block
+    int pad0;
+    double cx, cy, s;
+    double lam;
+    float* ws;                // NPLANES planes
+    float* A_out;             // m x n row-major (may be null)
+    float* E_out;
+};
+
+struct PatchState {
+    double tau[MAXP];
+    double NQ[MAXP * MAXPP];  // orthonormal basis of null(Q), p x pp
+    double R[MAXPP * MAXPP];  // J~ = Qb R (upper triangular)
+    double mu, c, dtau_norm, cond1, cond2, nuc, l1, objective;
+    double dA2, dE2;
+    int outer, inner, inner_total, done_inner, done_outer, status, svt_rank, warn;
+    long long svt_calls, sweeps, pairs, rotations, recon_rows;
+};
+
+struct SolverParams {
+    double eps1, eps2, eps_outer, mu0, rho0, mu_max;
+    int max_inner, max_outer, fixed_iters, max_sweeps;
+    float jacobi_tol;
+    int pad;
+};
+
+// Standalone SVT job (component entry point).
+struct SvtJob {
+    const float* M;   // m x n row-major
+    float* A;         // m x n row-major
+    float* sigma;     // min(m, n) singular values (unsorted), may be null
+    int m, n;
+    float eps;
+    int pad;
+};
+
+// LDS layout helpers (host and device).
+__host__ __device__ inline int svt_lpp(int cfg) { return (cfg == SVT_L4C4 || cfg == SVT_L4C8) ? 4 : 8; }
+__host__ __device__ inline int svt_maxch(int cfg) {
+    return cfg == SVT_L4C4 ? 4 : (cfg == SVT_L8C16 ? 16 : 8);
+}
+
+// Kernel launchers (tilt_kernels.hip).
+hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count,
+                        int* queue, int grid, size_t lds, hipStream_t s);
+hipError_t launch_setup(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx,
+                        size_t lds, hipStream_t s);
+hipError_t launch_svt(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx,
+                      size_t lds, hipStream_t s);
+hipError_t launch_update(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx,
+                         hipStream_t s);
+hipError_t launch_dtau(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx,
+                       hipStream_t s);
+hipError_t launch_finalize(const PatchDesc* d, PatchState* st, int idx, hipStream_t s);
+hipError_t launch_step1(const PatchDesc* d, PatchState* st, int count, float* I_out, float* J_out,
+                        hipStream_t s);
+hipError_t launch_svt_jobs(const SvtJob* jobs, int count, int cfg, int ld, int tb, float tol,
+                           int max_sweeps, long long* counters, float* scratch, size_t lds, hipStream_t s);
+
+}  // namespace tilt

@@ -1,0 +1,1385 @@
+// HIP kernels for TILT solved by LADMAP with variable warm start (gfx950).
+//
+// One workgroup of 256 threads owns one patch at a time.  Every step of
+// Alg. 1 is a device function that the whole workgroup calls:
+//
+//   dev_setup    Alg. 1 Step 1 + Sec. 4.3 constraints + Sec. 4.2 warm start:
+//                bilinear warp and exact interpolant gradient, normalisation,
+//                Jacobian of the normalised warp, reduced Jacobian J~ = J N_Q,
+//                orthonormal basis Qb of span(J~) (Cholesky-QR twice, FP64
+//                factors), Y <- J~perp Y, R <- J~perp(A + E - I),
+//                c = ||J~perp I||_F, mu_0 = 1.25 / ||I||_2.
+//   dev_svt      M = A - R - Y/mu and A <- S_{1/mu}(M) (Eqs. A, A_1,
+//                S_operator): one-sided Jacobi on the rows of M held in LDS,
+//                then S(M) = sum_j (1 - eps/s_j)/s_j^2 (M b_j) b_j^T over the
+//                orthogonalised rows b_j with s_j = ||b_j|| > eps.
+//   dev_update   N, E <- T_{lam/mu}(N) (Eq. E_1), R <- J~perp(A + E - I),
+//                Y <- Y + mu R (Eq. Y), Cond1/Cond2 (Eqs. Cond1, Cond2) and
+//                the adaptive penalty (Eqs. mu, rho).
+//   dev_dtau     Delta tau = N_Q R^{-1} Qb^T (A + E - I) (Eq. Delta_tau with
+//                the constraints eliminated), tau += Delta tau (FP64).
+//
+// The plain path launches one kernel per step; the batched path runs all
+// steps of whole patches in one persistent kernel.  Both call the same
+// device functions with the same workgroup shape, so a patch gives the same
+// bits either way.
+
+#include "tilt_internal.h"
+
+namespace tilt {
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+
+__device__ inline float wave_sum_f(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum K values over the workgroup; every thread receives the same bits.
+template <int K>
+__device__ inline void block_sum_f(float (&v)[K]) {
+    __shared__ float red[K * NWAVE];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum_f(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[k * NWAVE + w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        float s = red[k * NWAVE];
+#pragma unroll
+        for (int i = 1; i < NWAVE; ++i) s += red[k * NWAVE + i];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+template <int K>
+__device__ inline void block_sum_d(double (&v)[K]) {
+    __shared__ double red[K * NWAVE];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum_d(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[k * NWAVE + w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = red[k * NWAVE];
+#pragma unroll
+        for (int i = 1; i < NWAVE; ++i) s += red[k * NWAVE + i];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+__device__ inline long long block_sum_ll(long long v) {
+    __shared__ long long red[NT];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    long long r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Cross-lane moves inside a group of 4 or 8 consecutive lanes (DPP).
+__device__ inline float dpp_xor1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ inline float dpp_xor2(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+}
+__device__ inline float dpp_half_mirror(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+}
+
+// Sum over the LPP lanes of a group; all lanes get identical bits.
+template <int LPP>
+__device__ inline float group_sum(float v) {
+    v += dpp_xor1(v);
+    v += dpp_xor2(v);
+    if (LPP >= 8) v += dpp_half_mirror(v);
+    return v;
+}
+
+__device__ inline float4 f4(float a) { return make_float4(a, a, a, a); }
+
+// ---------------------------------------------------------------------------
+// One-sided Jacobi on the rows of B (LDS), round-robin ordering.
+//
+// Rows 0..nc-1 (plus a zero row when nc is odd) of length 4*nr4 with stride
+// ld.  Each round pairs every row with another (circle method: the last
+// index is fixed, pair k of round r is (r+k, r-k) mod N); a group of LPP
+// lanes owns one pair, holds both rows in registers, reduces the three inner
+// products with DPP and applies the rotation that makes the pair
+// orthogonal.  A pair is rotated when |a.b| > tol ||a|| ||b||; the sweeps
+// stop when a whole sweep rotates nothing.
+// ---------------------------------------------------------------------------
+
+struct JacobiStats {
+    long long sweeps, pairs, rotations;
+};
+
+template <int LPP, int MAXCH>
+__device__ void jacobi_rows(float* B, int nc, int nr4, int ld, float tol, int max_sweeps,
+                            JacobiStats& js) {
+    const int tid = threadIdx.x;
+    const int g = tid / LPP, q = tid % LPP;
+    constexpr int G = NT / LPP;
+    const int ncp = nc + (nc & 1);
+    const int P = ncp >> 1, N = ncp - 1;
+    long long rots = 0;
+    int sweeps = 0;
+    if (ncp >= 2) {
+        for (int sw = 0; sw < max_sweeps; ++sw) {
+            int any = 0;
+            for (int r = 0; r < N; ++r) {
+                for (int k = g; k < P; k += G) {
+                    int i, j;
+                    if (k == 0) {
+                        i = N;
+                        j = r;
+                    } else {
+                        i = r + k;
+                        if (i >= N) i -= N;
+                        j = r - k;
+                        if (j < 0) j += N;
+                    }
+                    float* pa = B + i * ld;
+                    float* pb = B + j * ld;
+                    float4 a[MAXCH], b[MAXCH];
+                    float al = 0.f, be = 0.f, ga = 0.f;
+#pragma unroll
+                    for (int c = 0; c < MAXCH; ++c) {
+                        const int ch = q + c * LPP;
+                        if (ch < nr4) {
+                            a[c] = *reinterpret_cast<const float4*>(pa + 4 * ch);
+                            b[c] = *reinterpret_cast<const float4*>(pb + 4 * ch);
+                        } else {
+                            a[c] = f4(0.f);
+                            b[c] = f4(0.f);
+                        }
+                        al = fmaf(a[c].x, a[c].x, al);
+                        al = fmaf(a[c].y, a[c].y, al);
+                        al = fmaf(a[c].z, a[c].z, al);
+                        al = fmaf(a[c].w, a[c].w, al);
+                        be = fmaf(b[c].x, b[c].x, be);
+                        be = fmaf(b[c].y, b[c].y, be);
+                        be = fmaf(b[c].z, b[c].z, be);
+                        be = fmaf(b[c].w, b[c].w, be);
+                        ga = fmaf(a[c].x, b[c].x, ga);
+                        ga = fmaf(a[c].y, b[c].y, ga);
+                        ga = fmaf(a[c].z, b[c].z, ga);
+                        ga = fmaf(a[c].w, b[c].w, ga);
+                    }
+                    al = group_sum<LPP>(al);
+                    be = group_sum<LPP>(be);
+                    ga = group_sum<LPP>(ga);
+                    if (fabsf(ga) > tol * (sqrtf(al) * sqrtf(be))) {
+                        const float zeta = (be - al) / (2.0f * ga);
+                        const float t = copysignf(1.0f, zeta) / (fabsf(zeta) + sqrtf(1.0f + zeta * zeta));
+                        const float cs = 1.0f / sqrtf(1.0f + t * t);
+                        const float sn = cs * t;
+#pragma unroll
+                        for (int c = 0; c < MAXCH; ++c) {
+                            const int ch = q + c * LPP;
+                            if (ch < nr4) {
+                                float4 na, nb;
+                                na.x = cs * a[c].x - sn * b[c].x;
+                                na.y = cs * a[c].y - sn * b[c].y;
+                                na.z = cs * a[c].z - sn * b[c].z;
+                                na.w = cs * a[c].w - sn * b[c].w;
+                                nb.x = sn * a[c].x + cs * b[c].x;
+                                nb.y = sn * a[c].y + cs * b[c].y;
+                                nb.z = sn * a[c].z + cs * b[c].z;
+                                nb.w = sn * a[c].w + cs * b[c].w;
+                                *reinterpret_cast<float4*>(pa + 4 * ch) = na;
+                                *reinterpret_cast<float4*>(pb + 4 * ch) = nb;
+                            }
+                        }
+                        any = 1;
+                        if (q == 0) ++rots;
+                    }
+                }
+                __syncthreads();
+            }
+            ++sweeps;
+            if (!__syncthreads_or(any)) break;
+        }
+    }
+    js.sweeps += sweeps;
+    js.pairs += (long long)sweeps * P * N;
+    js.rotations += block_sum_ll(rots);
+}
+
+// Squared norms of rows 0..nc-1 of B into s2 (LDS); same reduction shape as
+// the Jacobi inner products.
+template <int LPP, int MAXCH>
+__device__ void row_norms(const float* B, int nc, int nr4, int ld, float* s2) {
+    const int tid = threadIdx.x;
+    const int g = tid / LPP, q = tid % LPP;
+    constexpr int G = NT / LPP;
+    for (int j = g; j < nc; j += G) {
+        const float* pj = B + j * ld;
+        float v = 0.f;
+#pragma unroll
+        for (int c = 0; c < MAXCH; ++c) {
+            const int ch = q + c * LPP;
+            if (ch < nr4) {
+                const float4 x = *reinterpret_cast<const float4*>(pj + 4 * ch);
+                v = fmaf(x.x, x.x, v);
+                v = fmaf(x.y, x.y, v);
+                v = fmaf(x.z, x.z, v);
+                v = fmaf(x.w, x.w, v);
+            }
+        }
+        v = group_sum<LPP>(v);
+        if (q == 0) s2[j] = v;
+    }
+    __syncthreads();
+}
+
+__device__ void jacobi_dispatch(int cfg, float* B, int nc, int nr4, int ld, float tol, int max_sweeps,
+                                JacobiStats& js, float* s2) {
+    switch (cfg) {
+        case SVT_L4C4:
+            jacobi_rows<4, 4>(B, nc, nr4, ld, tol, max_sweeps, js);
+            row_norms<4, 4>(B, nc, nr4, ld, s2);
+            break;
+        case SVT_L4C8:
+            jacobi_rows<4, 8>(B, nc, nr4, ld, tol, max_sweeps, js);
+            row_norms<4, 8>(B, nc, nr4, ld, s2);
+            break;
+        case SVT_L8C8:
+            jacobi_rows<8, 8>(B, nc, nr4, ld, tol, max_sweeps, js);
+            row_norms<8, 8>(B, nc, nr4, ld, s2);
+            break;
+        default:
+            jacobi_rows<8, 16>(B, nc, nr4, ld, tol, max_sweeps, js);
+            row_norms<8, 16>(B, nc, nr4, ld, s2);
+            break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Singular value shrinkage from the orthogonalised rows.
+//
+// With B = V^T X (rows b_j orthogonal, s_j = ||b_j||) the SVD of X is
+// V diag(s) (B/s)^T rows, so S_eps(X) = sum_{s_j > eps} (1 - eps/s_j)/s_j^2
+// (X b_j^T) b_j.  Computed in blocks of TB rows of X:
+//   C = Xblk B_act^T,  Cw = C diag(w),  A_blk = Cw B_act.
+// ---------------------------------------------------------------------------
+
+__device__ void shrink_weights(const float* s2, int nc, float eps, float* w, int* act, int* k_out,
+                               double* nuc_out) {
+    __shared__ int sh_k;
+    __shared__ double sh_nuc;
+    if (threadIdx.x == 0) {
+        int k = 0;
+        double nuc = 0.0;
+        for (int j = 0; j < nc; ++j) {
+            const float sg = sqrtf(s2[j]);
+            if (sg > eps) {
+                w[j] = (1.0f - eps / sg) / s2[j];
+                act[k++] = j;
+                nuc += (double)sg - (double)eps;
+            } else {
+                w[j] = 0.f;
+            }
+        }
+        sh_k = k;
+        sh_nuc = nuc;
+    }
+    __syncthreads();
+    *k_out = sh_k;
+    *nuc_out = sh_nuc;
+    __syncthreads();
+}
+
+// Returns this thread's partial sum of (A_new - A_old)^2 when track_diff.
+__device__ float reconstruct(const float* B, int ld, const float* Xg, float* Ag, int nc, int nr4, int ldg,
+                             const float* w, const int* act, int k, int TB, float* xblk, float* cwt,
+                             bool track_diff) {
+    const int tid = threadIdx.x;
+    const int tb4 = TB >> 2;
+    const int k4 = (k + 3) >> 2;
+    float dsum = 0.f;
+    for (int i0 = 0; i0 < nc; i0 += TB) {
+        for (int idx = tid; idx < TB * nr4; idx += NT) {
+            const int ii = idx / nr4, c = idx - ii * nr4;
+            float4 v = f4(0.f);
+            if (i0 + ii < nc) v = reinterpret_cast<const float4*>(Xg + (size_t)(i0 + ii) * ldg)[c];
+            *reinterpret_cast<float4*>(xblk + ii * ld + 4 * c) = v;
+        }
+        __syncthreads();
+        for (int tile = tid; tile < tb4 * k4; tile += NT) {
+            const int ii4 = tile % tb4, jj4 = tile / tb4;
+            int jr[4];
+            float wj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int jj = 4 * jj4 + u;
+                if (jj < k) {
+                    jr[u] = act[jj];
+                    wj[u] = w[jr[u]];
+                } else {
+                    jr[u] = act[0];
+                    wj[u] = 0.f;
+                }
+            }
+            float acc[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[a][u] = 0.f;
+            for (int c = 0; c < nr4; ++c) {
+                float4 x[4], b[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) x[a] = *reinterpret_cast<const float4*>(xblk + (4 * ii4 + a) * ld + 4 * c);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) b[u] = *reinterpret_cast<const float4*>(B + jr[u] * ld + 4 * c);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        float s = acc[a][u];
+                        s = fmaf(x[a].x, b[u].x, s);
+                        s = fmaf(x[a].y, b[u].y, s);
+                        s = fmaf(x[a].z, b[u].z, s);
+                        s = fmaf(x[a].w, b[u].w, s);
+                        acc[a][u] = s;
+                    }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) cwt[(4 * jj4 + u) * TB + 4 * ii4 + a] = acc[a][u] * wj[u];
+        }
+        __syncthreads();
+        for (int tile = tid; tile < tb4 * nr4; tile += NT) {
+            const int r4 = tile % nr4, ii4 = tile / nr4;
+            float4 acc[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a] = f4(0.f);
+            for (int jj = 0; jj < k; ++jj) {
+                const float4 cw = *reinterpret_cast<const float4*>(cwt + jj * TB + 4 * ii4);
+                const float4 b = *reinterpret_cast<const float4*>(B + act[jj] * ld + 4 * r4);
+                acc[0].x = fmaf(cw.x, b.x, acc[0].x); acc[0].y = fmaf(cw.x, b.y, acc[0].y);
+                acc[0].z = fmaf(cw.x, b.z, acc[0].z); acc[0].w = fmaf(cw.x, b.w, acc[0].w);
+                acc[1].x = fmaf(cw.y, b.x, acc[1].x); acc[1].y = fmaf(cw.y, b.y, acc[1].y);
+                acc[1].z = fmaf(cw.y, b.z, acc[1].z); acc[1].w = fmaf(cw.y, b.w, acc[1].w);
+                acc[2].x = fmaf(cw.z, b.x, acc[2].x); acc[2].y = fmaf(cw.z, b.y, acc[2].y);
+                acc[2].z = fmaf(cw.z, b.z, acc[2].z); acc[2].w = fmaf(cw.z, b.w, acc[2].w);
+                acc[3].x = fmaf(cw.w, b.x, acc[3].x); acc[3].y = fmaf(cw.w, b.y, acc[3].y);
+                acc[3].z = fmaf(cw.w, b.z, acc[3].z); acc[3].w = fmaf(cw.w, b.w, acc[3].w);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int row = i0 + 4 * ii4 + a;
+                if (row < nc) {
+                    float4* p = reinterpret_cast<float4*>(Ag + (size_t)row * ldg) + r4;
+                    if (track_diff) {
+                        const float4 o = *p;
+                        const float dx = acc[a].x - o.x, dy = acc[a].y - o.y;
+                        const float dz = acc[a].z - o.z, dw = acc[a].w - o.w;
+                        dsum = fmaf(dx, dx, dsum);
+                        dsum = fmaf(dy, dy, dsum);
+                        dsum = fmaf(dz, dz, dsum);
+                        dsum = fmaf(dw, dw, dsum);
+                    }
+                    *p = acc[a];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    return dsum;
+}
+
+// LDS carve-up shared by the setup and SVT steps.
+struct SvtLds {
+    float* B;
+    float* xblk;
+    float* cwt;
+    float* s2;
+    float* w;
+    int* act;
+};
+
+__device__ inline SvtLds carve_lds(float* base, int nc, int ld, int tb) {
+    SvtLds L;
+    const int ncp = nc + (nc & 1);
+    const int nc4 = (nc + 3) & ~3;
+    L.B = base;
+    L.xblk = L.B + ncp * ld;
+    L.cwt = L.xblk + tb * ld;
+    L.s2 = L.cwt + nc4 * tb;
+    L.w = L.s2 + nc4;
+    L.act = reinterpret_cast<int*>(L.w + nc4);
+    return L;
+}
+
+// Load an X-layout plane into the Jacobi matrix in LDS and clear padding.
+__device__ void load_rows_lds(const float* Xg, int nc, int ldg, int ld, float* B) {
+    const int tid = threadIdx.x;
+    const int nr4 = ldg >> 2;
+    const int ncp = nc + (nc & 1);
+    for (int idx = tid; idx < nc * nr4; idx += NT) {
+        const int row = idx / nr4, c = idx - row * nr4;
+        *reinterpret_cast<float4*>(B + row * ld + 4 * c) = reinterpret_cast<const float4*>(Xg + (size_t)row * ldg)[c];
+    }
+    if (ncp > nc) {
+        for (int c = tid; c < ld; c += NT) B[nc * ld + c] = 0.f;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Geometry (Alg. 1 Step 1): bilinear sample and the coordinate Jacobian.
+// ---------------------------------------------------------------------------
+
+__device__ inline void xlayout_to_ij(const PatchDesc& d, int row, int col, int& i, int& j) {
+    if (d.colmajor) {
+        j = row;
+        i = col;
+    } else {
+        i = row;
+        j = col;
+    }
+}
+
+// Sample D o tau at grid point (i, j) and the raw Jacobian d(D o tau)/dtau.
+__device__ inline float warp_pixel(const PatchDesc& d, const double* h, int i, int j, float* jraw) {
+    const double s = d.s;
+    const double ut = ((double)j - 0.5 * (double)(d.n - 1)) / s;
+    const double vt = ((double)i - 0.5 * (double)(d.m - 1)) / s;
+    const double X = h[0] * ut + h[1] * vt + h[2];
+    const double Y = h[3] * ut + h[4] * vt + h[5];
+    const double Wh = h[6] * ut + h[7] * vt + 1.0;
+    const double iw = 1.0 / Wh;
+    const double xt = X * iw, yt = Y * iw;
+    const double x = s * xt + d.cx, y = s * yt + d.cy;
+    const double xc = fmin(fmax(x, 0.0), (double)(d.W - 1));
+    const double yc = fmin(fmax(y, 0.0), (double)(d.H - 1));
+    const int x0 = min((int)floor(xc), d.W - 2);
+    const int y0 = min((int)floor(yc), d.H - 2);
+    const float fx = (float)(xc - (double)x0);
+    const float fy = (float)(yc - (double)y0);
+    const float* r0 = d.image + (long long)y0 * d.stride + x0;
+    const float* r1 = r0 + d.stride;
+    const float v00 = r0[0], v01 = r0[1], v10 = r1[0], v11 = r1[1];
+    const float val = (1.f - fy) * ((1.f - fx) * v00 + fx * v01) + fy * ((1.f - fx) * v10 + fx * v11);
+    const bool inx = (x >= 0.0) && (x <= (double)(d.W - 1));
+    const bool iny = (y >= 0.0) && (y <= (double)(d.H - 1));
+    const float gx = inx ? (1.f - fy) * (v01 - v00) + fy * (v11 - v10) : 0.f;
+    const float gy = iny ? (1.f - fx) * (v10 - v00) + fx * (v11 - v01) : 0.f;
+    const double sw = s * iw;
+    const double gxd = gx, gyd = gy;
+    jraw[0] = (float)(gxd * sw * ut);
+    jraw[1] = (float)(gxd * sw * vt);
+    jraw[2] = (float)(gxd * sw);
+    jraw[3] = (float)(gyd * sw * ut);
+    jraw[4] = (float)(gyd * sw * vt);
+    jraw[5] = (float)(gyd * sw);
+    jraw[6] = (float)(-(gxd * xt + gyd * yt) * sw * ut);
+    jraw[7] = (float)(-(gxd * xt + gyd * yt) * sw * vt);
+    return val;
+}
+
+__device__ inline void tau_to_h(const PatchState* st, int model, double* h) {
+    for (int k = 0; k < 6; ++k) h[k] = st->tau[k];
+    h[6] = model == 8 ? st->tau[6] : 0.0;
+    h[7] = model == 8 ? st->tau[7] : 0.0;
+}
+
+// Gradient of the area of the image of the rectified rectangle w.r.t. tau
+// (normalised units), from the shoelace formula over the corners TL, TR, BR, BL.
+__device__ void area_gradient(const PatchDesc& d, const double* h, double* g) {
+    const double a = (double)(d.n - 1) / (2.0 * d.s);
+    const double b = (double)(d.m - 1) / (2.0 * d.s);
+    const double cu[4] = {-a, a, a, -a};
+    const double cv[4] = {-b, -b, b, b};
+    double xs[4], ys[4], dx[4][MAXP], dy[4][MAXP];
+    for (int c = 0; c < 4; ++c) {
+        const double u = cu[c], v = cv[c];
+        const double X = h[0] * u + h[1] * v + h[2];
+        const double Y = h[3] * u + h[4] * v + h[5];
+        const double Wd = h[6] * u + h[7] * v + 1.0;
+        const double xt = X / Wd, yt = Y / Wd;
+        xs[c] = xt;
+        ys[c] = yt;
+        for (int k = 0; k < MAXP; ++k) dx[c][k] = dy[c][k] = 0.0;
+        dx[c][0] = u / Wd;
+        dx[c][1] = v / Wd;
+        dx[c][2] = 1.0 / Wd;
+        dy[c][3] = u / Wd;
+        dy[c][4] = v / Wd;
+        dy[c][5] = 1.0 / Wd;
+        dx[c][6] = -xt * u / Wd;
+        dx[c][7] = -xt * v / Wd;
+        dy[c][6] = -yt * u / Wd;
+        dy[c][7] = -yt * v / Wd;
+    }
+    for (int k = 0; k < MAXP; ++k) {
+        double acc = 0.0;
+        for (int c = 0; c < 4; ++c) {
+            const int c2 = (c + 1) & 3;
+            acc += dx[c][k] * ys[c2] + xs[c] * dy[c2][k] - dx[c2][k] * ys[c] - xs[c2] * dy[c][k];
+        }
+        g[k] = 0.5 * acc;
+    }
+    if (d.model != 8) g[6] = g[7] = 0.0;
+}
+
+// Orthonormal basis of null(Q) with Q = [e_h13; e_h23; grad area]: the
+// translation entries are frozen and a Householder reflection of the area
+// gradient restricted to the other entries spans its complement.
+__device__ bool null_basis(const PatchDesc& d, const double* g, double* NQ) {
+    const int p = d.model;
+    int idx[MAXP];
+    int f = 0;
+    for (int k = 0; k < p; ++k)
+        if (k != 2 && k != 5) idx[f++] = k;
+    double v[MAXP];
+    double nrm2 = 0.0;
+    for (int a = 0; a < f; ++a) {
+        v[a] = g[idx[a]];
+        nrm2 += v[a] * v[a];
+    }
+    for (int k = 0; k < MAXP * MAXPP; ++k) NQ[k] = 0.0;
+    if (!(nrm2 > 0.0)) return false;
+    const double nrm = sqrt(nrm2);
+    v[0] += (v[0] >= 0.0 ? nrm : -nrm);
+    double vv = 0.0;
+    for (int a = 0; a < f; ++a) vv += v[a] * v[a];
+    // H = I - 2 v v^T / (v^T v); columns 1..f-1 span grad^perp.
+    for (int col = 1; col < f; ++col) {
+        for (int a = 0; a < f; ++a) {
+            const double hv = (a == col ? 1.0 : 0.0) - 2.0 * v[a] * v[col] / vv;
+            NQ[idx[a] * MAXPP + (col - 1)] = hv;
+        }
+    }
+    return true;
+}
+
+// Cholesky G = R^T R of a pp x pp SPD matrix (row-major, upper R).
+__device__ bool cholesky_upper(const double* G, int pp, double* R) {
+    for (int k = 0; k < MAXPP * MAXPP; ++k) R[k] = 0.0;
+    #pragma unroll
+    for (int i = 0; i < MAXPP; ++i) if (i < pp) {
+        double s = G[i * MAXPP + i];
+        for (int k = 0; k < i; ++k) s -= R[k * MAXPP + i] * R[k * MAXPP + i];
+        if (!(s > 0.0)) return false;
+        const double rii = sqrt(s);
+        R[i * MAXPP + i] = rii;
+        for (int j = i + 1; j < pp; ++j) {
+            double t = G[i * MAXPP + j];
+            for (int k = 0; k < i; ++k) t -= R[k * MAXPP + i] * R[k * MAXPP + j];
+            R[i * MAXPP + j] = t / rii;
+        }
+    }
+    return true;
+}
+
+// x = y R^{-1} for a row vector y (forward substitution on R^T); unrolled so
+// that x and y stay in registers.
+__device__ inline void solve_row_upper(const double* R, int pp, const double* y, double* x) {
+#pragma unroll
+    for (int l = 0; l < MAXPP; ++l) {
+        if (l < pp) {
+            double s = y[l];
+#pragma unroll
+            for (int k = 0; k < MAXPP; ++k)
+                if (k < l) s -= x[k] * R[k * MAXPP + l];
+            x[l] = s / R[l * MAXPP + l];
+        } else {
+            x[l] = 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step 1 + constraints + warm start
+// ---------------------------------------------------------------------------
+
+__device__ void dev_setup(const PatchDesc& d, PatchState* st, const SolverParams& prm, float* lds) {
+    __shared__ double sh_sIJ[MAXP];
+    __shared__ double sh_norm;
+    __shared__ double sh_NQ[MAXP * MAXPP];
+    __shared__ double sh_R[MAXPP * MAXPP];
+    __shared__ double sh_R1[MAXPP * MAXPP];
+    __shared__ int sh_fail;
+
+    const int tid = threadIdx.x;
+    const int p = d.model, pp = d.pp;
+    const int ldg = d.ldg, nr = d.nr, nc = d.nc;
+    const size_t np = (size_t)nc * ldg;
+    float* I = d.ws + PL_I * np;
+    float* A = d.ws + PL_A * np;
+    float* E = d.ws + PL_E * np;
+    float* Y = d.ws + PL_Y * np;
+    float* R = d.ws + PL_R * np;
+    float* Qp = d.ws + PL_Q * np;
+    const bool first = (st->outer == 0);
+
+    double h[8];
+    tau_to_h(st, p, h);
+
+    // Pass A: warp, raw Jacobian, ||I||^2 and I^T J_raw.
+    double acc[1 + MAXP];
+#pragma unroll
+    for (int k = 0; k <= MAXP; ++k) acc[k] = 0.0;
+    for (size_t e = tid; e < np; e += NT) {
+        const int row = (int)(e / ldg), col = (int)(e - (size_t)row * ldg);
+        if (col >= nr) {
+            I[e] = 0.f;
+            #pragma unroll
+            for (int k = 0; k < MAXP; ++k) if (k < p) Qp[k * np + e] = 0.f;
+            continue;
+        }
+        int i, j;
+        xlayout_to_ij(d, row, col, i, j);
+        float jr[MAXP];
+        const float val = warp_pixel(d, h, i, j, jr);
+        I[e] = val;
+        acc[0] += (double)val * (double)val;
+        #pragma unroll
+        for (int k = 0; k < MAXP; ++k) if (k < p) {
+            Qp[k * np + e] = jr[k];
+            acc[1 + k] += (double)val * (double)jr[k];
+        }
+    }
+    block_sum_d<1 + MAXP>(acc);
+    if (tid == 0) {
+        sh_norm = sqrt(acc[0]);
+        for (int k = 0; k < MAXP; ++k) sh_sIJ[k] = acc[1 + k];
+        double g[MAXP];
+        area_gradient(d, h, g);
+        const bool ok = null_basis(d, g, sh_NQ) && (sh_norm > 0.0) && isfinite(sh_norm);
+        sh_fail = ok ? 0 : 1;
+        for (int k = 0; k < MAXP * MAXPP; ++k) st->NQ[k] = sh_NQ[k];
+    }
+    __syncthreads();
+    if (sh_fail) {
+        if (tid == 0) {
+            st->status = (isfinite(sh_norm) ? -4 : -5);
+            st->done_outer = 1;
+            st->done_inner = 1;
+        }
+        __syncthreads();
+        return;
+    }
+    const double inv_n = 1.0 / sh_norm;
+    const double inv_n3 = inv_n * inv_n * inv_n;
+
+    // Pass B: normalise, J = J_raw/|I| - I (I^T J_raw)/|I|^3, J~ = J N_Q, Gram.
+    double gram[MAXPP * MAXPP];
+#pragma unroll
+    for (int k = 0; k < MAXPP * MAXPP; ++k) gram[k] = 0.0;
+    for (size_t e = tid; e < np; e += NT) {
+        const int row = (int)(e / ldg), col = (int)(e - (size_t)row * ldg);
+        if (col >= nr) {
+            if (first) A[e] = E[e] = Y[e] = 0.f;
+            continue;
+        }
+        const double val = (double)I[e];
+        double jt[MAXPP];
+        #pragma unroll
+        for (int l = 0; l < MAXPP; ++l) if (l < pp) jt[l] = 0.0;
+        #pragma unroll
+        for (int k = 0; k < MAXP; ++k) if (k < p) {
+            const double jk = (double)Qp[k * np + e] * inv_n - val * sh_sIJ[k] * inv_n3;
+            #pragma unroll
+            for (int l = 0; l < MAXPP; ++l) if (l < pp) jt[l] += jk * sh_NQ[k * MAXPP + l];
+        }
+        const float vn = (float)(val * inv_n);
+        I[e] = vn;
+        if (first) {
+            A[e] = vn;
+            E[e] = 0.f;
+            Y[e] = 0.f;
+        }
+        #pragma unroll
+        for (int l = 0; l < MAXPP; ++l) if (l < pp) {
+            const float f = (float)jt[l];
+            Qp[l * np + e] = f;
+            jt[l] = (double)f;
+        }
+        #pragma unroll
+        for (int l = 0; l < MAXPP; ++l)
+            #pragma unroll
+            for (int l2 = 0; l2 < MAXPP; ++l2)
+                if (l <= l2 && l2 < pp) gram[l * MAXPP + l2] += jt[l] * jt[l2];
+    }
+    block_sum_d<MAXPP * MAXPP>(gram);
+    if (tid == 0) {
+        double G[MAXPP * MAXPP];
+        for (int l = 0; l < MAXPP; ++l)
+            for (int l2 = l; l2 < MAXPP; ++l2) {
+                G[l * MAXPP + l2] = gram[l * MAXPP + l2];
+                G[l2 * MAXPP + l] = gram[l * MAXPP + l2];
+            }
+        sh_fail = cholesky_upper(G, pp, sh_R1) ? 0 : 1;
+    }
+    __syncthreads();
+    if (sh_fail) {
+        if (tid == 0) {
+            st->status = -4;
+            st->done_outer = 1;
+            st->done_inner = 1;
+        }
+        __syncthreads();
+        return;
+    }
+
+    // Pass C: second Gram of J~ R1^{-1} (Cholesky-QR, second pass).
+#pragma unroll
+    for (int k = 0; k < MAXPP * MAXPP; ++k) gram[k] = 0.0;
+    for (size_t e = tid; e < np; e += NT) {
+        const int row = (int)(e / ldg), col = (int)(e - (size_t)row * ldg);
+        if (col >= nr) continue;
+        double y[MAXPP], x[MAXPP];
+        #pragma unroll
+        for (int l = 0; l < MAXPP; ++l) if (l < pp) y[l] = (double)Qp[l * np + e];
+        solve_row_upper(sh_R1, pp, y, x);
+        #pragma unroll
+        for (int l = 0; l < MAXPP; ++l)
+            #pragma unroll
+            for (int l2 = 0; l2 < MAXPP; ++l2)
+                if (l <= l2 && l2 < pp) gram[l * MAXPP + l2] += x[l] * x[l2];
+    }
+    block_sum_d<MAXPP * MAXPP>(gram);
+    if (tid == 0) {
+        double G[MAXPP * MAXPP], R2[MAXPP * MAXPP];
+        for (int l = 0; l < MAXPP; ++l)
+            for (int l2 = l; l2 < MAXPP; ++l2) {
+                G[l * MAXPP + l2] = gram[l * MAXPP + l2];
+                G[l2 * MAXPP + l] = gram[l * MAXPP + l2];
+            }
+        const bool ok = cholesky_upper(G, pp, R2);
+        sh_fail = ok ? 0 : 1;
+        // R = R2 R1
+        for (int i = 0; i < MAXPP; ++i)
+            for (int j = 0; j < MAXPP; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < MAXPP; ++k) s += R2[i * MAXPP + k] * sh_R1[k * MAXPP + j];
+                sh_R[i * MAXPP + j] = s;
+                st->R[i * MAXPP + j] = s;
+            }
+    }
+    __syncthreads();
+    if (sh_fail) {
+        if (tid == 0) {
+            st->status = -4;
+            st->done_outer = 1;
+            st->done_inner = 1;
+        }
+        __syncthreads();
+        return;
+    }
+
+    // Pass D: Qb = J~ R^{-1} (stored), coefficients of Y, A + E - I and I.
+    float co[3 * MAXPP];
+#pragma unroll
+    for (int k = 0; k < 3 * MAXPP; ++k) co[k] = 0.f;
+    for (size_t e = tid; e < np; e += NT) {
+        const int row = (int)(e / ldg), col = (int)(e - (size_t)row * ldg);
+        if (col >= nr) continue;
+        double y[MAXPP], x[MAXPP];
+        #pragma unroll
+        for (int l = 0; l < MAXPP; ++l) if (l < pp) y[l] = (double)Qp[l * np + e];
+        solve_row_upper(sh_R, pp, y, x);
+        const float iv = I[e];
+        const float yv = Y[e];
+        const float sv = A[e] + E[e] - iv;
+        #pragma unroll
+        for (int l = 0; l < MAXPP; ++l) if (l < pp) {
+            const float qb = (float)x[l];
+            Qp[l * np + e] = qb;
+            co[l] = fmaf(qb, yv, co[l]);
+            co[MAXPP + l] = fmaf(qb, sv, co[MAXPP + l]);
+            co[2 * MAXPP + l] = fmaf(qb, iv, co[2 * MAXPP + l]);
+        }
+    }
+    block_sum_f<3 * MAXPP>(co);
+
+    // Pass E: Y <- J~perp Y (Eq. warm_start_Y), R <- J~perp(A + E - I),
+    // c^2 = ||J~perp I||^2.
+    float c2[1] = {0.f};
+    for (size_t e = tid; e < np; e += NT) {
+        const int row = (int)(e / ldg), col = (int)(e - (size_t)row * ldg);
+        if (col >= nr) {
+            R[e] = 0.f;
+            continue;
+        }
+        const float iv = I[e];
+        float yv = Y[e];
+        float sv = A[e] + E[e] - iv;
+        float ci = iv;
+        #pragma unroll
+        for (int l = 0; l < MAXPP; ++l) if (l < pp) {
+            const float qb = Qp[l * np + e];
+            yv = fmaf(-qb, co[l], yv);
+            sv = fmaf(-qb, co[MAXPP + l], sv);
+            ci = fmaf(-qb, co[2 * MAXPP + l], ci);
+        }
+        Y[e] = yv;
+        R[e] = sv;
+        c2[0] = fmaf(ci, ci, c2[0]);
+    }
+    block_sum_f<1>(c2);
+
+    // mu_0 = 1.25 / ||I||_2 from the Jacobi singular values of I.
+    double mu0 = prm.mu0;
+    if (!(mu0 > 0.0)) {
+        SvtLds L = carve_lds(lds, nc, d.ld, d.tb);
+        load_rows_lds(I, nc, ldg, d.ld, L.B);
+        JacobiStats js{0, 0, 0};
+        jacobi_dispatch(d.svt_cfg, L.B, nc, ldg >> 2, d.ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
+        __shared__ float sh_smax;
+        if (tid == 0) {
+            float mx = 0.f;
+            for (int j = 0; j < nc; ++j) mx = fmaxf(mx, L.s2[j]);
+            sh_smax = sqrtf(mx);
+            st->svt_calls += 1;
+            st->sweeps += js.sweeps;
+            st->pairs += js.pairs;
+            st->rotations += js.rotations;
+        }
+        __syncthreads();
+        mu0 = 1.25 / (double)sh_smax;
+    }
+    if (tid == 0) {
+        st->c = sqrt((double)c2[0]);
+        st->mu = mu0;
+        st->inner = 0;
+        st->done_inner = 0;
+        if (!(st->c > 0.0) || !isfinite(mu0)) {
+            st->status = -5;
+            st->done_outer = 1;
+            st->done_inner = 1;
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// A-update: M = A - R - Y/mu, A <- S_{1/mu}(M)
+// ---------------------------------------------------------------------------
+
+__device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& prm, float* lds) {
+    const int tid = threadIdx.x;
+    const int nc = d.nc, ldg = d.ldg, ld = d.ld;
+    const int nr4 = ldg >> 2;
+    const size_t np = (size_t)nc * ldg;
+    float* A = d.ws + PL_A * np;
+    const float* R = d.ws + PL_R * np;
+    const float* Y = d.ws + PL_Y * np;
+    float* M = d.ws + PL_M * np;
+    const double mu = st->mu;
+    const float inv_mu = (float)(1.0 / mu);
+    SvtLds L = carve_lds(lds, nc, ld, d.tb);
+
+    // M_k = A_k - J~perp(A_k + E_k - I) - Y_k/mu_k, with R = J~perp(A_k + E_k - I).
+    for (int idx = tid; idx < nc * nr4; idx += NT) {
+        const int row = idx / nr4, c = idx - row * nr4;
+        const size_t o = (size_t)row * ldg + 4 * c;
+        const float4 a = *reinterpret_cast<const float4*>(A + o);
+        const float4 r = *reinterpret_cast<const float4*>(R + o);
+        const float4 y = *reinterpret_cast<const float4*>(Y + o);
+        float4 mm;
+        mm.x = a.x - r.x - y.x * inv_mu;
+        mm.y = a.y - r.y - y.y * inv_mu;
+        mm.z = a.z - r.z - y.z * inv_mu;
+        mm.w = a.w - r.w - y.w * inv_mu;
+        *reinterpret_cast<float4*>(M + o) = mm;
+        *reinterpret_cast<float4*>(L.B + row * ld + 4 * c) = mm;
+    }
+    if (nc & 1) {
+        for (int c = tid; c < ld; c += NT) L.B[nc * ld + c] = 0.f;
+    }
+    __syncthreads();
+
+    JacobiStats js{0, 0, 0};
+    jacobi_dispatch(d.svt_cfg, L.B, nc, nr4, ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
+
+    const float eps = (float)(1.0 / mu);
+    int k;
+    double nuc;
+    shrink_weights(L.s2, nc, eps, L.w, L.act, &k, &nuc);
+    float dA[1];
+    dA[0] = reconstruct(L.B, ld, M, A, nc, nr4, ldg, L.w, L.act, k, d.tb, L.xblk, L.cwt, true);
+    block_sum_f<1>(dA);
+    if (tid == 0) {
+        st->dA2 = (double)dA[0];
+        st->nuc = nuc;
+        st->svt_rank = k;
+        st->svt_calls += 1;
+        st->sweeps += js.sweeps;
+        st->pairs += js.pairs;
+        st->rotations += js.rotations;
+        st->recon_rows += k;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// E-, Y- and mu-updates with the two J~perp products of Sec. 4.2
+// ---------------------------------------------------------------------------
+
+__device__ void dev_update(const PatchDesc& d, PatchState* st, const SolverParams& prm) {
+    const int tid = threadIdx.x;
+    const int pp = d.pp;
+    const size_t np = (size_t)d.nc * d.ldg;
+    const int n4 = (int)(np >> 2);
+    const float4* A = reinterpret_cast<const float4*>(d.ws + PL_A * np);
+    float4* E = reinterpret_cast<float4*>(d.ws + PL_E * np);
+    const float4* I = reinterpret_cast<const float4*>(d.ws + PL_I * np);
+    float4* Y = reinterpret_cast<float4*>(d.ws + PL_Y * np);
+    float4* R = reinterpret_cast<float4*>(d.ws + PL_R * np);
+    const float* Qp = d.ws + PL_Q * np;
+    const double mu = st->mu;
+    const float muf = (float)mu;
+    const float inv_mu = (float)(1.0 / mu);
+    const float thr = (float)(d.lam / mu);
+
+    // t1 = Qb^T (A_{k+1} + E_k - I)
+    float t1[MAXPP];
+#pragma unroll
+    for (int l = 0; l < MAXPP; ++l) t1[l] = 0.f;
+    for (int e = tid; e < n4; e += NT) {
+        const float4 a = A[e], ev = E[e], iv = I[e];
+        const float4 s = make_float4(a.x + ev.x - iv.x, a.y + ev.y - iv.y, a.z + ev.z - iv.z, a.w + ev.w - iv.w);
+        #pragma unroll
+        for (int l = 0; l < MAXPP; ++l) if (l < pp) {
+            const float4 q = reinterpret_cast<const float4*>(Qp + l * np)[e];
+            float acc = t1[l];
+            acc = fmaf(q.x, s.x, acc);
+            acc = fmaf(q.y, s.y, acc);
+            acc = fmaf(q.z, s.z, acc);
+            acc = fmaf(q.w, s.w, acc);
+            t1[l] = acc;
+        }
+    }
+    block_sum_f<MAXPP>(t1);
+
+    // N_k = E_k - J~perp(A_{k+1} + E_k - I) - Y_k/mu; E_{k+1} = T_{lam/mu}(N_k);
+    // t2 = Qb^T (A_{k+1} + E_{k+1} - I).
+    float t2[MAXPP + 1];
+#pragma unroll
+    for (int l = 0; l <= MAXPP; ++l) t2[l] = 0.f;
+    for (int e = tid; e < n4; e += NT) {
+        const float4 a = A[e], ev = E[e], iv = I[e], yv = Y[e];
+        float s[4] = {a.x + ev.x - iv.x, a.y + ev.y - iv.y, a.z + ev.z - iv.z, a.w + ev.w - iv.w};
+        float4 q[MAXPP];
+        #pragma unroll
+        for (int l = 0; l < MAXPP; ++l) if (l < pp) {
+            q[l] = reinterpret_cast<const float4*>(Qp + l * np)[e];
+            s[0] = fmaf(-q[l].x, t1[l], s[0]);
+            s[1] = fmaf(-q[l].y, t1[l], s[1]);
+            s[2] = fmaf(-q[l].z, t1[l], s[2]);
+            s[3] = fmaf(-q[l].w, t1[l], s[3]);
+        }
+        const float eo[4] = {ev.x, ev.y, ev.z, ev.w};
+        const float yy[4] = {yv.x, yv.y, yv.z, yv.w};
+        const float aa[4] = {a.x, a.y, a.z, a.w};
+        const float ii[4] = {iv.x, iv.y, iv.z, iv.w};
+        float en[4], s2[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float nv = eo[u] - s[u] - yy[u] * inv_mu;
+            const float mag = fabsf(nv) - thr;
+            en[u] = mag > 0.f ? copysignf(mag, nv) : 0.f;
+            const float de = en[u] - eo[u];
+            t2[MAXPP] = fmaf(de, de, t2[MAXPP]);
+            s2[u] = aa[u] + en[u] - ii[u];
+        }
+        E[e] = make_float4(en[0], en[1], en[2], en[3]);
+        #pragma unroll
+        for (int l = 0; l < MAXPP; ++l) if (l < pp) {
+            float acc = t2[l];
+            acc = fmaf(q[l].x, s2[0], acc);
+            acc = fmaf(q[l].y, s2[1], acc);
+            acc = fmaf(q[l].z, s2[2], acc);
+            acc = fmaf(q[l].w, s2[3], acc);
+            t2[l] = acc;
+        }
+    }
+    block_sum_f<MAXPP + 1>(t2);
+
+    // R_{k+1} = J~perp(A_{k+1} + E_{k+1} - I); Y_{k+1} = Y_k + mu R_{k+1}.
+    float r2[1] = {0.f};
+    for (int e = tid; e < n4; e += NT) {
+        const float4 a = A[e], ev = E[e], iv = I[e];
+        float4 yv = Y[e];
+        float s[4] = {a.x + ev.x - iv.x, a.y + ev.y - iv.y, a.z + ev.z - iv.z, a.w + ev.w - iv.w};
+        #pragma unroll
+        for (int l = 0; l < MAXPP; ++l) if (l < pp) {
+            const float4 q = reinterpret_cast<const float4*>(Qp + l * np)[e];
+            s[0] = fmaf(-q.x, t2[l], s[0]);
+            s[1] = fmaf(-q.y, t2[l], s[1]);
+            s[2] = fmaf(-q.z, t2[l], s[2]);
+            s[3] = fmaf(-q.w, t2[l], s[3]);
+        }
+        R[e] = make_float4(s[0], s[1], s[2], s[3]);
+        yv.x = fmaf(muf, s[0], yv.x);
+        yv.y = fmaf(muf, s[1], yv.y);
+        yv.z = fmaf(muf, s[2], yv.z);
+        yv.w = fmaf(muf, s[3], yv.w);
+        Y[e] = yv;
+        r2[0] = fmaf(s[0], s[0], r2[0]);
+        r2[0] = fmaf(s[1], s[1], r2[0]);
+        r2[0] = fmaf(s[2], s[2], r2[0]);
+        r2[0] = fmaf(s[3], s[3], r2[0]);
+    }
+    block_sum_f<1>(r2);
+
+    if (tid == 0) {
+        const double c = st->c;
+        const double dA = sqrt(st->dA2), dE = sqrt((double)t2[MAXPP]);
+        const double cond1 = sqrt((double)r2[0]) / c;
+        const double cond2 = mu * fmax(dA, dE) / c;
+        st->cond1 = cond1;
+        st->cond2 = cond2;
+        st->inner += 1;
+        st->inner_total += 1;
+        int stop = 0;
+        if (!isfinite(cond1) || !isfinite(cond2)) {
+            st->status = -5;
+            st->done_outer = 1;
+            stop = 1;
+        } else {
+            if (!prm.fixed_iters && cond1 < prm.eps1 && cond2 < prm.eps2) stop = 1;
+            if (!stop && cond2 < prm.eps2) st->mu = fmin(prm.mu_max, prm.rho0 * mu);
+            if (!stop && st->inner >= prm.max_inner) {
+                stop = 1;
+                if (!prm.fixed_iters) st->warn = 1;
+            }
+        }
+        st->done_inner = stop;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Steps 3 and 4: Delta tau and the transform update
+// ---------------------------------------------------------------------------
+
+__device__ void dev_dtau(const PatchDesc& d, PatchState* st, const SolverParams& prm) {
+    const int tid = threadIdx.x;
+    const int pp = d.pp, p = d.model;
+    const size_t np = (size_t)d.nc * d.ldg;
+    const float* A = d.ws + PL_A * np;
+    const float* E = d.ws + PL_E * np;
+    const float* I = d.ws + PL_I * np;
+    const float* Qp = d.ws + PL_Q * np;
+    double t[MAXPP];
+#pragma unroll
+    for (int l = 0; l < MAXPP; ++l) t[l] = 0.0;
+    for (size_t e = tid; e < np; e += NT) {
+        const float s = A[e] + E[e] - I[e];
+        #pragma unroll
+        for (int l = 0; l < MAXPP; ++l) if (l < pp) t[l] += (double)Qp[l * np + e] * (double)s;
+    }
+    block_sum_d<MAXPP>(t);
+    if (tid == 0) {
+        // y = R^{-1} t (back substitution), Delta tau = N_Q y.
+        double y[MAXPP];
+        for (int l = pp - 1; l >= 0; --l) {
+            double s = t[l];
+            for (int k = l + 1; k < pp; ++k) s -= st->R[l * MAXPP + k] * y[k];
+            y[l] = s / st->R[l * MAXPP + l];
+        }
+        double nrm2 = 0.0;
+        bool finite = true;
+        #pragma unroll
+        for (int k = 0; k < MAXP; ++k) if (k < p) {
+            double dk = 0.0;
+            #pragma unroll
+            for (int l = 0; l < MAXPP; ++l) if (l < pp) dk += st->NQ[k * MAXPP + l] * y[l];
+            st->tau[k] += dk;
+            nrm2 += dk * dk;
+            finite = finite && isfinite(st->tau[k]);
+        }
+        st->dtau_norm = sqrt(nrm2);
+        st->outer += 1;
+        int stop = 0;
+        if (!finite) {
+            st->status = -5;
+            stop = 1;
+        }
+        if (!prm.fixed_iters && st->dtau_norm < prm.eps_outer) stop = 1;
+        if (st->outer >= prm.max_outer) stop = 1;
+        st->done_outer = stop;
+    }
+    __syncthreads();
+}
+
+// Outputs in row-major m x n and the objective ||A||_* + lam ||E||_1.
+__device__ void dev_finalize(const PatchDesc& d, PatchState* st) {
+    const int tid = threadIdx.x;
+    const size_t np = (size_t)d.nc * d.ldg;
+    const float* A = d.ws + PL_A * np;
+    const float* E = d.ws + PL_E * np;
+    double l1[1] = {0.0};
+    for (size_t e = tid; e < np; e += NT) {
+        const int row = (int)(e / d.ldg), col = (int)(e - (size_t)row * d.ldg);
+        if (col >= d.nr) continue;
+        int i, j;
+        xlayout_to_ij(d, row, col, i, j);
+        const float ev = E[e];
+        l1[0] += fabs((double)ev);
+        if (d.A_out) d.A_out[(size_t)i * d.n + j] = A[e];
+        if (d.E_out) d.E_out[(size_t)i * d.n + j] = ev;
+    }
+    block_sum_d<1>(l1);
+    if (tid == 0) {
+        st->l1 = l1[0];
+        st->objective = st->nuc + d.lam * l1[0];
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+extern __shared__ float4 tilt_dyn_lds[];
+
+__device__ void solve_patch(const PatchDesc& d, PatchState* st, const SolverParams& prm, float* lds) {
+    __shared__ int sh_flag;
+    for (;;) {
+        dev_setup(d, st, prm, lds);
+        if (threadIdx.x == 0) sh_flag = st->status < 0;
+        __syncthreads();
+        if (sh_flag) break;
+        for (;;) {
+            dev_svt(d, st, prm, lds);
+            dev_update(d, st, prm);
+            if (threadIdx.x == 0) sh_flag = st->done_inner;
+            __syncthreads();
+            if (sh_flag) break;
+        }
+        if (threadIdx.x == 0) sh_flag = st->status < 0;
+        __syncthreads();
+        if (sh_flag) break;
+        dev_dtau(d, st, prm);
+        if (threadIdx.x == 0) sh_flag = st->done_outer;
+        __syncthreads();
+        if (sh_flag) break;
+    }
+    dev_finalize(d, st);
+}
+
+__global__ void __launch_bounds__(NT) k_fused(const PatchDesc* __restrict__ descs, PatchState* states,
+                                               SolverParams prm, int count, int* queue) {
+    __shared__ int sh_idx;
+    float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
+    for (;;) {
+        if (threadIdx.x == 0) sh_idx = atomicAdd(queue, 1);
+        __syncthreads();
+        const int idx = sh_idx;
+        __syncthreads();
+        if (idx >= count) break;
+        const PatchDesc d = descs[idx];
+        solve_patch(d, states + idx, prm, lds);
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_setup(const PatchDesc* descs, PatchState* states, SolverParams prm, int idx) {
+    float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
+    const PatchDesc d = descs[idx];
+    dev_setup(d, states + idx, prm, lds);
+}
+
+__global__ void __launch_bounds__(NT) k_svt(const PatchDesc* descs, PatchState* states, SolverParams prm, int idx) {
+    float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
+    const PatchDesc d = descs[idx];
+    dev_svt(d, states + idx, prm, lds);
+}
+
+__global__ void __launch_bounds__(NT) k_update(const PatchDesc* descs, PatchState* states, SolverParams prm, int idx) {
+    const PatchDesc d = descs[idx];
+    dev_update(d, states + idx, prm);
+}
+
+__global__ void __launch_bounds__(NT) k_dtau(const PatchDesc* descs, PatchState* states, SolverParams prm, int idx) {
+    const PatchDesc d = descs[idx];
+    dev_dtau(d, states + idx, prm);
+}
+
+__global__ void __launch_bounds__(NT) k_finalize(const PatchDesc* descs, PatchState* states, int idx) {
+    const PatchDesc d = descs[idx];
+    dev_finalize(d, states + idx);
+}
+
+// Component kernel: normalised warp and Jacobian (Alg. 1 Step 1); one
+// workgroup per patch, outputs in row-major m x n (I) and p planes of m x n
+// (J, parameter-major).
+__global__ void __launch_bounds__(NT) k_step1(const PatchDesc* descs, PatchState* states, float* I_out,
+                                              float* J_out) {
+    const PatchDesc d = descs[blockIdx.x];
+    const PatchState* st = states + blockIdx.x;
+    const int tid = threadIdx.x;
+    const int p = d.model;
+    const size_t mn = (size_t)d.m * d.n;
+    float* Io = I_out + (size_t)blockIdx.x * mn;
+    float* Jo = J_out + (size_t)blockIdx.x * mn * p;
+    double h[8];
+    tau_to_h(st, p, h);
+    double acc[1 + MAXP];
+#pragma unroll
+    for (int k = 0; k <= MAXP; ++k) acc[k] = 0.0;
+    for (size_t e = tid; e < mn; e += NT) {
+        const int i = (int)(e / d.n), j = (int)(e - (size_t)i * d.n);
+        float jr[MAXP];
+        const float val = warp_pixel(d, h, i, j, jr);
+        acc[0] += (double)val * val;
+        #pragma unroll
+        for (int k = 0; k < MAXP; ++k) if (k < p) acc[1 + k] += (double)val * (double)jr[k];
+    }
+    block_sum_d<1 + MAXP>(acc);
+    const double inv_n = 1.0 / sqrt(acc[0]);
+    const double inv_n3 = inv_n * inv_n * inv_n;
+    for (size_t e = tid; e < mn; e += NT) {
+        const int i = (int)(e / d.n), j = (int)(e - (size_t)i * d.n);
+        float jr[MAXP];
+        const double val = warp_pixel(d, h, i, j, jr);
+        Io[e] = (float)(val * inv_n);
+        #pragma unroll
+        for (int k = 0; k < MAXP; ++k) if (k < p) Jo[k * mn + e] = (float)((double)jr[k] * inv_n - val * acc[1 + k] * inv_n3);
+    }
+}
+
+// Component kernel: batched singular value shrinkage of independent
+// matrices (the A-update of Eq. A_1 on its own).
+__global__ void __launch_bounds__(NT) k_svt_jobs(const SvtJob* jobs, int cfg, int ld, int tb, float tol,
+                                                 int max_sweeps, long long* counters, float* scratch) {
+    const SvtJob jb = jobs[blockIdx.x];
+    float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
+    const int tid = threadIdx.x;
+    const int m = jb.m, n = jb.n;
+    const bool colmajor = m >= n;
+    const int nc = colmajor ? n : m, nr = colmajor ? m : n;
+    const int ldg = (nr + 3) & ~3;
+    const int nr4 = ldg >> 2;
+    const size_t np = (size_t)nc * ldg;
+    float* X = scratch + (size_t)blockIdx.x * 2 * np;
+    float* AX = X + np;
+    for (size_t e = tid; e < np; e += NT) {
+        const int row = (int)(e / ldg), col = (int)(e - (size_t)row * ldg);
+        float v = 0.f;
+        if (col < nr) v = colmajor ? jb.M[(size_t)col * n + row] : jb.M[(size_t)row * n + col];
+        X[e] = v;
+        AX[e] = 0.f;
+    }
+    __syncthreads();
+    SvtLds L = carve_lds(lds, nc, ld, tb);
+    load_rows_lds(X, nc, ldg, ld, L.B);
+    JacobiStats js{0, 0, 0};
+    jacobi_dispatch(cfg, L.B, nc, nr4, ld, tol, max_sweeps, js, L.s2);
+    int k;
+    double nuc;
+    shrink_weights(L.s2, nc, jb.eps, L.w, L.act, &k, &nuc);
+    if (jb.sigma) {
+        for (int j = tid; j < nc; j += NT) jb.sigma[j] = sqrtf(L.s2[j]);
+    }
+    reconstruct(L.B, ld, X, AX, nc, nr4, ldg, L.w, L.act, k, tb, L.xblk, L.cwt, false);
+    for (size_t e = tid; e < np; e += NT) {
+        const int row = (int)(e / ldg), col = (int)(e - (size_t)row * ldg);
+        if (col >= nr) continue;
+        if (colmajor)
+            jb.A[(size_t)col * n + row] = AX[e];
+        else
+            jb.A[(size_t)row * n + col] = AX[e];
+    }
+    if (tid == 0 && counters) {
+        long long* c = counters + 4 * blockIdx.x;
+        c[0] = js.sweeps;
+        c[1] = js.pairs;
+        c[2] = js.rotations;
+        c[3] = k;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+static hipError_t set_lds(const void* fn, size_t lds) {
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, int* queue,
+                        int grid, size_t lds, hipStream_t s) {
+    hipError_t e = set_lds((const void*)k_fused, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(NT), lds, s, d, st, prm, count, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx, size_t lds,
+                        hipStream_t s) {
+    hipError_t e = set_lds((const void*)k_setup, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(NT), lds, s, d, st, prm, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_svt(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx, size_t lds,
+                      hipStream_t s) {
+    hipError_t e = set_lds((const void*)k_svt, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_svt, dim3(1), dim3(NT), lds, s, d, st, prm, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx, hipStream_t s) {
+    hipLaunchKernelGGL(k_update, dim3(1), dim3(NT), 0, s, d, st, prm, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_dtau(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx, hipStream_t s) {
+    hipLaunchKernelGGL(k_dtau, dim3(1), dim3(NT), 0, s, d, st, prm, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const PatchDesc* d, PatchState* st, int idx, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NT), 0, s, d, st, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_step1(const PatchDesc* d, PatchState* st, int count, float* I_out, float* J_out,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_step1, dim3(count), dim3(NT), 0, s, d, st, I_out, J_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_svt_jobs(const SvtJob* jobs, int count, int cfg, int ld, int tb, float tol, int max_sweeps,
+                           long long* counters, float* scratch, size_t lds, hipStream_t s) {
+    hipError_t e = set_lds((const void*)k_svt_jobs, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_svt_jobs, dim3(count), dim3(NT), lds, s, jobs, cfg, ld, tb, tol, max_sweeps, counters,
+                       scratch);
+    return hipGetLastError();
+}
+
+}  // namespace tilt

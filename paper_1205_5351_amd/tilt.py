@@ -1,0 +1,328 @@
+"""ctypes binding of ``libtilt.so`` (the C interface in ``include/tilt.h``).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Device buffers are passed as raw pointers, typically from PyTorch tensors on
+``cuda:N`` (PyTorch is used for device memory and streams only).  If the
+library is missing, importing this module raises: there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("TILT_LIB", os.path.join(_PKG_DIR, "libtilt.so"))
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"HIP library not found at {LIB_PATH}; build it with "
+        "`python -m paper_1205_5351_amd.build` (or __graft_entry__.build())"
+    )
+
+_lib = C.CDLL(LIB_PATH)
+
+# ---------------------------------------------------------------------------
+# Status codes and models (mirror of the header)
+# ---------------------------------------------------------------------------
+TILT_OK = 0
+TILT_WARN_MAXITER = 1
+TILT_PENDING = 2
+TILT_ERR_ARG = -1
+TILT_ERR_NOMEM = -2
+TILT_ERR_DEVICE = -3
+TILT_ERR_SINGULAR = -4
+TILT_ERR_NONFINITE = -5
+TILT_ERR_TOO_LARGE = -6
+TILT_ERR_NOT_FOUND = -7
+
+AFFINE = 6
+PROJECTIVE = 8
+
+
+class TiltError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("lambda_", C.c_double),
+        ("eps1", C.c_double),
+        ("eps2", C.c_double),
+        ("eps_outer", C.c_double),
+        ("mu0", C.c_double),
+        ("rho0", C.c_double),
+        ("mu_max", C.c_double),
+        ("max_inner", C.c_int),
+        ("max_outer", C.c_int),
+        ("fixed_iters", C.c_int),
+        ("svt_mode", C.c_int),
+        ("jacobi_tol", C.c_float),
+        ("max_sweeps", C.c_int),
+    ]
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("image", C.c_void_p),
+        ("height", C.c_int),
+        ("width", C.c_int),
+        ("row_stride", C.c_longlong),
+        ("m", C.c_int),
+        ("n", C.c_int),
+        ("model", C.c_int),
+        ("reserved", C.c_int),
+        ("tau0", C.c_double * 9),
+    ]
+
+
+class Counters(C.Structure):
+    _fields_ = [
+        ("inner_iters", C.c_longlong),
+        ("svt_calls", C.c_longlong),
+        ("jacobi_sweeps", C.c_longlong),
+        ("jacobi_pairs", C.c_longlong),
+        ("jacobi_rotations", C.c_longlong),
+        ("recon_rows", C.c_longlong),
+    ]
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("tau", C.c_double * 9),
+        ("A", C.c_void_p),
+        ("E", C.c_void_p),
+        ("outer_iters", C.c_int),
+        ("inner_iters_total", C.c_int),
+        ("svt_rank", C.c_int),
+        ("status", C.c_int),
+        ("objective", C.c_double),
+        ("mu", C.c_double),
+        ("cond1", C.c_double),
+        ("cond2", C.c_double),
+        ("dtau_norm", C.c_double),
+        ("counters", Counters),
+    ]
+
+
+_lib.tilt_default_params.argtypes = [C.POINTER(Params)]
+_lib.tilt_default_params.restype = None
+_lib.tilt_status_string.argtypes = [C.c_int]
+_lib.tilt_status_string.restype = C.c_char_p
+_lib.tilt_version.argtypes = []
+_lib.tilt_version.restype = C.c_char_p
+_lib.tilt_tau_from_quad.argtypes = [C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]
+_lib.tilt_tau_from_quad.restype = C.c_int
+_lib.tilt_solve.argtypes = [C.POINTER(Problem), C.POINTER(Params), C.POINTER(Result)]
+_lib.tilt_solve.restype = C.c_int
+_lib.tilt_ctx_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_size_t]
+_lib.tilt_ctx_create.restype = C.c_int
+_lib.tilt_ctx_destroy.argtypes = [C.c_void_p]
+_lib.tilt_ctx_destroy.restype = C.c_int
+_lib.tilt_workspace_bytes.argtypes = [C.POINTER(Problem)]
+_lib.tilt_workspace_bytes.restype = C.c_size_t
+_lib.tilt_solve_batch.argtypes = [C.c_void_p, C.POINTER(Problem), C.c_int, C.POINTER(Params),
+                                  C.POINTER(Result), C.c_void_p]
+_lib.tilt_solve_batch.restype = C.c_int
+_lib.tilt_solve_batch_plain.argtypes = _lib.tilt_solve_batch.argtypes
+_lib.tilt_solve_batch_plain.restype = C.c_int
+_lib.tilt_svt_batch.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
+                                C.POINTER(C.c_float), C.POINTER(Params), C.POINTER(C.c_int),
+                                C.POINTER(Counters), C.c_void_p]
+_lib.tilt_svt_batch.restype = C.c_int
+_lib.tilt_warp_jacobian.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(C.c_double), C.c_int,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.tilt_warp_jacobian.restype = C.c_int
+
+EXPORTS = [
+    "tilt_default_params", "tilt_status_string", "tilt_version", "tilt_tau_from_quad", "tilt_solve",
+    "tilt_ctx_create", "tilt_ctx_destroy", "tilt_workspace_bytes", "tilt_solve_batch",
+    "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_warp_jacobian",
+]
+
+
+def library():
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return _lib.tilt_status_string(int(code)).decode()
+
+
+def version() -> str:
+    return _lib.tilt_version().decode()
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    _lib.tilt_default_params(C.byref(p))
+    for k, v in overrides.items():
+        key = "lambda_" if k in ("lam", "lambda") else k
+        if not hasattr(p, key):
+            raise KeyError(k)
+        setattr(p, key, v)
+    return p
+
+
+def tau_from_quad(quad: Sequence[float], m: int, n: int, model: int) -> np.ndarray:
+    q = (C.c_double * 8)(*[float(x) for x in quad])
+    out = (C.c_double * 9)()
+    rc = _lib.tilt_tau_from_quad(q, int(m), int(n), int(model), out)
+    if rc != TILT_OK:
+        raise TiltError(rc, "tilt_tau_from_quad")
+    return np.array(list(out)).reshape(3, 3)
+
+
+def make_problem(image_ptr: int, height: int, width: int, row_stride: int, m: int, n: int, model: int,
+                 tau0) -> Problem:
+    pr = Problem()
+    pr.image = C.c_void_p(int(image_ptr))
+    pr.height = int(height)
+    pr.width = int(width)
+    pr.row_stride = int(row_stride)
+    pr.m = int(m)
+    pr.n = int(n)
+    pr.model = int(model)
+    pr.reserved = 0
+    t = np.asarray(tau0, dtype=np.float64).reshape(9)
+    for k in range(9):
+        pr.tau0[k] = float(t[k])
+    return pr
+
+
+def workspace_bytes(m: int, n: int, model: int = PROJECTIVE) -> int:
+    pr = make_problem(1, 2, 2, 2, m, n, model, np.eye(3))
+    return int(_lib.tilt_workspace_bytes(C.byref(pr)))
+
+
+def result_dict(r: Result) -> dict:
+    c = r.counters
+    return dict(
+        tau=np.array(list(r.tau)).reshape(3, 3),
+        outer_iters=r.outer_iters,
+        inner_iters_total=r.inner_iters_total,
+        svt_rank=r.svt_rank,
+        status=r.status,
+        objective=r.objective,
+        mu=r.mu,
+        cond1=r.cond1,
+        cond2=r.cond2,
+        dtau_norm=r.dtau_norm,
+        counters=dict(inner_iters=c.inner_iters, svt_calls=c.svt_calls, jacobi_sweeps=c.jacobi_sweeps,
+                      jacobi_pairs=c.jacobi_pairs, jacobi_rotations=c.jacobi_rotations,
+                      recon_rows=c.recon_rows),
+    )
+
+
+def solve(image: np.ndarray, tau0, m: int, n: int, model: int, params: Optional[Params] = None,
+          want_AE: bool = True) -> dict:
+    """Plain single-patch path (``tilt_solve``): host arrays in and out."""
+    img = np.ascontiguousarray(image, dtype=np.float32)
+    if img.ndim != 2:
+        raise ValueError("image must be 2-D")
+    prm = params if params is not None else default_params()
+    pr = make_problem(img.ctypes.data, img.shape[0], img.shape[1], img.shape[1], m, n, model, tau0)
+    res = Result()
+    A = E = None
+    if want_AE:
+        A = np.zeros((m, n), np.float32)
+        E = np.zeros((m, n), np.float32)
+        res.A = C.c_void_p(A.ctypes.data)
+        res.E = C.c_void_p(E.ctypes.data)
+    rc = _lib.tilt_solve(C.byref(pr), C.byref(prm), C.byref(res))
+    if rc < 0 and rc not in (TILT_ERR_SINGULAR, TILT_ERR_NONFINITE):
+        raise TiltError(rc, "tilt_solve")
+    out = result_dict(res)
+    out["A"] = A
+    out["E"] = E
+    out["rc"] = rc
+    return out
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        return 0
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Context:
+    """Owns the device workspace of batched solves on one GPU."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        h = C.c_void_p()
+        rc = _lib.tilt_ctx_create(C.byref(h), int(device), C.c_size_t(int(budget_bytes)))
+        if rc != TILT_OK:
+            raise TiltError(rc, "tilt_ctx_create")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if self._h:
+            _lib.tilt_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _batch(self, fn, problems: List[Problem], params: Optional[Params], outs_A, outs_E, stream):
+        n = len(problems)
+        prm = params if params is not None else default_params()
+        parr = (Problem * n)(*problems)
+        rarr = (Result * n)()
+        for i in range(n):
+            rarr[i].A = C.c_void_p(int(outs_A[i])) if outs_A is not None and outs_A[i] else None
+            rarr[i].E = C.c_void_p(int(outs_E[i])) if outs_E is not None and outs_E[i] else None
+        rc = fn(self._h, parr, n, C.byref(prm), rarr, C.c_void_p(_stream_ptr(stream)))
+        if rc < 0 and rc not in (TILT_ERR_SINGULAR, TILT_ERR_NONFINITE, TILT_ERR_TOO_LARGE, TILT_ERR_ARG):
+            raise TiltError(rc, fn.__name__)
+        return rc, [result_dict(rarr[i]) for i in range(n)]
+
+    def solve_batch(self, problems, params=None, outs_A=None, outs_E=None, stream=None):
+        """Fused persistent kernel over all problems (device images/outputs)."""
+        return self._batch(_lib.tilt_solve_batch, problems, params, outs_A, outs_E, stream)
+
+    def solve_batch_plain(self, problems, params=None, outs_A=None, outs_E=None, stream=None):
+        """Step-by-step kernels, one patch after another (device images/outputs)."""
+        return self._batch(_lib.tilt_solve_batch_plain, problems, params, outs_A, outs_E, stream)
+
+    def svt_batch(self, M_ptr: int, A_ptr: int, sigma_ptr: int, count: int, m: int, n: int, eps,
+                  params: Optional[Params] = None, stream=None):
+        prm = params if params is not None else default_params()
+        e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.float32), (count,)))
+        earr = (C.c_float * count)(*e.tolist())
+        ranks = (C.c_int * count)()
+        cnt = Counters()
+        rc = _lib.tilt_svt_batch(self._h, C.c_void_p(int(M_ptr)), C.c_void_p(int(A_ptr)),
+                                 C.c_void_p(int(sigma_ptr)) if sigma_ptr else None, int(count), int(m), int(n),
+                                 earr, C.byref(prm), ranks, C.byref(cnt), C.c_void_p(_stream_ptr(stream)))
+        if rc != TILT_OK:
+            raise TiltError(rc, "tilt_svt_batch")
+        return list(ranks), dict(svt_calls=cnt.svt_calls, jacobi_sweeps=cnt.jacobi_sweeps,
+                                 jacobi_pairs=cnt.jacobi_pairs, jacobi_rotations=cnt.jacobi_rotations,
+                                 recon_rows=cnt.recon_rows)
+
+    def warp_jacobian(self, problems: List[Problem], taus, I_ptr: int, J_ptr: int, stream=None):
+        n = len(problems)
+        parr = (Problem * n)(*problems)
+        t = np.ascontiguousarray(np.asarray(taus, np.float64).reshape(n, 9))
+        tarr = (C.c_double * (9 * n))(*t.reshape(-1).tolist())
+        rc = _lib.tilt_warp_jacobian(self._h, parr, tarr, n, C.c_void_p(int(I_ptr)), C.c_void_p(int(J_ptr)),
+                                     C.c_void_p(_stream_ptr(stream)))
+        if rc != TILT_OK:
+            raise TiltError(rc, "tilt_warp_jacobian")

@@ -1,0 +1,246 @@
+"""HIP path vs the FP64 oracle, element by element, through the C interface.
+
+Tolerances (FP32 arithmetic on the device, FP64 in the oracle):
+  * SVT: ||A_gpu - A_ref||_F <= 1e-5 ||A_ref||_F and singular values within
+    1e-5 sigma_max.  The Jacobi stops when every pair satisfies
+    |a.b| <= 1e-6 ||a|| ||b||, so the orthogonalised rows (and the
+    shrinkage built from them) carry a relative error of order 1e-6, plus
+    FP32 rounding of length-n sums (~sqrt(n) 6e-8); 1e-5 leaves a 10x margin.
+  * warp: |I_gpu - I_ref| <= 2e-6 max|I| (FP32 bilinear blend of FP32 data);
+    Jacobian within 1e-5 relative in Frobenius norm.
+  * whole solve: relative tau error <= 1e-4 and relative objective error
+    <= 1e-4 (the stated FP32 targets), identical numerical rank
+    (#sigma > 1e-3 sigma_1, FP64 evaluator on both outputs).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import tilt_synth as ts
+from gpu_util import device_problems, oracle_params, solve_on_device, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+# ---------------------------------------------------------------------------
+# a5: singular value shrinkage on its own
+# ---------------------------------------------------------------------------
+
+SVT_SHAPES = [(8, 8), (17, 33), (33, 17), (50, 50), (64, 64), (100, 100), (101, 99), (90, 40), (40, 130),
+              (128, 128), (3, 70), (160, 96)]
+
+
+@pytest.mark.parametrize("m,n", SVT_SHAPES)
+def test_svt_matches_oracle(tilt, ctx, device, m, n):
+    import torch
+
+    rng = np.random.default_rng(1000 + 7 * m + n)
+    count = 4
+    Ms = []
+    for i in range(count):
+        r = min(m, n)
+        # low rank + noise, scaled like the TILT iterates (||M||_F ~ 1)
+        L = rng.standard_normal((m, 3)) @ rng.standard_normal((3, n))
+        Mi = L / np.linalg.norm(L) + 0.05 * rng.standard_normal((m, n)) / math.sqrt(m * n)
+        if i == 3:
+            Mi = rng.standard_normal((m, n)) / math.sqrt(m * n)
+        Ms.append(Mi.astype(np.float32))
+    M = np.stack(Ms)
+    eps = np.array([1e-3, 1e-2, 0.05, 0.02], np.float32)
+    dM = to_device(M, device)
+    dA = torch.zeros_like(dM)
+    k = min(m, n)
+    dS = torch.zeros((count, k), dtype=torch.float32, device=device)
+    ranks, cnt = ctx.svt_batch(dM.data_ptr(), dA.data_ptr(), dS.data_ptr(), count, m, n, eps)
+    torch.cuda.synchronize()
+    A = dA.cpu().numpy()
+    S = dS.cpu().numpy()
+    for i in range(count):
+        Aref, sref = O.svt(M[i].astype(np.float64), float(eps[i]))
+        err = np.linalg.norm(A[i] - Aref) / max(np.linalg.norm(Aref), 1e-30)
+        if np.linalg.norm(Aref) > 0:
+            assert err <= 1e-5, (m, n, i, err)
+        else:
+            assert np.linalg.norm(A[i]) <= 1e-6
+        sg = np.sort(S[i])[::-1]
+        assert np.max(np.abs(sg - sref)) <= 1e-5 * sref[0], (m, n, i)
+        near = np.any(np.abs(sref - eps[i]) <= 1e-5 * sref[0])
+        if not near:
+            assert ranks[i] == int(np.sum(sref > eps[i]))
+    assert cnt["svt_calls"] == count
+    assert cnt["jacobi_sweeps"] >= count
+
+
+def test_svt_zero_and_eps_extremes(tilt, ctx, device):
+    import torch
+
+    m, n = 40, 30
+    M = np.zeros((3, m, n), np.float32)
+    rng = np.random.default_rng(5)
+    M[1] = rng.standard_normal((m, n)).astype(np.float32)
+    M[2] = M[1]
+    eps = np.array([0.1, 0.0, 1e6], np.float32)
+    dM = to_device(M, device)
+    dA = torch.zeros_like(dM)
+    ranks, _ = ctx.svt_batch(dM.data_ptr(), dA.data_ptr(), 0, 3, m, n, eps)
+    A = dA.cpu().numpy()
+    assert np.all(A[0] == 0) and ranks[0] == 0             # S(0) = 0
+    assert np.linalg.norm(A[1] - M[1]) <= 1e-5 * np.linalg.norm(M[1])  # eps = 0: identity
+    assert ranks[1] == min(m, n)
+    assert np.all(A[2] == 0) and ranks[2] == 0             # eps above sigma_max
+
+
+# ---------------------------------------------------------------------------
+# a1/a2: warp and Jacobian of the normalised warp
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("cfg,idx", [(0, 0), (1, 0), (2, 3), (2, 8)])
+def test_warp_jacobian_matches_oracle(tilt, ctx, device, cfg, idx):
+    import torch
+
+    p = ts.make_batch(cfg, [idx])[0]
+    rng = np.random.default_rng(idx)
+    Hn0, c, s = O.normalise_transform(p.tau0, p.m, p.n)
+    taus = []
+    for k in range(2):
+        tau = O.tau_from_matrix(Hn0, p.model)
+        if k == 1:
+            tau = tau + rng.uniform(-0.05, 0.05, size=tau.size) * np.array(
+                [1, 1, 0, 1, 1, 0] + ([0.2, 0.2] if p.model == 8 else []))
+        taus.append(O.denormalise_transform(O.matrix_from_tau(tau, p.model), c, s))
+    probs, keep = device_problems(tilt, [p, p], device)
+    mn = p.m * p.n
+    dI = torch.zeros((2, p.m, p.n), dtype=torch.float32, device=device)
+    dJ = torch.zeros((2, p.model, p.m, p.n), dtype=torch.float32, device=device)
+    ctx.warp_jacobian(probs, np.stack(taus), dI.data_ptr(), dJ.data_ptr())
+    I = dI.cpu().numpy()
+    J = dJ.cpu().numpy()
+    for k in range(2):
+        # the evaluated transform in the window's scaled coordinates
+        Hk = np.array([[1 / s, 0, -c[0] / s], [0, 1 / s, -c[1] / s], [0, 0, 1.0]]) @ taus[k] @ np.diag([s, s, 1.0])
+        Hk = Hk / Hk[2, 2]
+        Iref, Jref, _ = O.step1(p.image.astype(np.float64), Hk, c, s, p.m, p.n, p.model)
+        assert np.max(np.abs(I[k] - Iref)) <= 2e-6 * np.max(np.abs(Iref))
+        Jg = J[k].reshape(p.model, mn).T
+        err = np.linalg.norm(Jg - Jref) / np.linalg.norm(Jref)
+        assert err <= 1e-5, err
+    del keep
+
+
+# ---------------------------------------------------------------------------
+# a2-a10: fixed iteration counts (arithmetic parity, no stopping decisions)
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("cfg,idx,outer,inner", [(0, 0, 1, 25), (0, 0, 2, 15), (2, 5, 1, 20)])
+def test_fixed_iterations_match_oracle(tilt, ctx, device, cfg, idx, outer, inner):
+    p = ts.make_batch(cfg, [idx])[0]
+    tp = tilt.default_params(fixed_iters=1, max_outer=outer, max_inner=inner, lam=p.lam)
+    rc, res = solve_on_device(tilt, ctx, [p], device, tp)
+    r = res[0]
+    assert r["status"] == 0, r
+    ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
+    assert r["outer_iters"] == outer and r["inner_iters_total"] == outer * inner
+    errA = np.linalg.norm(r["A"] - ref.A) / np.linalg.norm(ref.A)
+    errE = np.linalg.norm(r["E"] - ref.E) / max(np.linalg.norm(ref.E), 1e-12)
+    terr = O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n)
+    assert errA <= 1e-4, errA
+    assert errE <= 1e-3, errE
+    assert terr <= 1e-5, terr
+    assert abs(r["objective"] - ref.objective) <= 1e-4 * ref.objective
+
+
+# ---------------------------------------------------------------------------
+# Whole solve vs oracle (stopping tests active)
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("cfg,idx", [(0, 0), (1, 0), (2, 5)])
+def test_full_solve_matches_oracle(tilt, ctx, device, cfg, idx):
+    p = ts.make_batch(cfg, [idx])[0]
+    tp = tilt.default_params(lam=p.lam)
+    rc, res = solve_on_device(tilt, ctx, [p], device, tp)
+    r = res[0]
+    assert r["status"] >= 0, r
+    ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
+    terr = O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n)
+    assert terr <= 1e-4, (terr, r["outer_iters"], ref.outer_iters)
+    assert abs(r["objective"] - ref.objective) <= 1e-4 * ref.objective
+    assert O.numerical_rank(r["A"]) == O.numerical_rank(ref.A)
+
+
+# ---------------------------------------------------------------------------
+# Plain path == batched path, alone == in a mix (bitwise)
+# ---------------------------------------------------------------------------
+
+
+def _same(a, b):
+    return (np.array_equal(a["tau"], b["tau"]) and np.array_equal(a["A"], b["A"]) and
+            np.array_equal(a["E"], b["E"]) and a["inner_iters_total"] == b["inner_iters_total"])
+
+
+def test_plain_equals_batched_bitwise(tilt, ctx, device):
+    ps = ts.make_batch(1, [0, 1])
+    tp = tilt.default_params(lam=ps[0].lam)
+    _, fused = solve_on_device(tilt, ctx, ps, device, tp)
+    _, plain = solve_on_device(tilt, ctx, ps, device, tp, plain=True)
+    for a, b in zip(fused, plain):
+        assert _same(a, b)
+
+
+def test_alone_equals_in_mix(tilt, ctx, device):
+    mix = ts.make_batch(2, [0, 1, 2, 3, 4, 5, 6, 7])
+    tp = tilt.default_params(max_outer=3)
+    _, together = solve_on_device(tilt, ctx, mix, device, tp)
+    for k in (2, 5):
+        _, alone = solve_on_device(tilt, ctx, [mix[k]], device, tp)
+        assert _same(alone[0], together[k])
+
+
+def test_host_entry_equals_batched(tilt, ctx, device):
+    p = ts.make_batch(0, [0])[0]
+    tp = tilt.default_params(lam=p.lam, max_outer=5)
+    h = tilt.solve(p.image, p.tau0, p.m, p.n, p.model, tp)
+    _, res = solve_on_device(tilt, ctx, [p], device, tp)
+    assert _same(h, res[0])
+
+
+# ---------------------------------------------------------------------------
+# Degenerate inputs and error statuses
+# ---------------------------------------------------------------------------
+
+
+def test_error_statuses(tilt, ctx, device):
+    base = ts.make_batch(0, [0])[0]
+    flat = ts.Patch(image=np.full((64, 64), 0.5, np.float32), m=20, n=20, model=6, tau0=np.array(
+        [[1, 0, 31.5], [0, 1, 31.5], [0, 0, 1.0]]), lam=0.2, G_px=np.eye(3), rank=1, corruption=0.0)
+    nan = ts.Patch(image=base.image.copy(), m=base.m, n=base.n, model=6, tau0=base.tau0, lam=base.lam,
+                   G_px=base.G_px, rank=3, corruption=0.1)
+    nan.image[90:110, 90:110] = np.nan
+    tp = tilt.default_params(max_outer=2)
+    rc, res = solve_on_device(tilt, ctx, [flat, nan], device, tp)
+    assert res[0]["status"] == tilt.tilt.TILT_ERR_SINGULAR
+    assert res[1]["status"] == tilt.tilt.TILT_ERR_NONFINITE
+    big = ts.Patch(image=np.zeros((700, 700), np.float32), m=600, n=600, model=6,
+                   tau0=np.array([[1, 0, 349.5], [0, 1, 349.5], [0, 0, 1.0]]), lam=0.05, G_px=np.eye(3),
+                   rank=1, corruption=0.0)
+    rc, res = solve_on_device(tilt, ctx, [big], device, tp)
+    assert res[0]["status"] == tilt.tilt.TILT_ERR_TOO_LARGE
+
+
+@pytest.mark.parametrize("m,n,model", [(9, 9, 6), (12, 60, 8), (61, 13, 8), (7, 100, 6)])
+def test_ragged_shapes_fixed_iters(tilt, ctx, device, m, n, model):
+    rng = ts.patch_rng(99, m * 1000 + n)
+    p = ts.make_patch(rng, m=m, n=n, height=2 * max(m, n) + 8, width=2 * max(m, n) + 8, rank=2, model=model,
+                      corruption=0.05, theta_deg=5, skew=0.05)
+    tp = tilt.default_params(fixed_iters=1, max_outer=2, max_inner=10, lam=p.lam)
+    _, res = solve_on_device(tilt, ctx, [p], device, tp)
+    r = res[0]
+    ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
+    assert r["status"] == 0
+    assert np.linalg.norm(r["A"] - ref.A) <= 1e-4 * np.linalg.norm(ref.A)
+    assert O.tau_rel_err(r["tau"], ref.tau_px, m, n) <= 1e-5
