@@ -122,6 +122,10 @@ const char* tilt_status_string(int status);
 /* Library version string. */
 const char* tilt_version(void);
 
+/* Text of the last HIP runtime error seen by this thread inside the
+ * library ("" if none); valid until the next failing call. */
+const char* tilt_last_error(void);
+
 /* Homography that maps the centred m x n grid onto a quadrilateral given
  * by its corners TL, TR, BR, BL as (x, y) image pixels (8 doubles).  For
  * TILT_AFFINE the quad must be a parallelogram (the TL, TR, BL corners are

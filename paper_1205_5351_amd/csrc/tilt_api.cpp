@@ -203,6 +203,14 @@ SolverParams to_solver(const tilt_params* p) {
     return s;
 }
 
+thread_local char g_last_error[512] = "";
+
+int record_hip_error(hipError_t e, const char* what, int line) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s (%s) at tilt_api.cpp:%d: %s", hipGetErrorName(e),
+                  hipGetErrorString(e), line, what);
+    return TILT_ERR_DEVICE;
+}
+
 int worse(int a, int b) {
     // errors (negative) dominate warnings (positive) dominate OK
     if (a < 0 || b < 0) return std::min(a, b);
@@ -307,10 +315,10 @@ void fill_result(const PatchDesc& d, const PatchState& s, const Norm& nm, int pr
     r->counters.recon_rows = s.recon_rows;
 }
 
-#define HIP_TRY(x)                                  \
-    do {                                            \
-        hipError_t _e = (x);                        \
-        if (_e != hipSuccess) return TILT_ERR_DEVICE; \
+#define HIP_TRY(x)                                                  \
+    do {                                                            \
+        hipError_t _e = (x);                                        \
+        if (_e != hipSuccess) return record_hip_error(_e, #x, __LINE__); \
     } while (0)
 
 int upload(tilt_ctx* ctx, Prepared& P, hipStream_t stream) {
@@ -334,9 +342,8 @@ int run_plain_patch(tilt_ctx* ctx, const Prepared& P, const SolverParams& sp, in
     const size_t lds = P.max_lds;
     PatchState hs;
     auto fetch = [&]() -> int {
-        if (hipMemcpyAsync(&hs, ds + idx, sizeof(PatchState), hipMemcpyDeviceToHost, stream) != hipSuccess)
-            return TILT_ERR_DEVICE;
-        if (hipStreamSynchronize(stream) != hipSuccess) return TILT_ERR_DEVICE;
+        HIP_TRY(hipMemcpyAsync(&hs, ds + idx, sizeof(PatchState), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
         return TILT_OK;
     };
     for (;;) {
@@ -364,7 +371,7 @@ int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const 
     int st = validate_params(prm);
     if (st != TILT_OK) return st;
     if (count == 0) return TILT_OK;
-    if (hipSetDevice(ctx->device) != hipSuccess) return TILT_ERR_DEVICE;
+    HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     Prepared P;
     int worst = prepare(probs, count, prm, results, &P, true);
@@ -460,6 +467,8 @@ const char* tilt_status_string(int s) {
 
 const char* tilt_version(void) { return "tilt-mi355x 0.1 (gfx950)"; }
 
+const char* tilt_last_error(void) { return g_last_error; }
+
 int tilt_tau_from_quad(const double quad[8], int m, int n, int model, double tau_out[9]) {
     if (!quad || !tau_out || m < 2 || n < 2) return TILT_ERR_ARG;
     for (int k = 0; k < 8; ++k)
@@ -514,11 +523,12 @@ int tilt_ctx_create(tilt_ctx** ctx, int device, size_t hbm_budget_bytes) {
     if (!ctx) return TILT_ERR_ARG;
     *ctx = nullptr;
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return TILT_ERR_DEVICE;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (ndev <= 0) return TILT_ERR_DEVICE;
     if (device < 0 || device >= ndev) return TILT_ERR_ARG;
-    if (hipSetDevice(device) != hipSuccess) return TILT_ERR_DEVICE;
+    HIP_TRY(hipSetDevice(device));
     size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return TILT_ERR_DEVICE;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
     tilt_ctx* c = new (std::nothrow) tilt_ctx();
     if (!c) return TILT_ERR_NOMEM;
     c->device = device;
@@ -570,7 +580,7 @@ int tilt_solve(const tilt_problem* prob, const tilt_params* prm, tilt_result* re
         return st;
     }
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return TILT_ERR_DEVICE;
+    HIP_TRY(hipGetDevice(&dev));
     tilt_ctx* ctx = nullptr;
     st = tilt_ctx_create(&ctx, dev, 0);
     if (st != TILT_OK) return st;
@@ -635,7 +645,7 @@ int tilt_svt_batch(tilt_ctx* ctx, const float* M, float* A, float* sigma, int co
     ShapeCfg sc{};
     st = shape_config(m, n, &sc);
     if (st != TILT_OK) return st;
-    if (hipSetDevice(ctx->device) != hipSuccess) return TILT_ERR_DEVICE;
+    HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     const size_t mn = (size_t)m * n;
     const int k = std::min(m, n);
@@ -728,7 +738,7 @@ int tilt_warp_jacobian(tilt_ctx* ctx, const tilt_problem* probs, const double* t
         ps.tau[6] = model == TILT_PROJECTIVE ? Hn[6] : 0.0;
         ps.tau[7] = model == TILT_PROJECTIVE ? Hn[7] : 0.0;
     }
-    if (hipSetDevice(ctx->device) != hipSuccess) return TILT_ERR_DEVICE;
+    HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     if (ctx->descs.reserve(sizeof(PatchDesc) * count) != hipSuccess ||
         ctx->states.reserve(sizeof(PatchState) * count) != hipSuccess)

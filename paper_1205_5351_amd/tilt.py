@@ -23,6 +23,14 @@ if not os.path.exists(LIB_PATH):
         "`python -m paper_1205_5351_amd.build` (or __graft_entry__.build())"
     )
 
+try:
+    # PyTorch ships its own HIP runtime (soname libamdhip64.so.7).  Loading
+    # it first makes libtilt.so bind to that same runtime, so device memory
+    # and streams from torch are valid in the library.
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover - torch is optional for host-only use
+    torch = None
+
 _lib = C.CDLL(LIB_PATH)
 
 # ---------------------------------------------------------------------------
@@ -46,7 +54,8 @@ PROJECTIVE = 8
 class TiltError(RuntimeError):
     def __init__(self, code: int, what: str = ""):
         self.code = code
-        super().__init__(f"{what}: {status_string(code)} ({code})")
+        detail = last_error() if code == TILT_ERR_DEVICE else ""
+        super().__init__(f"{what}: {status_string(code)} ({code}){' ' + detail if detail else ''}")
 
 
 class Params(C.Structure):
@@ -116,6 +125,8 @@ _lib.tilt_status_string.argtypes = [C.c_int]
 _lib.tilt_status_string.restype = C.c_char_p
 _lib.tilt_version.argtypes = []
 _lib.tilt_version.restype = C.c_char_p
+_lib.tilt_last_error.argtypes = []
+_lib.tilt_last_error.restype = C.c_char_p
 _lib.tilt_tau_from_quad.argtypes = [C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]
 _lib.tilt_tau_from_quad.restype = C.c_int
 _lib.tilt_solve.argtypes = [C.POINTER(Problem), C.POINTER(Params), C.POINTER(Result)]
@@ -142,7 +153,7 @@ _lib.tilt_warp_jacobian.restype = C.c_int
 EXPORTS = [
     "tilt_default_params", "tilt_status_string", "tilt_version", "tilt_tau_from_quad", "tilt_solve",
     "tilt_ctx_create", "tilt_ctx_destroy", "tilt_workspace_bytes", "tilt_solve_batch",
-    "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_warp_jacobian",
+    "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_warp_jacobian", "tilt_last_error",
 ]
 
 
@@ -156,6 +167,10 @@ def status_string(code: int) -> str:
 
 def version() -> str:
     return _lib.tilt_version().decode()
+
+
+def last_error() -> str:
+    return _lib.tilt_last_error().decode()
 
 
 def default_params(**overrides) -> Params:
