@@ -1,6 +1,7 @@
 """Build the HIP library ``libtilt.so`` in-tree for gfx950.
 
-Usage: ``python -m paper_1205_5351_amd.build`` (or ``build()`` from Python).
+Usage: ``python paper_1205_5351_amd/build.py`` (run as a script so the
+package, which loads the library, is not imported first).
 The library is plain hipcc output: no PyTorch headers, no JIT cache.
 """
 

@@ -20,7 +20,7 @@ LIB_PATH = os.environ.get("TILT_LIB", os.path.join(_PKG_DIR, "libtilt.so"))
 if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"HIP library not found at {LIB_PATH}; build it with "
-        "`python -m paper_1205_5351_amd.build` (or __graft_entry__.build())"
+        "`python paper_1205_5351_amd/build.py` (or __graft_entry__.build())"
     )
 
 try:
