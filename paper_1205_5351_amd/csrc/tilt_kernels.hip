@@ -194,10 +194,15 @@ __device__ void jacobi_rows(float* B, int nc, int nr4, int ld, float tol, int ma
                     be = group_sum<LPP>(be);
                     ga = group_sum<LPP>(ga);
                     if (fabsf(ga) > tol * (sqrtf(al) * sqrtf(be))) {
-                        const float zeta = (be - al) / (2.0f * ga);
-                        const float t = copysignf(1.0f, zeta) / (fabsf(zeta) + sqrtf(1.0f + zeta * zeta));
-                        const float cs = 1.0f / sqrtf(1.0f + t * t);
-                        const float sn = cs * t;
+                        // Rotation angle in FP64, then c and s rounded once to
+                        // FP32: c^2 + s^2 - 1 is then an unbiased rounding
+                        // error, so row norms do not drift over the ~n^2 S/2
+                        // rotations of a decomposition.
+                        const double zeta = ((double)be - (double)al) / (2.0 * (double)ga);
+                        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                        const double cd = 1.0 / sqrt(1.0 + t * t);
+                        const float cs = (float)cd;
+                        const float sn = (float)(cd * t);
 #pragma unroll
                         for (int c = 0; c < MAXCH; ++c) {
                             const int ch = q + c * LPP;
