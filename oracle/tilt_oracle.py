@@ -37,8 +37,9 @@ design notes of the repository):
 * Q: the image of the rectified centre (2 rows) and the area of the image of
   the rectified rectangle (1 row) are held fixed to first order;
 * bilinear interpolation with pixel centres at integers; the gradient is the
-  exact derivative of the interpolant; outside the image the sample is
-  clamped to the border and its gradient along the clamped axis is zero;
+  exact derivative of the interpolant, taken from the cell right of / below
+  a pixel line for samples within 1e-9 px of it; outside the image the sample
+  is clamped to the border and its gradient along the clamped axis is zero;
 * tau is a homography in coordinates scaled by s = max(m, n)/2 about the
   image of the window centre; affine uses 6 entries, projective 8 (h33 = 1);
 * mu_0 = 1.25 / ||D o tau||_2 at the start of every inner loop unless given;
@@ -59,6 +60,7 @@ import numpy as np
 
 AFFINE = 6
 PROJECTIVE = 8
+SNAP = 1e-9  # pixels: cell-edge convention of the bilinear gradient
 
 
 # ---------------------------------------------------------------------------
@@ -158,8 +160,11 @@ def bilinear_with_gradient(img: np.ndarray, x: np.ndarray, y: np.ndarray):
         raise ValueError("image must be at least 2x2")
     xc = np.clip(x, 0.0, Ww - 1.0)
     yc = np.clip(y, 0.0, Hh - 1.0)
-    x0 = np.minimum(np.floor(xc), Ww - 2).astype(np.int64)
-    y0 = np.minimum(np.floor(yc), Hh - 2).astype(np.int64)
+    # a sample within SNAP pixels below a pixel line belongs to the next
+    # cell, so coordinates that sit on the pixel grid up to rounding always
+    # take the same one-sided gradient
+    x0 = np.minimum(np.floor(xc + SNAP), Ww - 2).astype(np.int64)
+    y0 = np.minimum(np.floor(yc + SNAP), Hh - 2).astype(np.int64)
     fx = xc - x0
     fy = yc - y0
     v00 = D[y0, x0]

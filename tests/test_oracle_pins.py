@@ -403,3 +403,15 @@ def test_identity_texture_stays_rectified():
     res = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, O.Params(max_outer=20), lam=p.lam)
     Mx = _gt_residual(p, res)
     assert abs(Mx[0, 1]) < 1e-3 and abs(Mx[1, 0]) < 1e-3
+
+
+def test_bilinear_gradient_cell_edge_convention():
+    """Samples on a pixel line (up to rounding) take the gradient of the cell
+    to their right / below; the interpolated value is continuous there."""
+    img = np.array([[0.0, 1.0, 5.0], [0.0, 2.0, 9.0], [0.0, 3.0, 1.0]])
+    for x in (1.0, 1.0 - 1e-12, 1.0 + 1e-12):
+        v, dx, dy = O.bilinear_with_gradient(img, np.array([x]), np.array([0.5]))
+        assert abs(dx[0] - ((1 - 0.5) * (5 - 1) + 0.5 * (9 - 2))) < 1e-9
+        assert abs(v[0] - 1.5) < 1e-9
+    v, dx, _ = O.bilinear_with_gradient(img, np.array([1.0 - 1e-6]), np.array([0.5]))
+    assert abs(dx[0] - ((1 - 0.5) * (1 - 0) + 0.5 * (2 - 0))) < 1e-9
