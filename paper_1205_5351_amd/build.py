@@ -41,6 +41,10 @@ def compile_flags():
         "-fPIC",
         # packed FP32 instructions are disabled for all device code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # no implicit multiply-add contraction: every fused multiply-add is
+        # an explicit fmaf, so a device function gives the same bits in
+        # every kernel it is inlined into (plain path == batched path)
+        "-ffp-contract=off",
         f"-I{INCLUDE}",
         f"-I{CSRC}",
         "-Wno-unused-command-line-argument",

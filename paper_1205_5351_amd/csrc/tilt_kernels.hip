@@ -208,14 +208,14 @@ __device__ void jacobi_rows(float* B, int nc, int nr4, int ld, float tol, int ma
                             const int ch = q + c * LPP;
                             if (ch < nr4) {
                                 float4 na, nb;
-                                na.x = cs * a[c].x - sn * b[c].x;
-                                na.y = cs * a[c].y - sn * b[c].y;
-                                na.z = cs * a[c].z - sn * b[c].z;
-                                na.w = cs * a[c].w - sn * b[c].w;
-                                nb.x = sn * a[c].x + cs * b[c].x;
-                                nb.y = sn * a[c].y + cs * b[c].y;
-                                nb.z = sn * a[c].z + cs * b[c].z;
-                                nb.w = sn * a[c].w + cs * b[c].w;
+                                na.x = fmaf(cs, a[c].x, -(sn * b[c].x));
+                                na.y = fmaf(cs, a[c].y, -(sn * b[c].y));
+                                na.z = fmaf(cs, a[c].z, -(sn * b[c].z));
+                                na.w = fmaf(cs, a[c].w, -(sn * b[c].w));
+                                nb.x = fmaf(sn, a[c].x, cs * b[c].x);
+                                nb.y = fmaf(sn, a[c].y, cs * b[c].y);
+                                nb.z = fmaf(sn, a[c].z, cs * b[c].z);
+                                nb.w = fmaf(sn, a[c].w, cs * b[c].w);
                                 *reinterpret_cast<float4*>(pa + 4 * ch) = na;
                                 *reinterpret_cast<float4*>(pb + 4 * ch) = nb;
                             }
@@ -471,7 +471,11 @@ __device__ inline void xlayout_to_ij(const PatchDesc& d, int row, int col, int& 
     }
 }
 
+constexpr double kSnap = 1e-9;  // pixels
+
 // Sample D o tau at grid point (i, j) and the raw Jacobian d(D o tau)/dtau.
+// Bilinear interpolation written as two horizontal lerps and one vertical
+// lerp; its partial derivatives are the exact ones of that interpolant.
 __device__ inline float warp_pixel(const PatchDesc& d, const double* h, int i, int j, float* jraw) {
     const double s = d.s;
     const double ut = ((double)j - 0.5 * (double)(d.n - 1)) / s;
@@ -484,18 +488,25 @@ __device__ inline float warp_pixel(const PatchDesc& d, const double* h, int i, i
     const double x = s * xt + d.cx, y = s * yt + d.cy;
     const double xc = fmin(fmax(x, 0.0), (double)(d.W - 1));
     const double yc = fmin(fmax(y, 0.0), (double)(d.H - 1));
-    const int x0 = min((int)floor(xc), d.W - 2);
-    const int y0 = min((int)floor(yc), d.H - 2);
+    // A sample within SNAP of a pixel line belongs to the cell right of /
+    // below it, so rounding of the coordinate cannot flip the cell (and the
+    // one-sided gradient) of samples that sit on the pixel grid.
+    const int x0 = min((int)floor(xc + kSnap), d.W - 2);
+    const int y0 = min((int)floor(yc + kSnap), d.H - 2);
     const float fx = (float)(xc - (double)x0);
     const float fy = (float)(yc - (double)y0);
     const float* r0 = d.image + (long long)y0 * d.stride + x0;
     const float* r1 = r0 + d.stride;
     const float v00 = r0[0], v01 = r0[1], v10 = r1[0], v11 = r1[1];
-    const float val = (1.f - fy) * ((1.f - fx) * v00 + fx * v01) + fy * ((1.f - fx) * v10 + fx * v11);
+    const float dtop = v01 - v00, dbot = v11 - v10;
+    const float top = fmaf(fx, dtop, v00);
+    const float bot = fmaf(fx, dbot, v10);
+    const float val = fmaf(fy, bot - top, top);
     const bool inx = (x >= 0.0) && (x <= (double)(d.W - 1));
     const bool iny = (y >= 0.0) && (y <= (double)(d.H - 1));
-    const float gx = inx ? (1.f - fy) * (v01 - v00) + fy * (v11 - v10) : 0.f;
-    const float gy = iny ? (1.f - fx) * (v10 - v00) + fx * (v11 - v01) : 0.f;
+    const float dl = v10 - v00, dr = v11 - v01;
+    const float gx = inx ? fmaf(fy, dbot - dtop, dtop) : 0.f;
+    const float gy = iny ? fmaf(fx, dr - dl, dl) : 0.f;
     const double sw = s * iw;
     const double gxd = gx, gyd = gy;
     jraw[0] = (float)(gxd * sw * ut);
@@ -911,10 +922,10 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
         const float4 r = *reinterpret_cast<const float4*>(R + o);
         const float4 y = *reinterpret_cast<const float4*>(Y + o);
         float4 mm;
-        mm.x = a.x - r.x - y.x * inv_mu;
-        mm.y = a.y - r.y - y.y * inv_mu;
-        mm.z = a.z - r.z - y.z * inv_mu;
-        mm.w = a.w - r.w - y.w * inv_mu;
+        mm.x = fmaf(-y.x, inv_mu, a.x - r.x);
+        mm.y = fmaf(-y.y, inv_mu, a.y - r.y);
+        mm.z = fmaf(-y.z, inv_mu, a.z - r.z);
+        mm.w = fmaf(-y.w, inv_mu, a.w - r.w);
         *reinterpret_cast<float4*>(M + o) = mm;
         *reinterpret_cast<float4*>(L.B + row * ld + 4 * c) = mm;
     }
@@ -1010,7 +1021,7 @@ __device__ void dev_update(const PatchDesc& d, PatchState* st, const SolverParam
         float en[4], s2[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const float nv = eo[u] - s[u] - yy[u] * inv_mu;
+            const float nv = fmaf(-yy[u], inv_mu, eo[u] - s[u]);
             const float mag = fabsf(nv) - thr;
             en[u] = mag > 0.f ? copysignf(mag, nv) : 0.f;
             const float de = en[u] - eo[u];
