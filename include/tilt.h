@@ -110,6 +110,10 @@ typedef struct {
     double mu;              /* penalty at the end of the last inner loop      */
     double cond1, cond2;    /* last values of the Cond1 / Cond2 quantities    */
     double dtau_norm;       /* ||Delta tau||_2 of the last outer iteration    */
+    double solve_ms;        /* device time from the start to the end of this
+                               patch's solve (device wall clock)              */
+    double done_ms;         /* device time from the start of the first patch
+                               of the call to the end of this one             */
     tilt_counters counters;
 } tilt_result;
 
@@ -147,6 +151,11 @@ typedef struct tilt_ctx tilt_ctx;
  * device workspace the context may hold (0 = 1/2 of free memory). */
 int tilt_ctx_create(tilt_ctx** ctx, int device, size_t hbm_budget_bytes);
 int tilt_ctx_destroy(tilt_ctx* ctx);
+
+/* Duration in milliseconds of the last fused batch kernel launched through
+ * this context, measured with HIP events recorded around the launch on its
+ * stream (0 if none). */
+int tilt_ctx_last_kernel_ms(tilt_ctx* ctx, double* ms);
 
 /* Bytes of device workspace one problem needs (for admission control). */
 size_t tilt_workspace_bytes(const tilt_problem* prob);

@@ -226,6 +226,9 @@ struct tilt_ctx {
     int device = 0;
     size_t budget = 0;
     DevBuf descs, states, ws, queue, scratch, jobs, counters, img;
+    double wall_rate_khz = 100000.0;  // device wall clock
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_kernel_ms = 0.0;
 };
 
 namespace {
@@ -292,11 +295,14 @@ int prepare(const tilt_problem* probs, int count, const tilt_params* prm, tilt_r
     return worst;
 }
 
-void fill_result(const PatchDesc& d, const PatchState& s, const Norm& nm, int prep_status, tilt_result* r) {
+void fill_result(const PatchDesc& d, const PatchState& s, const Norm& nm, int prep_status, tilt_result* r,
+                 double rate_khz, long long t0) {
     if (prep_status != TILT_OK) {
         r->status = prep_status;
         return;
     }
+    r->solve_ms = (double)(s.t_end - s.t_begin) / rate_khz;
+    r->done_ms = (double)(s.t_end - t0) / rate_khz;
     denormalise(s.tau, d.model, nm.cx, nm.cy, nm.s, r->tau);
     r->outer_iters = s.outer;
     r->inner_iters_total = s.inner_total;
@@ -405,17 +411,26 @@ int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const 
                 ncu = prop.multiProcessorCount;
             const int per_cu = std::max<int>(1, (int)(LDS_LIMIT / (Q.max_lds + kStaticLdsMargin)));
             const int grid = std::max(1, std::min(nlive, ncu * std::min(per_cu, 2)));
+            HIP_TRY(hipEventRecord(ctx->ev0, stream));
             HIP_TRY(launch_fused(reinterpret_cast<const PatchDesc*>(ctx->descs.p),
                                  reinterpret_cast<PatchState*>(ctx->states.p), sp, nlive,
                                  reinterpret_cast<int*>(ctx->queue.p), grid, Q.max_lds, stream));
+            HIP_TRY(hipEventRecord(ctx->ev1, stream));
         }
         std::vector<PatchState> out(nlive);
         HIP_TRY(hipMemcpyAsync(out.data(), ctx->states.p, sizeof(PatchState) * nlive, hipMemcpyDeviceToHost,
                                stream));
         HIP_TRY(hipStreamSynchronize(stream));
+        if (!plain) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+            ctx->last_kernel_ms = ms;
+        }
+        long long t0 = out[0].t_begin;
+        for (int k = 1; k < nlive; ++k) t0 = std::min(t0, out[k].t_begin);
         for (int k = 0; k < nlive; ++k) {
             const int i = live[k];
-            fill_result(P.descs[i], out[k], P.norms[i], TILT_OK, &results[i]);
+            fill_result(P.descs[i], out[k], P.norms[i], TILT_OK, &results[i], ctx->wall_rate_khz, t0);
             worst = worse(worst, results[i].status);
         }
     }
@@ -533,6 +548,13 @@ int tilt_ctx_create(tilt_ctx** ctx, int device, size_t hbm_budget_bytes) {
     if (!c) return TILT_ERR_NOMEM;
     c->device = device;
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : free_b / 2;
+    int rate = 0;
+    if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate > 0)
+        c->wall_rate_khz = (double)rate;
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        delete c;
+        return TILT_ERR_DEVICE;
+    }
     *ctx = c;
     return TILT_OK;
 }
@@ -549,7 +571,15 @@ int tilt_ctx_destroy(tilt_ctx* ctx) {
     ctx->jobs.release();
     ctx->counters.release();
     ctx->img.release();
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;
+    return TILT_OK;
+}
+
+int tilt_ctx_last_kernel_ms(tilt_ctx* ctx, double* ms) {
+    if (!ctx || !ms) return TILT_ERR_ARG;
+    *ms = ctx->last_kernel_ms;
     return TILT_OK;
 }
 

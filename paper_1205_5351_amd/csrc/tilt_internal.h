@@ -46,6 +46,7 @@ struct PatchState {
     double dA2, dE2;
     int outer, inner, inner_total, done_inner, done_outer, status, svt_rank, warn;
     long long svt_calls, sweeps, pairs, rotations, recon_rows;
+    long long t_begin, t_end;  // device wall clock at the start / end of the solve
 };
 
 struct SolverParams {

@@ -1182,6 +1182,7 @@ extern __shared__ float4 tilt_dyn_lds[];
 
 __device__ void solve_patch(const PatchDesc& d, PatchState* st, const SolverParams& prm, float* lds) {
     __shared__ int sh_flag;
+    if (threadIdx.x == 0) st->t_begin = (long long)wall_clock64();
     for (;;) {
         dev_setup(d, st, prm, lds);
         if (threadIdx.x == 0) sh_flag = st->status < 0;
@@ -1203,6 +1204,7 @@ __device__ void solve_patch(const PatchDesc& d, PatchState* st, const SolverPara
         if (sh_flag) break;
     }
     dev_finalize(d, st);
+    if (threadIdx.x == 0) st->t_end = (long long)wall_clock64();
 }
 
 __global__ void __launch_bounds__(NT) k_fused(const PatchDesc* __restrict__ descs, PatchState* states,
@@ -1223,6 +1225,7 @@ __global__ void __launch_bounds__(NT) k_fused(const PatchDesc* __restrict__ desc
 __global__ void __launch_bounds__(NT) k_setup(const PatchDesc* descs, PatchState* states, SolverParams prm, int idx) {
     float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
     const PatchDesc d = descs[idx];
+    if (threadIdx.x == 0 && states[idx].outer == 0) states[idx].t_begin = (long long)wall_clock64();
     dev_setup(d, states + idx, prm, lds);
 }
 
@@ -1245,6 +1248,7 @@ __global__ void __launch_bounds__(NT) k_dtau(const PatchDesc* descs, PatchState*
 __global__ void __launch_bounds__(NT) k_finalize(const PatchDesc* descs, PatchState* states, int idx) {
     const PatchDesc d = descs[idx];
     dev_finalize(d, states + idx);
+    if (threadIdx.x == 0) states[idx].t_end = (long long)wall_clock64();
 }
 
 // Component kernel: normalised warp and Jacobian (Alg. 1 Step 1); one

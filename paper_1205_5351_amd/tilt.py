@@ -115,6 +115,8 @@ class Result(C.Structure):
         ("cond1", C.c_double),
         ("cond2", C.c_double),
         ("dtau_norm", C.c_double),
+        ("solve_ms", C.c_double),
+        ("done_ms", C.c_double),
         ("counters", Counters),
     ]
 
@@ -135,6 +137,8 @@ _lib.tilt_ctx_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_size_t]
 _lib.tilt_ctx_create.restype = C.c_int
 _lib.tilt_ctx_destroy.argtypes = [C.c_void_p]
 _lib.tilt_ctx_destroy.restype = C.c_int
+_lib.tilt_ctx_last_kernel_ms.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
+_lib.tilt_ctx_last_kernel_ms.restype = C.c_int
 _lib.tilt_workspace_bytes.argtypes = [C.POINTER(Problem)]
 _lib.tilt_workspace_bytes.restype = C.c_size_t
 _lib.tilt_solve_batch.argtypes = [C.c_void_p, C.POINTER(Problem), C.c_int, C.POINTER(Params),
@@ -154,6 +158,7 @@ EXPORTS = [
     "tilt_default_params", "tilt_status_string", "tilt_version", "tilt_tau_from_quad", "tilt_solve",
     "tilt_ctx_create", "tilt_ctx_destroy", "tilt_workspace_bytes", "tilt_solve_batch",
     "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_warp_jacobian", "tilt_last_error",
+    "tilt_ctx_last_kernel_ms",
 ]
 
 
@@ -228,6 +233,8 @@ def result_dict(r: Result) -> dict:
         cond1=r.cond1,
         cond2=r.cond2,
         dtau_norm=r.dtau_norm,
+        solve_ms=r.solve_ms,
+        done_ms=r.done_ms,
         counters=dict(inner_iters=c.inner_iters, svt_calls=c.svt_calls, jacobi_sweeps=c.jacobi_sweeps,
                       jacobi_pairs=c.jacobi_pairs, jacobi_rotations=c.jacobi_rotations,
                       recon_rows=c.recon_rows),
@@ -307,6 +314,11 @@ class Context:
         if rc < 0 and rc not in (TILT_ERR_SINGULAR, TILT_ERR_NONFINITE, TILT_ERR_TOO_LARGE, TILT_ERR_ARG):
             raise TiltError(rc, fn.__name__)
         return rc, [result_dict(rarr[i]) for i in range(n)]
+
+    def last_kernel_ms(self) -> float:
+        ms = C.c_double()
+        _lib.tilt_ctx_last_kernel_ms(self._h, C.byref(ms))
+        return ms.value
 
     def solve_batch(self, problems, params=None, outs_A=None, outs_E=None, stream=None):
         """Fused persistent kernel over all problems (device images/outputs)."""
