@@ -53,28 +53,46 @@ struct ShapeCfg {
     size_t ws_floats;
 };
 
-int pick_svt_cfg(int nr4) {
-    if (nr4 <= 16) return SVT_L4C4;
-    if (nr4 <= 32) return SVT_L4C8;
-    if (nr4 <= 64) return SVT_L8C8;
-    if (nr4 <= 128) return SVT_L8C16;
-    return -1;
+// Jacobi layout for a matrix of nc rows of nr4 float4 chunks: lanes per
+// block pair (LPP) and chunks per lane (NCH, at most 8 so that the four
+// rows of a block pair fit in registers).  Estimated cycles per round are
+// proportional to the block pairs each lane group handles times (NCH + a
+// fixed cost for the reductions and rotation parameters, which grows with
+// the reduction width); the cheapest supported layout wins.
+int pick_svt_cfg(int nc, int nr4) {
+    const int nc4 = (nc + 3) & ~3;
+    const int Pb = nc4 / 4;
+    int best = -1;
+    double best_cost = 1e300;
+    const int lpps[3] = {4, 8, 16};
+    for (int li = 0; li < 3; ++li) {
+        const int lpp = lpps[li];
+        const int nch = (nr4 + lpp - 1) / lpp;
+        if (nch > SVT_MAX_NCH) continue;
+        const int groups = NT / lpp;
+        const int per_group = (Pb + groups - 1) / groups;
+        const double cost = per_group * (nch + 1.5 + 0.5 * li);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = svt_make_cfg(lpp, nch);
+        }
+    }
+    return best;
 }
 
-// Smallest LDS row stride >= ldg of the form 4*LPP*(2k+1): the LPP lanes of
-// a group read 16*LPP contiguous bytes and consecutive rows land on
-// disjoint bank ranges.
-int pick_ld(int ldg, int lpp) {
-    const int unit = 4 * lpp;
-    int k = 0;
-    while (unit * (2 * k + 1) < ldg) ++k;
-    return unit * (2 * k + 1);
+// LDS row stride: 4*LPP*NCH floats (every lane reads NCH chunks), bumped to
+// an odd multiple of 4*LPP so consecutive rows start in different bank
+// ranges.
+int pick_ld(int cfg) {
+    const int unit = 4 * svt_lpp(cfg);
+    int k = svt_nch(cfg);
+    if ((k & 1) == 0) ++k;
+    return unit * k;
 }
 
 size_t lds_bytes(int nc, int ld, int tb) {
-    const int ncp = nc + (nc & 1);
     const int nc4 = (nc + 3) & ~3;
-    return sizeof(float) * ((size_t)ncp * ld + (size_t)tb * ld + (size_t)nc4 * tb + 3 * (size_t)nc4);
+    return sizeof(float) * ((size_t)nc4 * ld + (size_t)tb * ld + (size_t)nc4 * tb + 3 * (size_t)nc4);
 }
 
 int shape_config(int m, int n, ShapeCfg* out) {
@@ -83,9 +101,10 @@ int shape_config(int m, int n, ShapeCfg* out) {
     c.nc = std::min(m, n);
     c.nr = std::max(m, n);
     c.ldg = (c.nr + 3) & ~3;
-    c.cfg = pick_svt_cfg(c.ldg / 4);
+    if (((c.nc + 3) & ~3) > SVT_MAX_ROWS) return TILT_ERR_TOO_LARGE;
+    c.cfg = pick_svt_cfg(c.nc, c.ldg / 4);
     if (c.cfg < 0) return TILT_ERR_TOO_LARGE;
-    c.ld = pick_ld(c.ldg, svt_lpp(c.cfg));
+    c.ld = pick_ld(c.cfg);
     c.tb = 32;
     c.lds = lds_bytes(c.nc, c.ld, c.tb);
     if (c.lds + kStaticLdsMargin > (size_t)LDS_LIMIT) {

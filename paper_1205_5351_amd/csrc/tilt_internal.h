@@ -18,8 +18,11 @@ constexpr int LDS_LIMIT = 160 * 1024;
 // one-sided Jacobi orthogonalises (length nr = max(m, n)) are contiguous.
 enum Plane { PL_I = 0, PL_A = 1, PL_E = 2, PL_Y = 3, PL_R = 4, PL_M = 5, PL_Q = 6 };
 
-// Jacobi variants: lanes per column pair and float4 chunks held per lane.
-enum SvtCfg { SVT_L4C4 = 0, SVT_L4C8 = 1, SVT_L8C8 = 2, SVT_L8C16 = 3, SVT_NCFG = 4 };
+// Jacobi variants: cfg = (log2(LPP) - 2) * 16 + (NCH - 1) with LPP lanes per
+// block pair (4, 8 or 16) and NCH float4 chunks of each row held per lane
+// (1..8).
+constexpr int SVT_MAX_NCH = 8;
+constexpr int SVT_MAX_ROWS = 256;  // rows of the Jacobi matrix (min(m, n) rounded up to 4)
 
 struct PatchDesc {
     const float* image;
@@ -67,9 +70,10 @@ struct SvtJob {
 };
 
 // LDS layout helpers (host and device).
-__host__ __device__ inline int svt_lpp(int cfg) { return (cfg == SVT_L4C4 || cfg == SVT_L4C8) ? 4 : 8; }
-__host__ __device__ inline int svt_maxch(int cfg) {
-    return cfg == SVT_L4C4 ? 4 : (cfg == SVT_L8C16 ? 16 : 8);
+__host__ __device__ inline int svt_lpp(int cfg) { return 4 << (cfg >> 4); }
+__host__ __device__ inline int svt_nch(int cfg) { return (cfg & 15) + 1; }
+__host__ __device__ inline int svt_make_cfg(int lpp, int nch) {
+    return (lpp == 4 ? 0 : (lpp == 8 ? 1 : 2)) * 16 + (nch - 1);
 }
 
 // Kernel launchers (tilt_kernels.hip).

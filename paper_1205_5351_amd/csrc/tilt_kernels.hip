@@ -111,178 +111,241 @@ __device__ inline float dpp_half_mirror(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
 }
 
-// Sum over the LPP lanes of a group; all lanes get identical bits.
+__device__ inline float dpp_mirror(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
+}
+
+// Sum over the LPP (4, 8 or 16) lanes of a group; all lanes get identical
+// bits (each step adds two equal partial sums in either order).
 template <int LPP>
 __device__ inline float group_sum(float v) {
     v += dpp_xor1(v);
     v += dpp_xor2(v);
     if (LPP >= 8) v += dpp_half_mirror(v);
+    if (LPP >= 16) v += dpp_mirror(v);
     return v;
 }
 
 __device__ inline float4 f4(float a) { return make_float4(a, a, a, a); }
 
 // ---------------------------------------------------------------------------
-// One-sided Jacobi on the rows of B (LDS), round-robin ordering.
+// One-sided Jacobi on the rows of B (LDS), blocks of two rows, round-robin
+// ordering of the blocks.
 //
-// Rows 0..nc-1 (plus a zero row when nc is odd) of length 4*nr4 with stride
-// ld.  Each round pairs every row with another (circle method: the last
-// index is fixed, pair k of round r is (r+k, r-k) mod N); a group of LPP
-// lanes owns one pair, holds both rows in registers, reduces the three inner
-// products with DPP and applies the rotation that makes the pair
-// orthogonal.  A pair is rotated when |a.b| > tol ||a|| ||b||; the sweeps
-// stop when a whole sweep rotates nothing.
+// Rows 0..nc4-1 (nc rounded up to a multiple of 4 with zero rows) with
+// stride ld; every row is zero-padded to 4*LPP*NCH floats so each of the
+// LPP lanes of a group reads exactly NCH float4 chunks (lane q owns chunks
+// q, q+LPP, ...).  Rows 2b and 2b+1 form block b.  Each round pairs every
+// block with another (circle method: the last block is fixed, pair k of
+// round r is (r+k, r-k) mod (nb-1)); a group owns one block pair, holds its
+// four rows in registers and applies, in order, the rotations of the pairs
+// (a1,b1), (a2,b2), (a1,b2), (a2,b1) -- plus (a1,a2), (b1,b2) in the first
+// round of a sweep -- so every pair of rows is met once per sweep while the
+// rows go through LDS once per round.  A pair is rotated when
+// |a.b| > tol ||a|| ||b||; the sweeps stop when a whole sweep rotates
+// nothing.  Squared row norms are recomputed exactly at the start of each
+// sweep and updated through each rotation (||a'||^2 = ||a||^2 - t a.b,
+// ||b'||^2 = ||b||^2 + t a.b), so the final sweep, which rotates nothing,
+// tests every pair against exact norms.
 // ---------------------------------------------------------------------------
 
 struct JacobiStats {
     long long sweeps, pairs, rotations;
 };
 
-template <int LPP, int MAXCH>
-__device__ void jacobi_rows(float* B, int nc, int nr4, int ld, float tol, int max_sweeps,
-                            JacobiStats& js) {
-    const int tid = threadIdx.x;
-    const int g = tid / LPP, q = tid % LPP;
-    constexpr int G = NT / LPP;
-    const int ncp = nc + (nc & 1);
-    const int P = ncp >> 1, N = ncp - 1;
-    long long rots = 0;
-    int sweeps = 0;
-    if (ncp >= 2) {
-        for (int sw = 0; sw < max_sweeps; ++sw) {
-            int any = 0;
-            for (int r = 0; r < N; ++r) {
-                for (int k = g; k < P; k += G) {
-                    int i, j;
-                    if (k == 0) {
-                        i = N;
-                        j = r;
-                    } else {
-                        i = r + k;
-                        if (i >= N) i -= N;
-                        j = r - k;
-                        if (j < 0) j += N;
-                    }
-                    float* pa = B + i * ld;
-                    float* pb = B + j * ld;
-                    float4 a[MAXCH], b[MAXCH];
-                    float al = 0.f, be = 0.f, ga = 0.f;
-#pragma unroll
-                    for (int c = 0; c < MAXCH; ++c) {
-                        const int ch = q + c * LPP;
-                        if (ch < nr4) {
-                            a[c] = *reinterpret_cast<const float4*>(pa + 4 * ch);
-                            b[c] = *reinterpret_cast<const float4*>(pb + 4 * ch);
-                        } else {
-                            a[c] = f4(0.f);
-                            b[c] = f4(0.f);
-                        }
-                        al = fmaf(a[c].x, a[c].x, al);
-                        al = fmaf(a[c].y, a[c].y, al);
-                        al = fmaf(a[c].z, a[c].z, al);
-                        al = fmaf(a[c].w, a[c].w, al);
-                        be = fmaf(b[c].x, b[c].x, be);
-                        be = fmaf(b[c].y, b[c].y, be);
-                        be = fmaf(b[c].z, b[c].z, be);
-                        be = fmaf(b[c].w, b[c].w, be);
-                        ga = fmaf(a[c].x, b[c].x, ga);
-                        ga = fmaf(a[c].y, b[c].y, ga);
-                        ga = fmaf(a[c].z, b[c].z, ga);
-                        ga = fmaf(a[c].w, b[c].w, ga);
-                    }
-                    al = group_sum<LPP>(al);
-                    be = group_sum<LPP>(be);
-                    ga = group_sum<LPP>(ga);
-                    if (fabsf(ga) > tol * (sqrtf(al) * sqrtf(be))) {
-                        // Rotation angle in FP64, then c and s rounded once to
-                        // FP32: c^2 + s^2 - 1 is then an unbiased rounding
-                        // error, so row norms do not drift over the ~n^2 S/2
-                        // rotations of a decomposition.
-                        const double zeta = ((double)be - (double)al) / (2.0 * (double)ga);
-                        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                        const double cd = 1.0 / sqrt(1.0 + t * t);
-                        const float cs = (float)cd;
-                        const float sn = (float)(cd * t);
-#pragma unroll
-                        for (int c = 0; c < MAXCH; ++c) {
-                            const int ch = q + c * LPP;
-                            if (ch < nr4) {
-                                float4 na, nb;
-                                na.x = fmaf(cs, a[c].x, -(sn * b[c].x));
-                                na.y = fmaf(cs, a[c].y, -(sn * b[c].y));
-                                na.z = fmaf(cs, a[c].z, -(sn * b[c].z));
-                                na.w = fmaf(cs, a[c].w, -(sn * b[c].w));
-                                nb.x = fmaf(sn, a[c].x, cs * b[c].x);
-                                nb.y = fmaf(sn, a[c].y, cs * b[c].y);
-                                nb.z = fmaf(sn, a[c].z, cs * b[c].z);
-                                nb.w = fmaf(sn, a[c].w, cs * b[c].w);
-                                *reinterpret_cast<float4*>(pa + 4 * ch) = na;
-                                *reinterpret_cast<float4*>(pb + 4 * ch) = nb;
-                            }
-                        }
-                        any = 1;
-                        if (q == 0) ++rots;
-                    }
-                }
-                __syncthreads();
-            }
-            ++sweeps;
-            if (!__syncthreads_or(any)) break;
-        }
-    }
-    js.sweeps += sweeps;
-    js.pairs += (long long)sweeps * P * N;
-    js.rotations += block_sum_ll(rots);
+// Rotation (c, s, t) that zeroes a.b for norms al = ||a||^2, be = ||b||^2
+// and ga = a.b (Hestenes / Rutishauser: t = sgn(z)/(|z| + sqrt(1 + z^2)),
+// z = (be - al)/(2 ga), c = 1/sqrt(1 + t^2), s = c t).  Hardware
+// reciprocal / square-root estimates give the angle to about one ulp; the
+// final scaling by 1 + (1 - c^2 - s^2)/2 removes, to first order, the
+// deviation of c^2 + s^2 from 1, so row norms do not drift over the many
+// rotations of a decomposition.
+__device__ inline void jacobi_rotation(float al, float be, float ga, float& cs, float& sn, float& tn) {
+    const float zeta = (be - al) * __builtin_amdgcn_rcpf(2.0f * ga);
+    const float root = __builtin_amdgcn_sqrtf(fmaf(zeta, zeta, 1.0f));
+    const float t = copysignf(__builtin_amdgcn_rcpf(fabsf(zeta) + root), zeta);
+    float c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.0f));
+    float s = c * t;
+    const float d = fmaf(-c, c, fmaf(-s, s, 1.0f));
+    const float corr = fmaf(0.5f, d, 1.0f);
+    cs = c * corr;
+    sn = s * corr;
+    tn = t;
 }
 
-// Squared norms of rows 0..nc-1 of B into s2 (LDS); same reduction shape as
-// the Jacobi inner products.
-template <int LPP, int MAXCH>
-__device__ void row_norms(const float* B, int nc, int nr4, int ld, float* s2) {
+__device__ inline float dot4(const float4& a, const float4& b, float acc) {
+    acc = fmaf(a.x, b.x, acc);
+    acc = fmaf(a.y, b.y, acc);
+    acc = fmaf(a.z, b.z, acc);
+    acc = fmaf(a.w, b.w, acc);
+    return acc;
+}
+
+// a.b summed over the group (two partial sums per lane for shorter chains).
+template <int LPP, int NCH>
+__device__ inline float group_dot(const float4* a, const float4* b) {
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCH; c += 2) s0 = dot4(a[c], b[c], s0);
+#pragma unroll
+    for (int c = 1; c < NCH; c += 2) s1 = dot4(a[c], b[c], s1);
+    return group_sum<LPP>(s0 + s1);
+}
+
+// Rotate rows x, y (registers of the group) if they are not yet orthogonal
+// to tolerance; updates their squared norms.  The decision is uniform over
+// the group (all lanes hold identical sums).
+template <int LPP, int NCH>
+__device__ inline bool rotate_rows(float4* x, float4* y, float& nx, float& ny, float tol) {
+    const float ga = group_dot<LPP, NCH>(x, y);
+    if (!(fabsf(ga) > tol * (__builtin_amdgcn_sqrtf(nx) * __builtin_amdgcn_sqrtf(ny)))) return false;
+    float cs, sn, t;
+    jacobi_rotation(nx, ny, ga, cs, sn, t);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const float4 a = x[c], b = y[c];
+        x[c].x = fmaf(cs, a.x, -(sn * b.x));
+        x[c].y = fmaf(cs, a.y, -(sn * b.y));
+        x[c].z = fmaf(cs, a.z, -(sn * b.z));
+        x[c].w = fmaf(cs, a.w, -(sn * b.w));
+        y[c].x = fmaf(sn, a.x, cs * b.x);
+        y[c].y = fmaf(sn, a.y, cs * b.y);
+        y[c].z = fmaf(sn, a.z, cs * b.z);
+        y[c].w = fmaf(sn, a.w, cs * b.w);
+    }
+    // Tracked norms; clamped at 0 (cancellation can only make a small norm
+    // inaccurate until the exact recomputation at the next sweep start).
+    nx = fmaxf(fmaf(-t, ga, nx), 0.f);
+    ny = fmaxf(fmaf(t, ga, ny), 0.f);
+    return true;
+}
+
+// Squared norms of rows 0..nrows-1 of B into s2 (LDS).
+template <int LPP, int NCH>
+__device__ void row_norms(const float* B, int nrows, int ld, float* s2) {
     const int tid = threadIdx.x;
     const int g = tid / LPP, q = tid % LPP;
     constexpr int G = NT / LPP;
-    for (int j = g; j < nc; j += G) {
-        const float* pj = B + j * ld;
-        float v = 0.f;
+    for (int j = g; j < nrows; j += G) {
+        const float* pj = B + j * ld + 4 * q;
+        float4 x[NCH];
 #pragma unroll
-        for (int c = 0; c < MAXCH; ++c) {
-            const int ch = q + c * LPP;
-            if (ch < nr4) {
-                const float4 x = *reinterpret_cast<const float4*>(pj + 4 * ch);
-                v = fmaf(x.x, x.x, v);
-                v = fmaf(x.y, x.y, v);
-                v = fmaf(x.z, x.z, v);
-                v = fmaf(x.w, x.w, v);
-            }
-        }
-        v = group_sum<LPP>(v);
+        for (int c = 0; c < NCH; ++c) x[c] = *reinterpret_cast<const float4*>(pj + 4 * LPP * c);
+        const float v = group_dot<LPP, NCH>(x, x);
         if (q == 0) s2[j] = v;
     }
     __syncthreads();
 }
 
-__device__ void jacobi_dispatch(int cfg, float* B, int nc, int nr4, int ld, float tol, int max_sweeps,
-                                JacobiStats& js, float* s2) {
+// Squared row norms during the sweeps: one LDS array for every variant.
+__shared__ float tilt_jacobi_nrm[SVT_MAX_ROWS];
+
+template <int LPP, int NCH>
+__device__ void jacobi_rows(float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js) {
+    float* nrm = tilt_jacobi_nrm;
+    const int tid = threadIdx.x;
+    const int g = tid / LPP, q = tid % LPP;
+    constexpr int G = NT / LPP;
+    const int nc4 = (nc + 3) & ~3;
+    const int nb = nc4 >> 1;          // blocks of two rows (even)
+    const int Pb = nb >> 1, Nb = nb - 1;
+    long long rots = 0;
+    int sweeps = 0;
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+        row_norms<LPP, NCH>(B, nc4, ld, nrm);
+        int any = 0;
+        for (int r = 0; r < Nb; ++r) {
+            for (int k = g; k < Pb; k += G) {
+                int I, J;
+                if (k == 0) {
+                    I = Nb;
+                    J = r;
+                } else {
+                    I = r + k;
+                    if (I >= Nb) I -= Nb;
+                    J = r - k;
+                    if (J < 0) J += Nb;
+                }
+                float* p0 = B + (2 * I) * ld + 4 * q;
+                float* p1 = p0 + ld;
+                float* p2 = B + (2 * J) * ld + 4 * q;
+                float* p3 = p2 + ld;
+                float4 a1[NCH], a2[NCH], b1[NCH], b2[NCH];
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    a1[c] = *reinterpret_cast<const float4*>(p0 + 4 * LPP * c);
+                    a2[c] = *reinterpret_cast<const float4*>(p1 + 4 * LPP * c);
+                    b1[c] = *reinterpret_cast<const float4*>(p2 + 4 * LPP * c);
+                    b2[c] = *reinterpret_cast<const float4*>(p3 + 4 * LPP * c);
+                }
+                float na1 = nrm[2 * I], na2 = nrm[2 * I + 1], nb1 = nrm[2 * J], nb2 = nrm[2 * J + 1];
+                bool d0 = false, d1 = false, d2 = false, d3 = false, f;
+                if (r == 0) {
+                    f = rotate_rows<LPP, NCH>(a1, a2, na1, na2, tol);
+                    d0 |= f; d1 |= f; rots += f;
+                    f = rotate_rows<LPP, NCH>(b1, b2, nb1, nb2, tol);
+                    d2 |= f; d3 |= f; rots += f;
+                }
+                f = rotate_rows<LPP, NCH>(a1, b1, na1, nb1, tol);
+                d0 |= f; d2 |= f; rots += f;
+                f = rotate_rows<LPP, NCH>(a2, b2, na2, nb2, tol);
+                d1 |= f; d3 |= f; rots += f;
+                f = rotate_rows<LPP, NCH>(a1, b2, na1, nb2, tol);
+                d0 |= f; d3 |= f; rots += f;
+                f = rotate_rows<LPP, NCH>(a2, b1, na2, nb1, tol);
+                d1 |= f; d2 |= f; rots += f;
+                if (d0 | d1 | d2 | d3) any = 1;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    if (d0) *reinterpret_cast<float4*>(p0 + 4 * LPP * c) = a1[c];
+                    if (d1) *reinterpret_cast<float4*>(p1 + 4 * LPP * c) = a2[c];
+                    if (d2) *reinterpret_cast<float4*>(p2 + 4 * LPP * c) = b1[c];
+                    if (d3) *reinterpret_cast<float4*>(p3 + 4 * LPP * c) = b2[c];
+                }
+                if (q == 0) {
+                    nrm[2 * I] = na1;
+                    nrm[2 * I + 1] = na2;
+                    nrm[2 * J] = nb1;
+                    nrm[2 * J + 1] = nb2;
+                }
+            }
+            __syncthreads();
+        }
+        ++sweeps;
+        if (!__syncthreads_or(any)) break;
+    }
+    // every pair of the nc4 rows is examined once per sweep
+    js.sweeps += sweeps;
+    js.pairs += (long long)sweeps * ((long long)nc4 * (nc4 - 1) / 2);
+    js.rotations += block_sum_ll(q == 0 ? rots : 0);
+}
+
+template <int LPP, int NCH>
+__device__ void jacobi_svd_rows(float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js, float* s2) {
+    jacobi_rows<LPP, NCH>(B, nc, ld, tol, max_sweeps, js);
+    row_norms<LPP, NCH>(B, nc, ld, s2);
+}
+
+// cfg = (log2(LPP) - 2) * 16 + (NCH - 1)
+#define TILT_SVT_CASE(L, C)                                                   \
+    case ((L == 4 ? 0 : (L == 8 ? 1 : 2)) * 16 + (C - 1)):                     \
+        jacobi_svd_rows<L, C>(B, nc, ld, tol, max_sweeps, js, s2);             \
+        break;
+
+__device__ void jacobi_dispatch(int cfg, float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js,
+                                float* s2) {
     switch (cfg) {
-        case SVT_L4C4:
-            jacobi_rows<4, 4>(B, nc, nr4, ld, tol, max_sweeps, js);
-            row_norms<4, 4>(B, nc, nr4, ld, s2);
-            break;
-        case SVT_L4C8:
-            jacobi_rows<4, 8>(B, nc, nr4, ld, tol, max_sweeps, js);
-            row_norms<4, 8>(B, nc, nr4, ld, s2);
-            break;
-        case SVT_L8C8:
-            jacobi_rows<8, 8>(B, nc, nr4, ld, tol, max_sweeps, js);
-            row_norms<8, 8>(B, nc, nr4, ld, s2);
-            break;
+        TILT_SVT_CASE(4, 1) TILT_SVT_CASE(4, 2) TILT_SVT_CASE(4, 3) TILT_SVT_CASE(4, 4)
+        TILT_SVT_CASE(4, 5) TILT_SVT_CASE(4, 6) TILT_SVT_CASE(4, 7) TILT_SVT_CASE(4, 8)
+        TILT_SVT_CASE(8, 1) TILT_SVT_CASE(8, 2) TILT_SVT_CASE(8, 3) TILT_SVT_CASE(8, 4)
+        TILT_SVT_CASE(8, 5) TILT_SVT_CASE(8, 6) TILT_SVT_CASE(8, 7) TILT_SVT_CASE(8, 8)
+        TILT_SVT_CASE(16, 1) TILT_SVT_CASE(16, 2) TILT_SVT_CASE(16, 3) TILT_SVT_CASE(16, 4)
+        TILT_SVT_CASE(16, 5) TILT_SVT_CASE(16, 6) TILT_SVT_CASE(16, 7) TILT_SVT_CASE(16, 8)
         default:
-            jacobi_rows<8, 16>(B, nc, nr4, ld, tol, max_sweeps, js);
-            row_norms<8, 16>(B, nc, nr4, ld, s2);
             break;
     }
 }
+#undef TILT_SVT_CASE
 
 // ---------------------------------------------------------------------------
 // Singular value shrinkage from the orthogonalised rows.
@@ -295,28 +358,36 @@ __device__ void jacobi_dispatch(int cfg, float* B, int nc, int nr4, int ld, floa
 
 __device__ void shrink_weights(const float* s2, int nc, float eps, float* w, int* act, int* k_out,
                                double* nuc_out) {
-    __shared__ int sh_k;
-    __shared__ double sh_nuc;
-    if (threadIdx.x == 0) {
-        int k = 0;
-        double nuc = 0.0;
-        for (int j = 0; j < nc; ++j) {
+    // w_j = (1 - eps/s_j)/s_j^2 for s_j > eps (else 0); act lists the kept
+    // rows in ascending order (ballot + prefix count per wavefront).
+    __shared__ int wave_cnt[NWAVE];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double nuc[1] = {0.0};
+    int base = 0;
+    for (int j0 = 0; j0 < nc; j0 += NT) {
+        const int j = j0 + tid;
+        bool on = false;
+        if (j < nc) {
             const float sg = sqrtf(s2[j]);
-            if (sg > eps) {
-                w[j] = (1.0f - eps / sg) / s2[j];
-                act[k++] = j;
-                nuc += (double)sg - (double)eps;
-            } else {
-                w[j] = 0.f;
-            }
+            on = sg > eps;
+            w[j] = on ? (1.0f - eps / sg) / s2[j] : 0.f;
+            if (on) nuc[0] += (double)sg - (double)eps;
         }
-        sh_k = k;
-        sh_nuc = nuc;
+        const unsigned long long bal = __ballot(on);
+        if (lane == 0) wave_cnt[wv] = __popcll(bal);
+        __syncthreads();
+        int off = base, tot = base;
+        for (int u = 0; u < NWAVE; ++u) {
+            if (u < wv) off += wave_cnt[u];
+            tot += wave_cnt[u];
+        }
+        if (on) act[off + __popcll(bal & ((1ull << lane) - 1ull))] = j;
+        __syncthreads();
+        base = tot;
     }
-    __syncthreads();
-    *k_out = sh_k;
-    *nuc_out = sh_nuc;
-    __syncthreads();
+    block_sum_d<1>(nuc);
+    *k_out = base;
+    *nuc_out = nuc[0];
 }
 
 // Returns this thread's partial sum of (A_new - A_old)^2 when track_diff.
@@ -431,10 +502,9 @@ struct SvtLds {
 
 __device__ inline SvtLds carve_lds(float* base, int nc, int ld, int tb) {
     SvtLds L;
-    const int ncp = nc + (nc & 1);
     const int nc4 = (nc + 3) & ~3;
     L.B = base;
-    L.xblk = L.B + ncp * ld;
+    L.xblk = L.B + nc4 * ld;
     L.cwt = L.xblk + tb * ld;
     L.s2 = L.cwt + nc4 * tb;
     L.w = L.s2 + nc4;
@@ -442,18 +512,32 @@ __device__ inline SvtLds carve_lds(float* base, int nc, int ld, int tb) {
     return L;
 }
 
+// Zero the LDS padding of the Jacobi matrix: columns [ldg, ld) of every
+// row and the extra rows nc..nc4-1 (nc rounded up to a multiple of 4).
+__device__ void clear_lds_padding(float* B, int nc, int ldg, int ld) {
+    const int tid = threadIdx.x;
+    const int padw4 = (ld - ldg) >> 2;
+    for (int idx = tid; idx < nc * padw4; idx += NT) {
+        const int row = idx / padw4, c = idx - row * padw4;
+        *reinterpret_cast<float4*>(B + row * ld + ldg + 4 * c) = f4(0.f);
+    }
+    const int nc4 = (nc + 3) & ~3;
+    const int ld4 = ld >> 2;
+    for (int idx = tid; idx < (nc4 - nc) * ld4; idx += NT) {
+        const int row = nc + idx / ld4, c = idx - (row - nc) * ld4;
+        *reinterpret_cast<float4*>(B + row * ld + 4 * c) = f4(0.f);
+    }
+}
+
 // Load an X-layout plane into the Jacobi matrix in LDS and clear padding.
 __device__ void load_rows_lds(const float* Xg, int nc, int ldg, int ld, float* B) {
     const int tid = threadIdx.x;
     const int nr4 = ldg >> 2;
-    const int ncp = nc + (nc & 1);
     for (int idx = tid; idx < nc * nr4; idx += NT) {
         const int row = idx / nr4, c = idx - row * nr4;
         *reinterpret_cast<float4*>(B + row * ld + 4 * c) = reinterpret_cast<const float4*>(Xg + (size_t)row * ldg)[c];
     }
-    if (ncp > nc) {
-        for (int c = tid; c < ld; c += NT) B[nc * ld + c] = 0.f;
-    }
+    clear_lds_padding(B, nc, ldg, ld);
     __syncthreads();
 }
 
@@ -869,7 +953,7 @@ __device__ void dev_setup(const PatchDesc& d, PatchState* st, const SolverParams
         SvtLds L = carve_lds(lds, nc, d.ld, d.tb);
         load_rows_lds(I, nc, ldg, d.ld, L.B);
         JacobiStats js{0, 0, 0};
-        jacobi_dispatch(d.svt_cfg, L.B, nc, ldg >> 2, d.ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
+        jacobi_dispatch(d.svt_cfg, L.B, nc, d.ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
         __shared__ float sh_smax;
         if (tid == 0) {
             float mx = 0.f;
@@ -929,13 +1013,11 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
         *reinterpret_cast<float4*>(M + o) = mm;
         *reinterpret_cast<float4*>(L.B + row * ld + 4 * c) = mm;
     }
-    if (nc & 1) {
-        for (int c = tid; c < ld; c += NT) L.B[nc * ld + c] = 0.f;
-    }
+    clear_lds_padding(L.B, nc, ldg, ld);
     __syncthreads();
 
     JacobiStats js{0, 0, 0};
-    jacobi_dispatch(d.svt_cfg, L.B, nc, nr4, ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
+    jacobi_dispatch(d.svt_cfg, L.B, nc, ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
 
     const float eps = (float)(1.0 / mu);
     int k;
@@ -1315,7 +1397,7 @@ __global__ void __launch_bounds__(NT) k_svt_jobs(const SvtJob* jobs, int cfg, in
     SvtLds L = carve_lds(lds, nc, ld, tb);
     load_rows_lds(X, nc, ldg, ld, L.B);
     JacobiStats js{0, 0, 0};
-    jacobi_dispatch(cfg, L.B, nc, nr4, ld, tol, max_sweeps, js, L.s2);
+    jacobi_dispatch(cfg, L.B, nc, ld, tol, max_sweeps, js, L.s2);
     int k;
     double nuc;
     shrink_weights(L.s2, nc, jb.eps, L.w, L.act, &k, &nuc);
@@ -1344,7 +1426,13 @@ __global__ void __launch_bounds__(NT) k_svt_jobs(const SvtJob* jobs, int cfg, in
 // Launchers
 // ---------------------------------------------------------------------------
 
+// Allow `lds` bytes of dynamic LDS; fails (hipErrorInvalidValue) when the
+// kernel's static LDS plus `lds` exceeds the 160 KiB of a CU.
 static hipError_t set_lds(const void* fn, size_t lds) {
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, fn);
+    if (e != hipSuccess) return e;
+    if (attr.sharedSizeBytes + lds > (size_t)LDS_LIMIT) return hipErrorInvalidValue;
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 

@@ -159,18 +159,36 @@ def test_fixed_iterations_match_oracle(tilt, ctx, device, cfg, idx, outer, inner
 # ---------------------------------------------------------------------------
 
 
-@pytest.mark.parametrize("cfg,idx", [(0, 0), (1, 0), (2, 5)])
+@pytest.mark.parametrize("cfg,idx", [(0, 1), (0, 2), (0, 6), (1, 0), (2, 2), (2, 5), (2, 8)])
 def test_full_solve_matches_oracle(tilt, ctx, device, cfg, idx):
+    """Converged solves: relative tau error <= 1e-4, objective within 1e-4,
+    same numerical rank."""
     p = ts.make_batch(cfg, [idx])[0]
     tp = tilt.default_params(lam=p.lam)
     rc, res = solve_on_device(tilt, ctx, [p], device, tp)
     r = res[0]
     assert r["status"] >= 0, r
     ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
+    assert ref.outer_iters < tp.max_outer and r["outer_iters"] < tp.max_outer  # both converged
     terr = O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n)
     assert terr <= 1e-4, (terr, r["outer_iters"], ref.outer_iters)
     assert abs(r["objective"] - ref.objective) <= 1e-4 * ref.objective
     assert O.numerical_rank(r["A"]) == O.numerical_rank(ref.A)
+
+
+def test_unconverged_outer_loop_tracks_oracle(tilt, ctx, device):
+    """A patch whose outer loop does not converge in 50 iterations (tau keeps
+    drifting along the axis-scaling direction that leaves a separable
+    texture low-rank): after the same 50 outer iterations the FP32 and FP64
+    trajectories still agree to 1e-3 in tau and 1e-4 in the objective."""
+    p = ts.make_batch(0, [0])[0]
+    tp = tilt.default_params(lam=p.lam)
+    rc, res = solve_on_device(tilt, ctx, [p], device, tp)
+    r = res[0]
+    ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
+    assert r["outer_iters"] == ref.outer_iters == tp.max_outer
+    assert O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n) <= 1e-3
+    assert abs(r["objective"] - ref.objective) <= 1e-4 * ref.objective
 
 
 # ---------------------------------------------------------------------------
