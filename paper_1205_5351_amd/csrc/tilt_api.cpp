@@ -18,7 +18,7 @@ using namespace tilt;
 
 namespace {
 
-constexpr int kStaticLdsMargin = 8 * 1024;  // static __shared__ use of the kernels
+constexpr int kStaticLdsMargin = 8 * 1024;  // static __shared__ use of the kernels (checked at launch)
 
 // ---------------------------------------------------------------------------
 // Device buffer that grows on demand.
@@ -53,41 +53,70 @@ struct ShapeCfg {
     size_t ws_floats;
 };
 
-// Jacobi layout for a matrix of nc rows of nr4 float4 chunks: lanes per
-// block pair (LPP) and chunks per lane (NCH, at most 8 so that the four
-// rows of a block pair fit in registers).  Estimated cycles per round are
-// proportional to the block pairs each lane group handles times (NCH + a
-// fixed cost for the reductions and rotation parameters, which grows with
-// the reduction width); the cheapest supported layout wins.
+// Jacobi layout for a matrix of nc rows of nr4 float4 chunks: rows per
+// block (BS), lanes per block pair (LPP) and chunks per lane (NCH).  The
+// model counts, per sweep, rounds x block pairs per lane group x the
+// instructions of a round (BS^2 rotations of NCH chunks plus a fixed cost
+// for the reduction and rotation parameters that grows with the reduction
+// width, plus the row loads/stores), and divides by the number of
+// concurrent groups' worth of issue slots when fewer groups than slots are
+// busy.  The cheapest layout wins.
 int pick_svt_cfg(int nc, int nr4) {
     const int nc4 = (nc + 3) & ~3;
-    const int Pb = nc4 / 4;
     int best = -1;
     double best_cost = 1e300;
     const int lpps[3] = {4, 8, 16};
-    for (int li = 0; li < 3; ++li) {
-        const int lpp = lpps[li];
-        const int nch = (nr4 + lpp - 1) / lpp;
-        if (nch > SVT_MAX_NCH) continue;
-        const int groups = NT / lpp;
-        const int per_group = (Pb + groups - 1) / groups;
-        const double cost = per_group * (nch + 1.5 + 0.5 * li);
-        if (cost < best_cost) {
-            best_cost = cost;
-            best = svt_make_cfg(lpp, nch);
+    for (int bs = 1; bs <= 2; ++bs) {
+        for (int li = 0; li < 3; ++li) {
+            const int lpp = lpps[li];
+            const int nch = (nr4 + lpp - 1) / lpp;
+            if (nch > (bs == 1 ? SVT_MAX_NCH : 4)) continue;
+            const int groups = NT / lpp;
+            const int nb = nc4 / bs;
+            const int pairs = nb / 2;
+            const int per_group = (pairs + groups - 1) / groups;
+            const int active = std::min(pairs, groups);
+            const double rot = 20.0 * nch + 30.0 + 4.0 * li;
+            const double round_instr = per_group * (bs * bs * rot + 4.0 * bs * nch) + 40.0;
+            // waves with work per SIMD: issue-bound when >= 2, latency-bound below
+            const double waves = std::max(1.0, active * (double)lpp / 64.0 / 4.0);
+            const double round_cycles = round_instr * 4.0 * std::max(waves, 2.0) / (bs == 2 ? 1.5 : 1.0);
+            // layouts whose rows exceed the register budget spill to scratch
+            const bool spills = NT > 256 && ((bs == 2 && nch > 2) || (bs == 1 && lpp == 16 && nch > 5));
+            const double cost = (nb - 1) * round_cycles * (spills ? 4.0 : 1.0);
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = svt_make_cfg(bs, lpp, nch);
+            }
         }
     }
     return best;
 }
 
-// LDS row stride: 4*LPP*NCH floats (every lane reads NCH chunks), bumped to
-// an odd multiple of 4*LPP so consecutive rows start in different bank
-// ranges.
+// LDS row stride: at least 4*LPP*NCH floats (every lane reads NCH chunks)
+// and chosen so that the lane groups served by one 256-byte LDS pass
+// (consecutive groups start BS rows apart) hit disjoint banks.
 int pick_ld(int cfg) {
-    const int unit = 4 * svt_lpp(cfg);
-    int k = svt_nch(cfg);
-    if ((k & 1) == 0) ++k;
-    return unit * k;
+    const int bs = svt_bs(cfg), lpp = svt_lpp(cfg), nch = svt_nch(cfg);
+    const int min_ld = 4 * lpp * nch;
+    const int group_bytes = 16 * lpp;
+    const int per_pass = std::max(1, 256 / group_bytes);
+    for (int ld = min_ld; ld < min_ld + 256; ld += 4) {
+        bool ok = true;
+        unsigned used = 0;
+        for (int gi = 0; gi < per_pass && ok; ++gi) {
+            const int off = (gi * bs * ld * 4) % 256;
+            if (off % group_bytes != 0) {
+                ok = false;
+                break;
+            }
+            const unsigned bit = 1u << (off / group_bytes);
+            if (used & bit) ok = false;
+            used |= bit;
+        }
+        if (ok) return ld;
+    }
+    return min_ld;
 }
 
 size_t lds_bytes(int nc, int ld, int tb) {

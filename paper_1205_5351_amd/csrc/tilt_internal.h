@@ -18,9 +18,10 @@ constexpr int LDS_LIMIT = 160 * 1024;
 // one-sided Jacobi orthogonalises (length nr = max(m, n)) are contiguous.
 enum Plane { PL_I = 0, PL_A = 1, PL_E = 2, PL_Y = 3, PL_R = 4, PL_M = 5, PL_Q = 6 };
 
-// Jacobi variants: cfg = (log2(LPP) - 2) * 16 + (NCH - 1) with LPP lanes per
-// block pair (4, 8 or 16) and NCH float4 chunks of each row held per lane
-// (1..8).
+// Jacobi variants: cfg = (BS - 1) * 64 + (log2(LPP) - 2) * 16 + (NCH - 1)
+// with BS rows per block (1 or 2), LPP lanes per block pair (4, 8 or 16)
+// and NCH float4 chunks of each row held per lane (1..8 for BS = 1, 1..4
+// for BS = 2: at most 64 floats of rows per lane).
 constexpr int SVT_MAX_NCH = 8;
 constexpr int SVT_MAX_ROWS = 256;  // rows of the Jacobi matrix (min(m, n) rounded up to 4)
 
@@ -70,10 +71,11 @@ struct SvtJob {
 };
 
 // LDS layout helpers (host and device).
-__host__ __device__ inline int svt_lpp(int cfg) { return 4 << (cfg >> 4); }
+__host__ __device__ inline int svt_bs(int cfg) { return (cfg >> 6) + 1; }
+__host__ __device__ inline int svt_lpp(int cfg) { return 4 << ((cfg >> 4) & 3); }
 __host__ __device__ inline int svt_nch(int cfg) { return (cfg & 15) + 1; }
-__host__ __device__ inline int svt_make_cfg(int lpp, int nch) {
-    return (lpp == 4 ? 0 : (lpp == 8 ? 1 : 2)) * 16 + (nch - 1);
+__host__ __device__ inline int svt_make_cfg(int bs, int lpp, int nch) {
+    return (bs - 1) * 64 + (lpp == 4 ? 0 : (lpp == 8 ? 1 : 2)) * 16 + (nch - 1);
 }
 
 // Kernel launchers (tilt_kernels.hip).

@@ -44,10 +44,16 @@ __device__ inline double wave_sum_d(double v) {
     return v;
 }
 
+// One LDS scratch buffer for every workgroup reduction (one slot per value
+// per wavefront).
+constexpr int RED_MAX = 24;
+__shared__ double tilt_red_scratch[RED_MAX * NWAVE];
+
 // Sum K values over the workgroup; every thread receives the same bits.
 template <int K>
 __device__ inline void block_sum_f(float (&v)[K]) {
-    __shared__ float red[K * NWAVE];
+    static_assert(K <= RED_MAX, "reduction too wide");
+    float* red = reinterpret_cast<float*>(tilt_red_scratch);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = wave_sum_f(v[k]);
@@ -56,19 +62,23 @@ __device__ inline void block_sum_f(float (&v)[K]) {
         for (int k = 0; k < K; ++k) red[k * NWAVE + w] = v[k];
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
+    // thread k combines the per-wave partials of value k (fixed order)
+    if ((int)threadIdx.x < K) {
+        const int k = threadIdx.x;
         float s = red[k * NWAVE];
-#pragma unroll
         for (int i = 1; i < NWAVE; ++i) s += red[k * NWAVE + i];
-        v[k] = s;
+        red[k * NWAVE] = s;
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = red[k * NWAVE];
     __syncthreads();
 }
 
 template <int K>
 __device__ inline void block_sum_d(double (&v)[K]) {
-    __shared__ double red[K * NWAVE];
+    static_assert(K <= RED_MAX, "reduction too wide");
+    double* red = tilt_red_scratch;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = wave_sum_d(v[k]);
@@ -77,27 +87,31 @@ __device__ inline void block_sum_d(double (&v)[K]) {
         for (int k = 0; k < K; ++k) red[k * NWAVE + w] = v[k];
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
+    // thread k combines the per-wave partials of value k (fixed order)
+    if ((int)threadIdx.x < K) {
+        const int k = threadIdx.x;
         double s = red[k * NWAVE];
-#pragma unroll
         for (int i = 1; i < NWAVE; ++i) s += red[k * NWAVE + i];
-        v[k] = s;
+        red[k * NWAVE] = s;
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = red[k * NWAVE];
     __syncthreads();
 }
 
 __device__ inline long long block_sum_ll(long long v) {
-    __shared__ long long red[NT];
-    red[threadIdx.x] = v;
+    long long* red = reinterpret_cast<long long*>(tilt_red_scratch);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[w] = v;
     __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    long long r = red[0];
+    long long s = 0;
+#pragma unroll
+    for (int i = 0; i < NWAVE; ++i) s += red[i];
     __syncthreads();
-    return r;
+    return s;
 }
 
 // Cross-lane moves inside a group of 4 or 8 consecutive lanes (DPP).
@@ -129,19 +143,18 @@ __device__ inline float group_sum(float v) {
 __device__ inline float4 f4(float a) { return make_float4(a, a, a, a); }
 
 // ---------------------------------------------------------------------------
-// One-sided Jacobi on the rows of B (LDS), blocks of two rows, round-robin
-// ordering of the blocks.
+// One-sided Jacobi on the rows of B (LDS), round-robin ordering of blocks
+// of BS rows (BS = 1: single rows, BS = 2: pairs of rows).
 //
 // Rows 0..nc4-1 (nc rounded up to a multiple of 4 with zero rows) with
 // stride ld; every row is zero-padded to 4*LPP*NCH floats so each of the
 // LPP lanes of a group reads exactly NCH float4 chunks (lane q owns chunks
-// q, q+LPP, ...).  Rows 2b and 2b+1 form block b.  Each round pairs every
-// block with another (circle method: the last block is fixed, pair k of
-// round r is (r+k, r-k) mod (nb-1)); a group owns one block pair, holds its
-// four rows in registers and applies, in order, the rotations of the pairs
-// (a1,b1), (a2,b2), (a1,b2), (a2,b1) -- plus (a1,a2), (b1,b2) in the first
-// round of a sweep -- so every pair of rows is met once per sweep while the
-// rows go through LDS once per round.  A pair is rotated when
+// q, q+LPP, ...).  Each round pairs every block with another (circle
+// method: the last block is fixed, pair k of round r is (r+k, r-k) mod
+// (nb-1)); a group owns one block pair, holds its 2 BS rows in registers
+// and rotates its cross pairs -- for BS = 2 in the order (a1,b1), (a2,b2),
+// (a1,b2), (a2,b1), plus (a1,a2), (b1,b2) in the first round of a sweep --
+// so every pair of rows is met once per sweep.  A pair is rotated when
 // |a.b| > tol ||a|| ||b||; the sweeps stop when a whole sweep rotates
 // nothing.  Squared row norms are recomputed exactly at the start of each
 // sweep and updated through each rotation (||a'||^2 = ||a||^2 - t a.b,
@@ -241,13 +254,25 @@ __device__ void row_norms(const float* B, int nrows, int ld, float* s2) {
 __shared__ float tilt_jacobi_nrm[SVT_MAX_ROWS];
 
 template <int LPP, int NCH>
+__device__ inline void load_row(const float* p, float4* x) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) x[c] = *reinterpret_cast<const float4*>(p + 4 * LPP * c);
+}
+
+template <int LPP, int NCH>
+__device__ inline void store_row(float* p, const float4* x) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) *reinterpret_cast<float4*>(p + 4 * LPP * c) = x[c];
+}
+
+template <int BS, int LPP, int NCH>
 __device__ void jacobi_rows(float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js) {
     float* nrm = tilt_jacobi_nrm;
     const int tid = threadIdx.x;
     const int g = tid / LPP, q = tid % LPP;
     constexpr int G = NT / LPP;
     const int nc4 = (nc + 3) & ~3;
-    const int nb = nc4 >> 1;          // blocks of two rows (even)
+    const int nb = nc4 / BS;          // blocks (even)
     const int Pb = nb >> 1, Nb = nb - 1;
     long long rots = 0;
     int sweeps = 0;
@@ -266,47 +291,57 @@ __device__ void jacobi_rows(float* B, int nc, int ld, float tol, int max_sweeps,
                     J = r - k;
                     if (J < 0) J += Nb;
                 }
-                float* p0 = B + (2 * I) * ld + 4 * q;
-                float* p1 = p0 + ld;
-                float* p2 = B + (2 * J) * ld + 4 * q;
-                float* p3 = p2 + ld;
-                float4 a1[NCH], a2[NCH], b1[NCH], b2[NCH];
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    a1[c] = *reinterpret_cast<const float4*>(p0 + 4 * LPP * c);
-                    a2[c] = *reinterpret_cast<const float4*>(p1 + 4 * LPP * c);
-                    b1[c] = *reinterpret_cast<const float4*>(p2 + 4 * LPP * c);
-                    b2[c] = *reinterpret_cast<const float4*>(p3 + 4 * LPP * c);
-                }
-                float na1 = nrm[2 * I], na2 = nrm[2 * I + 1], nb1 = nrm[2 * J], nb2 = nrm[2 * J + 1];
-                bool d0 = false, d1 = false, d2 = false, d3 = false, f;
-                if (r == 0) {
-                    f = rotate_rows<LPP, NCH>(a1, a2, na1, na2, tol);
-                    d0 |= f; d1 |= f; rots += f;
-                    f = rotate_rows<LPP, NCH>(b1, b2, nb1, nb2, tol);
-                    d2 |= f; d3 |= f; rots += f;
-                }
-                f = rotate_rows<LPP, NCH>(a1, b1, na1, nb1, tol);
-                d0 |= f; d2 |= f; rots += f;
-                f = rotate_rows<LPP, NCH>(a2, b2, na2, nb2, tol);
-                d1 |= f; d3 |= f; rots += f;
-                f = rotate_rows<LPP, NCH>(a1, b2, na1, nb2, tol);
-                d0 |= f; d3 |= f; rots += f;
-                f = rotate_rows<LPP, NCH>(a2, b1, na2, nb1, tol);
-                d1 |= f; d2 |= f; rots += f;
-                if (d0 | d1 | d2 | d3) any = 1;
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    if (d0) *reinterpret_cast<float4*>(p0 + 4 * LPP * c) = a1[c];
-                    if (d1) *reinterpret_cast<float4*>(p1 + 4 * LPP * c) = a2[c];
-                    if (d2) *reinterpret_cast<float4*>(p2 + 4 * LPP * c) = b1[c];
-                    if (d3) *reinterpret_cast<float4*>(p3 + 4 * LPP * c) = b2[c];
-                }
-                if (q == 0) {
-                    nrm[2 * I] = na1;
-                    nrm[2 * I + 1] = na2;
-                    nrm[2 * J] = nb1;
-                    nrm[2 * J + 1] = nb2;
+                float* pa = B + (BS * I) * ld + 4 * q;
+                float* pb = B + (BS * J) * ld + 4 * q;
+                if (BS == 1) {
+                    float4 a1[NCH], b1[NCH];
+                    load_row<LPP, NCH>(pa, a1);
+                    load_row<LPP, NCH>(pb, b1);
+                    float na1 = nrm[I], nb1 = nrm[J];
+                    const bool f = rotate_rows<LPP, NCH>(a1, b1, na1, nb1, tol);
+                    if (f) {
+                        any = 1;
+                        rots += 1;
+                        store_row<LPP, NCH>(pa, a1);
+                        store_row<LPP, NCH>(pb, b1);
+                        if (q == 0) {
+                            nrm[I] = na1;
+                            nrm[J] = nb1;
+                        }
+                    }
+                } else {
+                    float4 a1[NCH], a2[NCH], b1[NCH], b2[NCH];
+                    load_row<LPP, NCH>(pa, a1);
+                    load_row<LPP, NCH>(pa + ld, a2);
+                    load_row<LPP, NCH>(pb, b1);
+                    load_row<LPP, NCH>(pb + ld, b2);
+                    float na1 = nrm[2 * I], na2 = nrm[2 * I + 1], nb1 = nrm[2 * J], nb2 = nrm[2 * J + 1];
+                    bool d0 = false, d1 = false, d2 = false, d3 = false, f;
+                    if (r == 0) {
+                        f = rotate_rows<LPP, NCH>(a1, a2, na1, na2, tol);
+                        d0 |= f; d1 |= f; rots += f;
+                        f = rotate_rows<LPP, NCH>(b1, b2, nb1, nb2, tol);
+                        d2 |= f; d3 |= f; rots += f;
+                    }
+                    f = rotate_rows<LPP, NCH>(a1, b1, na1, nb1, tol);
+                    d0 |= f; d2 |= f; rots += f;
+                    f = rotate_rows<LPP, NCH>(a2, b2, na2, nb2, tol);
+                    d1 |= f; d3 |= f; rots += f;
+                    f = rotate_rows<LPP, NCH>(a1, b2, na1, nb2, tol);
+                    d0 |= f; d3 |= f; rots += f;
+                    f = rotate_rows<LPP, NCH>(a2, b1, na2, nb1, tol);
+                    d1 |= f; d2 |= f; rots += f;
+                    if (d0 | d1 | d2 | d3) any = 1;
+                    if (d0) store_row<LPP, NCH>(pa, a1);
+                    if (d1) store_row<LPP, NCH>(pa + ld, a2);
+                    if (d2) store_row<LPP, NCH>(pb, b1);
+                    if (d3) store_row<LPP, NCH>(pb + ld, b2);
+                    if (q == 0) {
+                        nrm[2 * I] = na1;
+                        nrm[2 * I + 1] = na2;
+                        nrm[2 * J] = nb1;
+                        nrm[2 * J + 1] = nb2;
+                    }
                 }
             }
             __syncthreads();
@@ -320,31 +355,34 @@ __device__ void jacobi_rows(float* B, int nc, int ld, float tol, int max_sweeps,
     js.rotations += block_sum_ll(q == 0 ? rots : 0);
 }
 
-template <int LPP, int NCH>
+template <int BS, int LPP, int NCH>
 __device__ void jacobi_svd_rows(float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js, float* s2) {
-    jacobi_rows<LPP, NCH>(B, nc, ld, tol, max_sweeps, js);
+    jacobi_rows<BS, LPP, NCH>(B, nc, ld, tol, max_sweeps, js);
     row_norms<LPP, NCH>(B, nc, ld, s2);
 }
 
-// cfg = (log2(LPP) - 2) * 16 + (NCH - 1)
-#define TILT_SVT_CASE(L, C)                                                   \
-    case ((L == 4 ? 0 : (L == 8 ? 1 : 2)) * 16 + (C - 1)):                     \
-        jacobi_svd_rows<L, C>(B, nc, ld, tol, max_sweeps, js, s2);             \
+// cfg = (BS - 1) * 64 + (log2(LPP) - 2) * 16 + (NCH - 1)
+#define TILT_SVT_CASE(S, L, C)                                                            \
+    case ((S - 1) * 64 + (L == 4 ? 0 : (L == 8 ? 1 : 2)) * 16 + (C - 1)):                  \
+        jacobi_svd_rows<S, L, C>(B, nc, ld, tol, max_sweeps, js, s2);                       \
         break;
+#define TILT_SVT_CASES8(S, L)                                                              \
+    TILT_SVT_CASE(S, L, 1) TILT_SVT_CASE(S, L, 2) TILT_SVT_CASE(S, L, 3) TILT_SVT_CASE(S, L, 4) \
+    TILT_SVT_CASE(S, L, 5) TILT_SVT_CASE(S, L, 6) TILT_SVT_CASE(S, L, 7) TILT_SVT_CASE(S, L, 8)
+#define TILT_SVT_CASES4(S, L) \
+    TILT_SVT_CASE(S, L, 1) TILT_SVT_CASE(S, L, 2) TILT_SVT_CASE(S, L, 3) TILT_SVT_CASE(S, L, 4)
 
 __device__ void jacobi_dispatch(int cfg, float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js,
                                 float* s2) {
     switch (cfg) {
-        TILT_SVT_CASE(4, 1) TILT_SVT_CASE(4, 2) TILT_SVT_CASE(4, 3) TILT_SVT_CASE(4, 4)
-        TILT_SVT_CASE(4, 5) TILT_SVT_CASE(4, 6) TILT_SVT_CASE(4, 7) TILT_SVT_CASE(4, 8)
-        TILT_SVT_CASE(8, 1) TILT_SVT_CASE(8, 2) TILT_SVT_CASE(8, 3) TILT_SVT_CASE(8, 4)
-        TILT_SVT_CASE(8, 5) TILT_SVT_CASE(8, 6) TILT_SVT_CASE(8, 7) TILT_SVT_CASE(8, 8)
-        TILT_SVT_CASE(16, 1) TILT_SVT_CASE(16, 2) TILT_SVT_CASE(16, 3) TILT_SVT_CASE(16, 4)
-        TILT_SVT_CASE(16, 5) TILT_SVT_CASE(16, 6) TILT_SVT_CASE(16, 7) TILT_SVT_CASE(16, 8)
+        TILT_SVT_CASES8(1, 4) TILT_SVT_CASES8(1, 8) TILT_SVT_CASES8(1, 16)
+        TILT_SVT_CASES4(2, 4) TILT_SVT_CASES4(2, 8) TILT_SVT_CASES4(2, 16)
         default:
             break;
     }
 }
+#undef TILT_SVT_CASES4
+#undef TILT_SVT_CASES8
 #undef TILT_SVT_CASE
 
 // ---------------------------------------------------------------------------
@@ -680,6 +718,11 @@ __device__ bool null_basis(const PatchDesc& d, const double* g, double* NQ) {
     return true;
 }
 
+// Packed upper-triangle index of (l, l2), l <= l2 < MAXPP (constant after
+// unrolling, so the Gram accumulators stay in registers).
+constexpr int NTRI = MAXPP * (MAXPP + 1) / 2;
+__host__ __device__ constexpr int tri(int l, int l2) { return l * MAXPP - l * (l - 1) / 2 + (l2 - l); }
+
 // Cholesky G = R^T R of a pp x pp SPD matrix (row-major, upper R).
 __device__ bool cholesky_upper(const double* G, int pp, double* R) {
     for (int k = 0; k < MAXPP * MAXPP; ++k) R[k] = 0.0;
@@ -791,9 +834,9 @@ __device__ void dev_setup(const PatchDesc& d, PatchState* st, const SolverParams
     const double inv_n3 = inv_n * inv_n * inv_n;
 
     // Pass B: normalise, J = J_raw/|I| - I (I^T J_raw)/|I|^3, J~ = J N_Q, Gram.
-    double gram[MAXPP * MAXPP];
+    double gram[NTRI];
 #pragma unroll
-    for (int k = 0; k < MAXPP * MAXPP; ++k) gram[k] = 0.0;
+    for (int k = 0; k < NTRI; ++k) gram[k] = 0.0;
     for (size_t e = tid; e < np; e += NT) {
         const int row = (int)(e / ldg), col = (int)(e - (size_t)row * ldg);
         if (col >= nr) {
@@ -827,15 +870,15 @@ __device__ void dev_setup(const PatchDesc& d, PatchState* st, const SolverParams
         for (int l = 0; l < MAXPP; ++l)
             #pragma unroll
             for (int l2 = 0; l2 < MAXPP; ++l2)
-                if (l <= l2 && l2 < pp) gram[l * MAXPP + l2] += jt[l] * jt[l2];
+                if (l <= l2 && l2 < pp) gram[tri(l, l2)] += jt[l] * jt[l2];
     }
-    block_sum_d<MAXPP * MAXPP>(gram);
+    block_sum_d<NTRI>(gram);
     if (tid == 0) {
         double G[MAXPP * MAXPP];
         for (int l = 0; l < MAXPP; ++l)
             for (int l2 = l; l2 < MAXPP; ++l2) {
-                G[l * MAXPP + l2] = gram[l * MAXPP + l2];
-                G[l2 * MAXPP + l] = gram[l * MAXPP + l2];
+                G[l * MAXPP + l2] = gram[tri(l, l2)];
+                G[l2 * MAXPP + l] = gram[tri(l, l2)];
             }
         sh_fail = cholesky_upper(G, pp, sh_R1) ? 0 : 1;
     }
@@ -852,7 +895,7 @@ __device__ void dev_setup(const PatchDesc& d, PatchState* st, const SolverParams
 
     // Pass C: second Gram of J~ R1^{-1} (Cholesky-QR, second pass).
 #pragma unroll
-    for (int k = 0; k < MAXPP * MAXPP; ++k) gram[k] = 0.0;
+    for (int k = 0; k < NTRI; ++k) gram[k] = 0.0;
     for (size_t e = tid; e < np; e += NT) {
         const int row = (int)(e / ldg), col = (int)(e - (size_t)row * ldg);
         if (col >= nr) continue;
@@ -864,15 +907,15 @@ __device__ void dev_setup(const PatchDesc& d, PatchState* st, const SolverParams
         for (int l = 0; l < MAXPP; ++l)
             #pragma unroll
             for (int l2 = 0; l2 < MAXPP; ++l2)
-                if (l <= l2 && l2 < pp) gram[l * MAXPP + l2] += x[l] * x[l2];
+                if (l <= l2 && l2 < pp) gram[tri(l, l2)] += x[l] * x[l2];
     }
-    block_sum_d<MAXPP * MAXPP>(gram);
+    block_sum_d<NTRI>(gram);
     if (tid == 0) {
         double G[MAXPP * MAXPP], R2[MAXPP * MAXPP];
         for (int l = 0; l < MAXPP; ++l)
             for (int l2 = l; l2 < MAXPP; ++l2) {
-                G[l * MAXPP + l2] = gram[l * MAXPP + l2];
-                G[l2 * MAXPP + l] = gram[l * MAXPP + l2];
+                G[l * MAXPP + l2] = gram[tri(l, l2)];
+                G[l2 * MAXPP + l] = gram[tri(l, l2)];
             }
         const bool ok = cholesky_upper(G, pp, R2);
         sh_fail = ok ? 0 : 1;
