@@ -49,6 +49,7 @@ struct DevBuf {
 // Shape-dependent launch configuration of the SVT for one patch.
 struct ShapeCfg {
     int nc, nr, ldg, colmajor, cfg, ld, tb;
+    int sb, nsb, ncp;  // tiled SVT (sb = 0: the whole matrix is held in LDS)
     size_t lds;
     size_t ws_floats;
 };
@@ -124,27 +125,69 @@ size_t lds_bytes(int nc, int ld, int tb) {
     return sizeof(float) * ((size_t)nc4 * ld + (size_t)tb * ld + (size_t)nc4 * tb + 3 * (size_t)nc4);
 }
 
+size_t lds_bytes_tiled(int sb, int ncp, int ld, int ldg, int tb) {
+    const size_t front = std::max((size_t)2 * sb * ld, (size_t)tb * ldg + (size_t)ncp * tb);
+    return sizeof(float) * (front + 3 * (size_t)ncp);
+}
+
+// The whole matrix in LDS when it fits; otherwise the tiled Jacobi with the
+// largest super-blocks whose staged pair fits (fewest block loads, most
+// lane groups busy per round; the pairs examined per sweep, about ncp^2,
+// do not depend on the block size).
 int shape_config(int m, int n, ShapeCfg* out) {
     ShapeCfg c;
     c.colmajor = m >= n ? 1 : 0;
     c.nc = std::min(m, n);
     c.nr = std::max(m, n);
     c.ldg = (c.nr + 3) & ~3;
-    if (((c.nc + 3) & ~3) > SVT_MAX_ROWS) return TILT_ERR_TOO_LARGE;
-    c.cfg = pick_svt_cfg(c.nc, c.ldg / 4);
-    if (c.cfg < 0) return TILT_ERR_TOO_LARGE;
-    c.ld = pick_ld(c.cfg);
-    c.tb = 32;
-    c.lds = lds_bytes(c.nc, c.ld, c.tb);
-    if (c.lds + kStaticLdsMargin > (size_t)LDS_LIMIT) {
-        c.tb = 16;
-        c.lds = lds_bytes(c.nc, c.ld, c.tb);
+    c.sb = c.nsb = c.ncp = 0;
+    const int nc4 = (c.nc + 3) & ~3;
+    const size_t budget = (size_t)LDS_LIMIT - kStaticLdsMargin;
+    if (nc4 <= SVT_MAX_ROWS) {
+        c.cfg = pick_svt_cfg(c.nc, c.ldg / 4);
+        if (c.cfg >= 0) {
+            c.ld = pick_ld(c.cfg);
+            for (int tb = 32; tb >= 16; tb -= 16) {
+                c.tb = tb;
+                c.lds = lds_bytes(c.nc, c.ld, c.tb);
+                if (c.lds <= budget) {
+                    c.ws_floats = (size_t)NPLANES * c.nc * c.ldg;
+                    *out = c;
+                    return TILT_OK;
+                }
+            }
+        }
     }
-    if (c.lds + kStaticLdsMargin > (size_t)LDS_LIMIT) return TILT_ERR_TOO_LARGE;
-    c.ws_floats = (size_t)NPLANES * c.nc * c.ldg;
-    *out = c;
-    return TILT_OK;
+    if (c.nr > SVT_MAX_COLS) return TILT_ERR_TOO_LARGE;
+    for (int nsb = 2; nsb <= SVT_MAX_TILED_ROWS / 4; nsb += 2) {
+        const int sb = (((nc4 + nsb - 1) / nsb) + 3) & ~3;
+        if (2 * sb > SVT_MAX_ROWS) continue;
+        const int ncp = nsb * sb;
+        if (ncp > SVT_MAX_TILED_ROWS) break;
+        const int cfg = pick_svt_cfg(2 * sb, c.ldg / 4);
+        if (cfg < 0) return TILT_ERR_TOO_LARGE;
+        const int ld = pick_ld(cfg);
+        for (int tb = 32; tb >= 16; tb -= 16) {
+            const size_t lds = lds_bytes_tiled(sb, ncp, ld, c.ldg, tb);
+            if (lds <= budget) {
+                c.cfg = cfg;
+                c.ld = ld;
+                c.tb = tb;
+                c.sb = sb;
+                c.nsb = nsb;
+                c.ncp = ncp;
+                c.lds = lds;
+                c.ws_floats = (size_t)NPLANES * c.nc * c.ldg + (size_t)ncp * c.ldg;
+                *out = c;
+                return TILT_OK;
+            }
+        }
+    }
+    return TILT_ERR_TOO_LARGE;
 }
+
+// Predicted relative cost of a solve (one-sided Jacobi work per iteration).
+double predicted_cost(const PatchDesc& d) { return (double)d.nc * d.nc * d.nr; }
 
 // ---------------------------------------------------------------------------
 // Transform normalisation (FP64).
@@ -273,7 +316,7 @@ int worse(int a, int b) {
 struct tilt_ctx {
     int device = 0;
     size_t budget = 0;
-    DevBuf descs, states, ws, queue, scratch, jobs, counters, img;
+    DevBuf descs, states, ws, queue, order, scratch, jobs, counters, img;
     double wall_rate_khz = 100000.0;  // device wall clock
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_kernel_ms = 0.0;
@@ -326,6 +369,9 @@ int prepare(const tilt_problem* probs, int count, const tilt_params* prm, tilt_r
         d.ld = sc.ld;
         d.svt_cfg = sc.cfg;
         d.tb = sc.tb;
+        d.sb = sc.sb;
+        d.nsb = sc.nsb;
+        d.ncp = sc.ncp;
         d.cx = nm.cx;
         d.cy = nm.cy;
         d.s = nm.s;
@@ -452,6 +498,14 @@ int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const 
             }
         } else {
             if (ctx->queue.reserve(256) != hipSuccess) return TILT_ERR_NOMEM;
+            if (ctx->order.reserve(sizeof(int) * nlive) != hipSuccess) return TILT_ERR_NOMEM;
+            // longest predicted solve first (stable: equal shapes keep their order)
+            std::vector<int> order(nlive);
+            for (int k = 0; k < nlive; ++k) order[k] = k;
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+                return predicted_cost(Q.descs[a]) > predicted_cost(Q.descs[b]);
+            });
+            HIP_TRY(hipMemcpyAsync(ctx->order.p, order.data(), sizeof(int) * nlive, hipMemcpyHostToDevice, stream));
             HIP_TRY(hipMemsetAsync(ctx->queue.p, 0, sizeof(int), stream));
             int ncu = 256;
             hipDeviceProp_t prop;
@@ -462,7 +516,8 @@ int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const 
             HIP_TRY(hipEventRecord(ctx->ev0, stream));
             HIP_TRY(launch_fused(reinterpret_cast<const PatchDesc*>(ctx->descs.p),
                                  reinterpret_cast<PatchState*>(ctx->states.p), sp, nlive,
-                                 reinterpret_cast<int*>(ctx->queue.p), grid, Q.max_lds, stream));
+                                 reinterpret_cast<const int*>(ctx->order.p), reinterpret_cast<int*>(ctx->queue.p),
+                                 grid, Q.max_lds, stream));
             HIP_TRY(hipEventRecord(ctx->ev1, stream));
         }
         std::vector<PatchState> out(nlive);
@@ -615,6 +670,7 @@ int tilt_ctx_destroy(tilt_ctx* ctx) {
     ctx->states.release();
     ctx->ws.release();
     ctx->queue.release();
+    ctx->order.release();
     ctx->scratch.release();
     ctx->jobs.release();
     ctx->counters.release();
@@ -739,13 +795,15 @@ int tilt_svt_batch(tilt_ctx* ctx, const float* M, float* A, float* sigma, int co
         jobs[i].pad = 0;
     }
     const size_t np = (size_t)sc.nc * sc.ldg;
+    const size_t per_job = 2 * np + (sc.sb > 0 ? (size_t)sc.ncp * sc.ldg : 0);
     if (ctx->jobs.reserve(sizeof(SvtJob) * count) != hipSuccess ||
         ctx->counters.reserve(sizeof(long long) * 4 * count) != hipSuccess ||
-        ctx->scratch.reserve(sizeof(float) * 2 * np * count) != hipSuccess)
+        ctx->scratch.reserve(sizeof(float) * per_job * count) != hipSuccess)
         return TILT_ERR_NOMEM;
     HIP_TRY(hipMemcpyAsync(ctx->jobs.p, jobs.data(), sizeof(SvtJob) * count, hipMemcpyHostToDevice, stream));
-    HIP_TRY(launch_svt_jobs(reinterpret_cast<const SvtJob*>(ctx->jobs.p), count, sc.cfg, sc.ld, sc.tb,
-                            prm->jacobi_tol, prm->max_sweeps, reinterpret_cast<long long*>(ctx->counters.p),
+    const SvtShape shape{sc.cfg, sc.ld, sc.tb, sc.sb, sc.nsb, sc.ncp};
+    HIP_TRY(launch_svt_jobs(reinterpret_cast<const SvtJob*>(ctx->jobs.p), count, shape, prm->jacobi_tol,
+                            prm->max_sweeps, reinterpret_cast<long long*>(ctx->counters.p),
                             reinterpret_cast<float*>(ctx->scratch.p), sc.lds, stream));
     std::vector<long long> cnt(4 * (size_t)count);
     HIP_TRY(hipMemcpyAsync(cnt.data(), ctx->counters.p, sizeof(long long) * 4 * count, hipMemcpyDeviceToHost,

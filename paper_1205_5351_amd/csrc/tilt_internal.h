@@ -23,7 +23,11 @@ enum Plane { PL_I = 0, PL_A = 1, PL_E = 2, PL_Y = 3, PL_R = 4, PL_M = 5, PL_Q = 
 // and NCH float4 chunks of each row held per lane (1..8 for BS = 1, 1..4
 // for BS = 2: at most 64 floats of rows per lane).
 constexpr int SVT_MAX_NCH = 8;
-constexpr int SVT_MAX_ROWS = 256;  // rows of the Jacobi matrix (min(m, n) rounded up to 4)
+constexpr int SVT_MAX_ROWS = 256;  // rows of the Jacobi matrix held in LDS at once
+// Tiled SVT (matrices larger than LDS): the rows live in a device plane and
+// are processed in pairs of super-blocks of sb rows staged through LDS.
+constexpr int SVT_MAX_TILED_ROWS = 768;  // rows of the working plane (min(m, n) rounded up to whole super-blocks)
+constexpr int SVT_MAX_COLS = 512;        // max(m, n): 16 lanes x 8 chunks x 4 floats
 
 struct PatchDesc {
     const float* image;
@@ -34,10 +38,13 @@ struct PatchDesc {
     int ld;                   // LDS row stride of the Jacobi matrix
     int svt_cfg;
     int tb;                   // rows per reconstruction block
-    int pad0;
+    int sb;                   // tiled SVT: rows per super-block (0: whole matrix in LDS)
+    int nsb;                  // tiled SVT: super-blocks (even)
+    int ncp;                  // tiled SVT: rows of the working plane (nsb * sb >= nc)
+    int pad0, pad1;
     double cx, cy, s;
     double lam;
-    float* ws;                // NPLANES planes
+    float* ws;                // NPLANES planes (+ one ncp x ldg working plane when tiled)
     float* A_out;             // m x n row-major (may be null)
     float* E_out;
 };
@@ -60,6 +67,12 @@ struct SolverParams {
     int pad;
 };
 
+// Launch shape of the SVT for one matrix shape.
+struct SvtShape {
+    int cfg, ld, tb;
+    int sb, nsb, ncp;
+};
+
 // Standalone SVT job (component entry point).
 struct SvtJob {
     const float* M;   // m x n row-major
@@ -80,7 +93,7 @@ __host__ __device__ inline int svt_make_cfg(int bs, int lpp, int nch) {
 
 // Kernel launchers (tilt_kernels.hip).
 hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count,
-                        int* queue, int grid, size_t lds, hipStream_t s);
+                        const int* order, int* queue, int grid, size_t lds, hipStream_t s);
 hipError_t launch_setup(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx,
                         size_t lds, hipStream_t s);
 hipError_t launch_svt(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx,
@@ -92,7 +105,7 @@ hipError_t launch_dtau(const PatchDesc* d, PatchState* st, const SolverParams& p
 hipError_t launch_finalize(const PatchDesc* d, PatchState* st, int idx, hipStream_t s);
 hipError_t launch_step1(const PatchDesc* d, PatchState* st, int count, float* I_out, float* J_out,
                         hipStream_t s);
-hipError_t launch_svt_jobs(const SvtJob* jobs, int count, int cfg, int ld, int tb, float tol,
+hipError_t launch_svt_jobs(const SvtJob* jobs, int count, const SvtShape& shape, float tol,
                            int max_sweeps, long long* counters, float* scratch, size_t lds, hipStream_t s);
 
 }  // namespace tilt

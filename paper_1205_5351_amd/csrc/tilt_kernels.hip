@@ -166,23 +166,33 @@ struct JacobiStats {
     long long sweeps, pairs, rotations;
 };
 
-// Rotation (c, s, t) that zeroes a.b for norms al = ||a||^2, be = ||b||^2
-// and ga = a.b (Hestenes / Rutishauser: t = sgn(z)/(|z| + sqrt(1 + z^2)),
-// z = (be - al)/(2 ga), c = 1/sqrt(1 + t^2), s = c t).  Hardware
-// reciprocal / square-root estimates give the angle to about one ulp; the
-// final scaling by 1 + (1 - c^2 - s^2)/2 removes, to first order, the
-// deviation of c^2 + s^2 from 1, so row norms do not drift over the many
-// rotations of a decomposition.
-__device__ inline void jacobi_rotation(float al, float be, float ga, float& cs, float& sn, float& tn) {
+// Rotation that zeroes a.b for norms al = ||a||^2, be = ||b||^2 and
+// ga = a.b (Hestenes / Rutishauser: t = sgn(z)/(|z| + sqrt(1 + z^2)),
+// z = (be - al)/(2 ga)), returned as t, s = sin = t/r and the half-angle
+// tangent tau = s/(1 + c) = t/(1 + r), r = sqrt(1 + t^2).  The rows are
+// then updated as a' = a - s (b + tau a), b' = b + s (a - tau b), whose
+// effective cosine 1 - s tau never rounds to 1 for small angles.  Any t
+// gives an orthogonal rotation, so t comes from hardware estimates; r, s
+// and tau each get one Newton correction (r from the residual of
+// r^2 = 1 + t^2 without rounding 1 + t^2) so that the transformation stays
+// orthogonal to within rounding with no systematic shrink or growth of the
+// rows over the thousands of rotations of a decomposition.
+__device__ inline void jacobi_rotation(float al, float be, float ga, float& sn, float& ta, float& tn) {
     const float zeta = (be - al) * __builtin_amdgcn_rcpf(2.0f * ga);
     const float root = __builtin_amdgcn_sqrtf(fmaf(zeta, zeta, 1.0f));
     const float t = copysignf(__builtin_amdgcn_rcpf(fabsf(zeta) + root), zeta);
-    float c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.0f));
-    float s = c * t;
-    const float d = fmaf(-c, c, fmaf(-s, s, 1.0f));
-    const float corr = fmaf(0.5f, d, 1.0f);
-    cs = c * corr;
-    sn = s * corr;
+    float r = __builtin_amdgcn_sqrtf(fmaf(t, t, 1.0f));
+    const float res = fmaf(t, t, fmaf(-r, r, 1.0f));
+    r = fmaf(0.5f * res, __builtin_amdgcn_rcpf(r), r);
+    const float rr = __builtin_amdgcn_rcpf(r);
+    float s = t * rr;
+    s = fmaf(fmaf(-s, r, t), rr, s);
+    const float onep = 1.0f + r;
+    const float ro = __builtin_amdgcn_rcpf(onep);
+    float h = t * ro;
+    h = fmaf(fmaf(-h, onep, t), ro, h);
+    sn = s;
+    ta = h;
     tn = t;
 }
 
@@ -212,19 +222,19 @@ template <int LPP, int NCH>
 __device__ inline bool rotate_rows(float4* x, float4* y, float& nx, float& ny, float tol) {
     const float ga = group_dot<LPP, NCH>(x, y);
     if (!(fabsf(ga) > tol * (__builtin_amdgcn_sqrtf(nx) * __builtin_amdgcn_sqrtf(ny)))) return false;
-    float cs, sn, t;
-    jacobi_rotation(nx, ny, ga, cs, sn, t);
+    float sn, ta, t;
+    jacobi_rotation(nx, ny, ga, sn, ta, t);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         const float4 a = x[c], b = y[c];
-        x[c].x = fmaf(cs, a.x, -(sn * b.x));
-        x[c].y = fmaf(cs, a.y, -(sn * b.y));
-        x[c].z = fmaf(cs, a.z, -(sn * b.z));
-        x[c].w = fmaf(cs, a.w, -(sn * b.w));
-        y[c].x = fmaf(sn, a.x, cs * b.x);
-        y[c].y = fmaf(sn, a.y, cs * b.y);
-        y[c].z = fmaf(sn, a.z, cs * b.z);
-        y[c].w = fmaf(sn, a.w, cs * b.w);
+        x[c].x = fmaf(-sn, fmaf(ta, a.x, b.x), a.x);
+        x[c].y = fmaf(-sn, fmaf(ta, a.y, b.y), a.y);
+        x[c].z = fmaf(-sn, fmaf(ta, a.z, b.z), a.z);
+        x[c].w = fmaf(-sn, fmaf(ta, a.w, b.w), a.w);
+        y[c].x = fmaf(sn, fmaf(-ta, b.x, a.x), b.x);
+        y[c].y = fmaf(sn, fmaf(-ta, b.y, a.y), b.y);
+        y[c].z = fmaf(sn, fmaf(-ta, b.z, a.z), b.z);
+        y[c].w = fmaf(sn, fmaf(-ta, b.w, a.w), b.w);
     }
     // Tracked norms; clamped at 0 (cancellation can only make a small norm
     // inaccurate until the exact recomputation at the next sweep start).
@@ -265,8 +275,9 @@ __device__ inline void store_row(float* p, const float4* x) {
     for (int c = 0; c < NCH; ++c) *reinterpret_cast<float4*>(p + 4 * LPP * c) = x[c];
 }
 
+// Returns 1 (uniform over the workgroup) if any pair was rotated.
 template <int BS, int LPP, int NCH>
-__device__ void jacobi_rows(float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js) {
+__device__ int jacobi_rows(float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js) {
     float* nrm = tilt_jacobi_nrm;
     const int tid = threadIdx.x;
     const int g = tid / LPP, q = tid % LPP;
@@ -275,7 +286,7 @@ __device__ void jacobi_rows(float* B, int nc, int ld, float tol, int max_sweeps,
     const int nb = nc4 / BS;          // blocks (even)
     const int Pb = nb >> 1, Nb = nb - 1;
     long long rots = 0;
-    int sweeps = 0;
+    int sweeps = 0, rotated = 0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
         row_norms<LPP, NCH>(B, nc4, ld, nrm);
         int any = 0;
@@ -347,12 +358,15 @@ __device__ void jacobi_rows(float* B, int nc, int ld, float tol, int max_sweeps,
             __syncthreads();
         }
         ++sweeps;
-        if (!__syncthreads_or(any)) break;
+        const int a = __syncthreads_or(any);
+        rotated |= a;
+        if (!a) break;
     }
     // every pair of the nc4 rows is examined once per sweep
     js.sweeps += sweeps;
     js.pairs += (long long)sweeps * ((long long)nc4 * (nc4 - 1) / 2);
     js.rotations += block_sum_ll(q == 0 ? rots : 0);
+    return rotated;
 }
 
 template <int BS, int LPP, int NCH>
@@ -384,6 +398,118 @@ __device__ void jacobi_dispatch(int cfg, float* B, int nc, int ld, float tol, in
 #undef TILT_SVT_CASES4
 #undef TILT_SVT_CASES8
 #undef TILT_SVT_CASE
+
+// One sweep over all pairs of the nrows rows of B (LDS); 1 if any rotated.
+#define TILT_SWEEP_CASE(S, L, C)                                                          \
+    case ((S - 1) * 64 + (L == 4 ? 0 : (L == 8 ? 1 : 2)) * 16 + (C - 1)):                  \
+        return jacobi_rows<S, L, C>(B, nrows, ld, tol, 1, js);
+#define TILT_SWEEP_CASES8(S, L)                                                                    \
+    TILT_SWEEP_CASE(S, L, 1) TILT_SWEEP_CASE(S, L, 2) TILT_SWEEP_CASE(S, L, 3) TILT_SWEEP_CASE(S, L, 4) \
+    TILT_SWEEP_CASE(S, L, 5) TILT_SWEEP_CASE(S, L, 6) TILT_SWEEP_CASE(S, L, 7) TILT_SWEEP_CASE(S, L, 8)
+#define TILT_SWEEP_CASES4(S, L) \
+    TILT_SWEEP_CASE(S, L, 1) TILT_SWEEP_CASE(S, L, 2) TILT_SWEEP_CASE(S, L, 3) TILT_SWEEP_CASE(S, L, 4)
+
+__device__ int jacobi_sweep_dispatch(int cfg, float* B, int nrows, int ld, float tol, JacobiStats& js) {
+    switch (cfg) {
+        TILT_SWEEP_CASES8(1, 4) TILT_SWEEP_CASES8(1, 8) TILT_SWEEP_CASES8(1, 16)
+        TILT_SWEEP_CASES4(2, 4) TILT_SWEEP_CASES4(2, 8) TILT_SWEEP_CASES4(2, 16)
+        default:
+            break;
+    }
+    return 0;
+}
+#undef TILT_SWEEP_CASES4
+#undef TILT_SWEEP_CASES8
+#undef TILT_SWEEP_CASE
+
+// ---------------------------------------------------------------------------
+// Tiled one-sided Jacobi for matrices that do not fit in LDS.
+//
+// The ncp rows (nc real rows, then zero rows) live in a device plane with
+// stride ldg and are split into nsb super-blocks of sb rows.  A sweep runs
+// the circle method over super-blocks; for each super-block pair both
+// blocks are staged into LDS as one 2 sb-row matrix, one full Jacobi sweep
+// over its rows is applied (cross pairs and the pairs inside each block),
+// and the blocks are written back if anything rotated.  Every pair of rows
+// is examined at least once per sweep; a sweep in which no pair rotates
+// leaves every row unchanged, so all pairs were tested against the final
+// rows, and the iteration stops.  Zero rows are never rotated (a.b = 0).
+// ---------------------------------------------------------------------------
+
+__device__ void clear_lds_padding(float* B, int nc, int ldg, int ld);
+
+__device__ void load_block(const float* Bg, int r0, int cnt, int ldg, float* mini, int dst, int ld) {
+    const int nr4 = ldg >> 2;
+    for (int idx = threadIdx.x; idx < cnt * nr4; idx += NT) {
+        const int row = idx / nr4, c = idx - row * nr4;
+        *reinterpret_cast<float4*>(mini + (dst + row) * ld + 4 * c) =
+            reinterpret_cast<const float4*>(Bg + (size_t)(r0 + row) * ldg)[c];
+    }
+}
+
+__device__ void store_block(float* Bg, int r0, int cnt, int ldg, const float* mini, int src, int ld) {
+    const int nr4 = ldg >> 2;
+    for (int idx = threadIdx.x; idx < cnt * nr4; idx += NT) {
+        const int row = idx / nr4, c = idx - row * nr4;
+        reinterpret_cast<float4*>(Bg + (size_t)(r0 + row) * ldg)[c] =
+            *reinterpret_cast<const float4*>(mini + (src + row) * ld + 4 * c);
+    }
+}
+
+__device__ void jacobi_tiled(int cfg, float* Bg, int sb, int nsb, int ldg, int ld, float* mini, float tol,
+                             int max_sweeps, JacobiStats& js) {
+    const int Nb = nsb - 1, Pb = nsb >> 1;
+    const long long sweeps0 = js.sweeps;
+    int sweeps = 0;
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+        int any = 0;
+        for (int r = 0; r < Nb; ++r) {
+            for (int k = 0; k < Pb; ++k) {
+                int I, J;
+                if (k == 0) {
+                    I = Nb;
+                    J = r;
+                } else {
+                    I = r + k;
+                    if (I >= Nb) I -= Nb;
+                    J = r - k;
+                    if (J < 0) J += Nb;
+                }
+                load_block(Bg, I * sb, sb, ldg, mini, 0, ld);
+                load_block(Bg, J * sb, sb, ldg, mini, sb, ld);
+                clear_lds_padding(mini, 2 * sb, ldg, ld);
+                __syncthreads();
+                const int rot = jacobi_sweep_dispatch(cfg, mini, 2 * sb, ld, tol, js);
+                if (rot) {
+                    store_block(Bg, I * sb, sb, ldg, mini, 0, ld);
+                    store_block(Bg, J * sb, sb, ldg, mini, sb, ld);
+                }
+                any |= rot;
+                __syncthreads();
+            }
+        }
+        ++sweeps;
+        if (!any) break;
+    }
+    js.sweeps = sweeps0 + sweeps;
+}
+
+// Squared norms of rows 0..nrows-1 of a device plane (stride ldg) into s2.
+__device__ void row_norms_global(const float* X, int nrows, int ldg, float* s2) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nr4 = ldg >> 2;
+    for (int j = wv; j < nrows; j += NWAVE) {
+        const float4* pr = reinterpret_cast<const float4*>(X + (size_t)j * ldg);
+        float acc = 0.f;
+        for (int c = lane; c < nr4; c += 64) {
+            const float4 v = pr[c];
+            acc = dot4(v, v, acc);
+        }
+        acc = wave_sum_f(acc);
+        if (lane == 0) s2[j] = acc;
+    }
+    __syncthreads();
+}
 
 // ---------------------------------------------------------------------------
 // Singular value shrinkage from the orthogonalised rows.
@@ -550,6 +676,28 @@ __device__ inline SvtLds carve_lds(float* base, int nc, int ld, int tb) {
     return L;
 }
 
+// Tiled SVT: the staged super-block pair (2 sb rows of stride ld) and the
+// reconstruction blocks (tb rows of stride ldg, ncp x tb products) share
+// the front of LDS; the per-row arrays follow.
+__device__ inline SvtLds carve_lds_tiled(float* base, int sb, int ncp, int ld, int ldg, int tb) {
+    SvtLds L;
+    L.B = base;
+    L.xblk = base;
+    L.cwt = L.xblk + tb * ldg;
+    const int front = max(2 * sb * ld, tb * ldg + ncp * tb);
+    L.s2 = base + front;
+    L.w = L.s2 + ncp;
+    L.act = reinterpret_cast<int*>(L.w + ncp);
+    return L;
+}
+
+// Singular values (squared, into L.s2, rows 0..nc-1) of the X-layout plane
+// X: the Jacobi runs on LDS (rows in L.B) or, tiled, on the working plane
+// Bg, which then holds the orthogonalised rows.
+__device__ void svd_rows(const PatchDesc& d, const float* X, float* Bg, const SvtLds& L, float tol, int max_sweeps,
+                         JacobiStats& js);
+
+
 // Zero the LDS padding of the Jacobi matrix: columns [ldg, ld) of every
 // row and the extra rows nc..nc4-1 (nc rounded up to a multiple of 4).
 __device__ void clear_lds_padding(float* B, int nc, int ldg, int ld) {
@@ -577,6 +725,29 @@ __device__ void load_rows_lds(const float* Xg, int nc, int ldg, int ld, float* B
     }
     clear_lds_padding(B, nc, ldg, ld);
     __syncthreads();
+}
+
+__device__ void svd_rows(const PatchDesc& d, const float* X, float* Bg, const SvtLds& L, float tol, int max_sweeps,
+                         JacobiStats& js) {
+    if (d.sb > 0) {
+        const int nr4 = d.ldg >> 2;
+        for (int idx = threadIdx.x; idx < d.ncp * nr4; idx += NT) {
+            const int row = idx / nr4, c = idx - row * nr4;
+            float4 v = f4(0.f);
+            if (row < d.nc) v = reinterpret_cast<const float4*>(X + (size_t)row * d.ldg)[c];
+            reinterpret_cast<float4*>(Bg + (size_t)row * d.ldg)[c] = v;
+        }
+        __syncthreads();
+        jacobi_tiled(d.svt_cfg, Bg, d.sb, d.nsb, d.ldg, d.ld, L.B, tol, max_sweeps, js);
+        row_norms_global(Bg, d.nc, d.ldg, L.s2);
+    } else {
+        load_rows_lds(X, d.nc, d.ldg, d.ld, L.B);
+        jacobi_dispatch(d.svt_cfg, L.B, d.nc, d.ld, tol, max_sweeps, js, L.s2);
+    }
+}
+
+__device__ inline SvtLds carve_for(const PatchDesc& d, float* lds) {
+    return d.sb > 0 ? carve_lds_tiled(lds, d.sb, d.ncp, d.ld, d.ldg, d.tb) : carve_lds(lds, d.nc, d.ld, d.tb);
 }
 
 // ---------------------------------------------------------------------------
@@ -993,10 +1164,9 @@ __device__ void dev_setup(const PatchDesc& d, PatchState* st, const SolverParams
     // mu_0 = 1.25 / ||I||_2 from the Jacobi singular values of I.
     double mu0 = prm.mu0;
     if (!(mu0 > 0.0)) {
-        SvtLds L = carve_lds(lds, nc, d.ld, d.tb);
-        load_rows_lds(I, nc, ldg, d.ld, L.B);
+        const SvtLds L = carve_for(d, lds);
         JacobiStats js{0, 0, 0};
-        jacobi_dispatch(d.svt_cfg, L.B, nc, d.ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
+        svd_rows(d, I, d.ws + NPLANES * np, L, prm.jacobi_tol, prm.max_sweeps, js);
         __shared__ float sh_smax;
         if (tid == 0) {
             float mx = 0.f;
@@ -1039,7 +1209,9 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
     float* M = d.ws + PL_M * np;
     const double mu = st->mu;
     const float inv_mu = (float)(1.0 / mu);
-    SvtLds L = carve_lds(lds, nc, ld, d.tb);
+    const bool tiled = d.sb > 0;
+    float* Bg = d.ws + NPLANES * np;
+    const SvtLds L = carve_for(d, lds);
 
     // M_k = A_k - J~perp(A_k + E_k - I) - Y_k/mu_k, with R = J~perp(A_k + E_k - I).
     for (int idx = tid; idx < nc * nr4; idx += NT) {
@@ -1054,20 +1226,25 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
         mm.z = fmaf(-y.z, inv_mu, a.z - r.z);
         mm.w = fmaf(-y.w, inv_mu, a.w - r.w);
         *reinterpret_cast<float4*>(M + o) = mm;
-        *reinterpret_cast<float4*>(L.B + row * ld + 4 * c) = mm;
+        if (!tiled) *reinterpret_cast<float4*>(L.B + row * ld + 4 * c) = mm;
     }
-    clear_lds_padding(L.B, nc, ldg, ld);
-    __syncthreads();
-
     JacobiStats js{0, 0, 0};
-    jacobi_dispatch(d.svt_cfg, L.B, nc, ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
+    if (tiled) {
+        __syncthreads();
+        svd_rows(d, M, Bg, L, prm.jacobi_tol, prm.max_sweeps, js);
+    } else {
+        clear_lds_padding(L.B, nc, ldg, ld);
+        __syncthreads();
+        jacobi_dispatch(d.svt_cfg, L.B, nc, ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
+    }
 
     const float eps = (float)(1.0 / mu);
     int k;
     double nuc;
     shrink_weights(L.s2, nc, eps, L.w, L.act, &k, &nuc);
     float dA[1];
-    dA[0] = reconstruct(L.B, ld, M, A, nc, nr4, ldg, L.w, L.act, k, d.tb, L.xblk, L.cwt, true);
+    dA[0] = tiled ? reconstruct(Bg, ldg, M, A, nc, nr4, ldg, L.w, L.act, k, d.tb, L.xblk, L.cwt, true)
+                  : reconstruct(L.B, ld, M, A, nc, nr4, ldg, L.w, L.act, k, d.tb, L.xblk, L.cwt, true);
     block_sum_f<1>(dA);
     if (tid == 0) {
         st->dA2 = (double)dA[0];
@@ -1332,12 +1509,19 @@ __device__ void solve_patch(const PatchDesc& d, PatchState* st, const SolverPara
     if (threadIdx.x == 0) st->t_end = (long long)wall_clock64();
 }
 
+// Persistent solver: each workgroup takes the next patch from the queue
+// (in the order given by `order`, longest predicted solve first) until the
+// queue is exhausted.
 __global__ void __launch_bounds__(NT) k_fused(const PatchDesc* __restrict__ descs, PatchState* states,
-                                               SolverParams prm, int count, int* queue) {
+                                               SolverParams prm, int count, const int* __restrict__ order,
+                                               int* queue) {
     __shared__ int sh_idx;
     float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
     for (;;) {
-        if (threadIdx.x == 0) sh_idx = atomicAdd(queue, 1);
+        if (threadIdx.x == 0) {
+            const int q = atomicAdd(queue, 1);
+            sh_idx = q < count ? order[q] : count;
+        }
         __syncthreads();
         const int idx = sh_idx;
         __syncthreads();
@@ -1416,8 +1600,8 @@ __global__ void __launch_bounds__(NT) k_step1(const PatchDesc* descs, PatchState
 
 // Component kernel: batched singular value shrinkage of independent
 // matrices (the A-update of Eq. A_1 on its own).
-__global__ void __launch_bounds__(NT) k_svt_jobs(const SvtJob* jobs, int cfg, int ld, int tb, float tol,
-                                                 int max_sweeps, long long* counters, float* scratch) {
+__global__ void __launch_bounds__(NT) k_svt_jobs(const SvtJob* jobs, SvtShape shape, float tol, int max_sweeps,
+                                                 long long* counters, float* scratch) {
     const SvtJob jb = jobs[blockIdx.x];
     float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
     const int tid = threadIdx.x;
@@ -1427,8 +1611,20 @@ __global__ void __launch_bounds__(NT) k_svt_jobs(const SvtJob* jobs, int cfg, in
     const int ldg = (nr + 3) & ~3;
     const int nr4 = ldg >> 2;
     const size_t np = (size_t)nc * ldg;
-    float* X = scratch + (size_t)blockIdx.x * 2 * np;
+    const size_t per_job = 2 * np + (shape.sb > 0 ? (size_t)shape.ncp * ldg : 0);
+    float* X = scratch + (size_t)blockIdx.x * per_job;
     float* AX = X + np;
+    float* Bg = AX + np;
+    PatchDesc d{};
+    d.nc = nc;
+    d.nr = nr;
+    d.ldg = ldg;
+    d.ld = shape.ld;
+    d.svt_cfg = shape.cfg;
+    d.tb = shape.tb;
+    d.sb = shape.sb;
+    d.nsb = shape.nsb;
+    d.ncp = shape.ncp;
     for (size_t e = tid; e < np; e += NT) {
         const int row = (int)(e / ldg), col = (int)(e - (size_t)row * ldg);
         float v = 0.f;
@@ -1437,17 +1633,20 @@ __global__ void __launch_bounds__(NT) k_svt_jobs(const SvtJob* jobs, int cfg, in
         AX[e] = 0.f;
     }
     __syncthreads();
-    SvtLds L = carve_lds(lds, nc, ld, tb);
-    load_rows_lds(X, nc, ldg, ld, L.B);
+    const SvtLds L = carve_for(d, lds);
     JacobiStats js{0, 0, 0};
-    jacobi_dispatch(cfg, L.B, nc, ld, tol, max_sweeps, js, L.s2);
+    svd_rows(d, X, Bg, L, tol, max_sweeps, js);
     int k;
     double nuc;
     shrink_weights(L.s2, nc, jb.eps, L.w, L.act, &k, &nuc);
     if (jb.sigma) {
         for (int j = tid; j < nc; j += NT) jb.sigma[j] = sqrtf(L.s2[j]);
     }
-    reconstruct(L.B, ld, X, AX, nc, nr4, ldg, L.w, L.act, k, tb, L.xblk, L.cwt, false);
+    if (d.sb > 0)
+        reconstruct(Bg, ldg, X, AX, nc, nr4, ldg, L.w, L.act, k, d.tb, L.xblk, L.cwt, false);
+    else
+        reconstruct(L.B, d.ld, X, AX, nc, nr4, ldg, L.w, L.act, k, d.tb, L.xblk, L.cwt, false);
+    __syncthreads();
     for (size_t e = tid; e < np; e += NT) {
         const int row = (int)(e / ldg), col = (int)(e - (size_t)row * ldg);
         if (col >= nr) continue;
@@ -1479,11 +1678,11 @@ static hipError_t set_lds(const void* fn, size_t lds) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, int* queue,
-                        int grid, size_t lds, hipStream_t s) {
+hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, const int* order,
+                        int* queue, int grid, size_t lds, hipStream_t s) {
     hipError_t e = set_lds((const void*)k_fused, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(NT), lds, s, d, st, prm, count, queue);
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(NT), lds, s, d, st, prm, count, order, queue);
     return hipGetLastError();
 }
 
@@ -1524,11 +1723,11 @@ hipError_t launch_step1(const PatchDesc* d, PatchState* st, int count, float* I_
     return hipGetLastError();
 }
 
-hipError_t launch_svt_jobs(const SvtJob* jobs, int count, int cfg, int ld, int tb, float tol, int max_sweeps,
+hipError_t launch_svt_jobs(const SvtJob* jobs, int count, const SvtShape& shape, float tol, int max_sweeps,
                            long long* counters, float* scratch, size_t lds, hipStream_t s) {
     hipError_t e = set_lds((const void*)k_svt_jobs, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_svt_jobs, dim3(count), dim3(NT), lds, s, jobs, cfg, ld, tb, tol, max_sweeps, counters,
+    hipLaunchKernelGGL(k_svt_jobs, dim3(count), dim3(NT), lds, s, jobs, shape, tol, max_sweeps, counters,
                        scratch);
     return hipGetLastError();
 }

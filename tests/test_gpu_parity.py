@@ -31,9 +31,13 @@ pytestmark = pytest.mark.gpu
 
 SVT_SHAPES = [(8, 8), (17, 33), (33, 17), (50, 50), (64, 64), (100, 100), (101, 99), (90, 40), (40, 130),
               (128, 128), (3, 70), (160, 96)]
+# Matrices beyond LDS (tiled Jacobi over super-blocks of rows), ragged and
+# maximum sizes, plus a long-row shape that still fits in LDS.
+SVT_SHAPES_LARGE = [(180, 180), (200, 200), (256, 256), (300, 200), (131, 257), (400, 400), (512, 512),
+                    (40, 400)]
 
 
-@pytest.mark.parametrize("m,n", SVT_SHAPES)
+@pytest.mark.parametrize("m,n", SVT_SHAPES + SVT_SHAPES_LARGE)
 def test_svt_matches_oracle(tilt, ctx, device, m, n):
     import torch
 
@@ -159,7 +163,7 @@ def test_fixed_iterations_match_oracle(tilt, ctx, device, cfg, idx, outer, inner
 # ---------------------------------------------------------------------------
 
 
-@pytest.mark.parametrize("cfg,idx", [(0, 1), (0, 2), (0, 6), (1, 0), (2, 2), (2, 5), (2, 8)])
+@pytest.mark.parametrize("cfg,idx", [(0, 1), (0, 2), (0, 6), (1, 0), (2, 2), (2, 5), (2, 8), (2, 18)])
 def test_full_solve_matches_oracle(tilt, ctx, device, cfg, idx):
     """Converged solves: relative tau error <= 1e-4, objective within 1e-4,
     same numerical rank."""
@@ -250,12 +254,14 @@ def test_error_statuses(tilt, ctx, device):
     assert res[0]["status"] == tilt.tilt.TILT_ERR_TOO_LARGE
 
 
-@pytest.mark.parametrize("m,n,model", [(9, 9, 6), (12, 60, 8), (61, 13, 8), (7, 100, 6)])
+@pytest.mark.parametrize("m,n,model", [(9, 9, 6), (12, 60, 8), (61, 13, 8), (7, 100, 6), (200, 236, 6),
+                                       (257, 181, 8), (400, 400, 8)])
 def test_ragged_shapes_fixed_iters(tilt, ctx, device, m, n, model):
     rng = ts.patch_rng(99, m * 1000 + n)
     p = ts.make_patch(rng, m=m, n=n, height=2 * max(m, n) + 8, width=2 * max(m, n) + 8, rank=2, model=model,
                       corruption=0.05, theta_deg=5, skew=0.05)
-    tp = tilt.default_params(fixed_iters=1, max_outer=2, max_inner=10, lam=p.lam)
+    inner = 10 if m * n <= 40000 else 4
+    tp = tilt.default_params(fixed_iters=1, max_outer=2, max_inner=inner, lam=p.lam)
     _, res = solve_on_device(tilt, ctx, [p], device, tp)
     r = res[0]
     ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
