@@ -75,6 +75,13 @@ typedef struct {
     int svt_mode;       /* 0: cold one-sided Jacobi SVT every iteration       */
     float jacobi_tol;   /* rotate a pair when |a.b| > tol ||a|| ||b||; 1e-6   */
     int max_sweeps;     /* Jacobi sweep cap, default 40                       */
+    int pyramid_levels; /* 1 (default): solve the window as given.  L in 2..4:
+                           solve coarse to fine over L levels; level l has the
+                           image blurred by the binomial [1 4 6 4 1]/16
+                           (borders clamped) and sampled at every second pixel
+                           l times, a ceil(m/2^l) x ceil(n/2^l) window, and
+                           starts cold from the coarser level's transform
+                           conjugated by diag(2, 2, 1).  Not in the paper.     */
 } tilt_params;
 
 /* One window of one image. */
@@ -175,6 +182,37 @@ int tilt_solve_batch_plain(tilt_ctx* ctx, const tilt_problem* probs, int count,
                            const tilt_params* prm, tilt_result* results, void* hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Serving (continuous batching).  Requests are admitted while earlier ones
+ * are still running: a persistent kernel (one workgroup per compute unit)
+ * claims each published request as soon as a workgroup is free, so a
+ * request never waits for a batch to fill or drain.  Workspaces come from a
+ * device arena owned by the context (min(budget, 8 GiB)); a request that
+ * does not fit waits on the host until an earlier one is polled.
+ *
+ * tilt_submit: validates and queues one problem (image: DEVICE pointer that
+ * must stay valid until the request is finished).  A_out / E_out: DEVICE
+ * pointers (m x n row-major) or NULL, written when the request finishes.
+ * On success *ticket identifies the request.  Argument errors (including
+ * TILT_ERR_TOO_LARGE) are returned here and no ticket is issued.
+ *
+ * tilt_poll: TILT_PENDING while the request runs; otherwise fills *res
+ * (A/E fields untouched), releases the request and returns its status.
+ * Polling also admits queued requests and restarts the kernel when it has
+ * exited after being idle (100 ms without work), so a caller waiting for
+ * results must keep polling.  TILT_ERR_NOT_FOUND for unknown or already
+ * collected tickets.
+ *
+ * tilt_serve_stop: waits until every published request has finished,
+ * then stops the kernel (requests still queued on the host stay queued;
+ * the next submit or poll restarts it).  tilt_ctx_destroy stops it too.
+ * Calls on one context are serialised by a lock.
+ * ---------------------------------------------------------------------- */
+int tilt_submit(tilt_ctx* ctx, const tilt_problem* prob, const tilt_params* prm, float* A_out, float* E_out,
+                unsigned long long* ticket);
+int tilt_poll(tilt_ctx* ctx, unsigned long long ticket, tilt_result* res);
+int tilt_serve_stop(tilt_ctx* ctx);
+
+/* ------------------------------------------------------------------------
  * Components of the hot path, exposed for checking and benchmarking.
  * All pointers are DEVICE pointers unless stated; calls synchronise the
  * stream before returning.
@@ -200,6 +238,12 @@ int tilt_svt_batch(tilt_ctx* ctx, const float* M, float* A, float* sigma, int co
  * problems must share m, n and model. */
 int tilt_warp_jacobian(tilt_ctx* ctx, const tilt_problem* probs, const double* taus, int count,
                        float* I_out, float* J_out, void* hip_stream);
+
+/* Pyramid levels 1..levels-1 of one image (DEVICE pointers), as used when
+ * pyramid_levels = levels: level l (ceil(H/2^l) x ceil(W/2^l), row-major,
+ * contiguous) follows level l-1 in `out`.  levels in 2..4. */
+int tilt_pyramid(tilt_ctx* ctx, const float* image, int height, int width, long long row_stride, float* out,
+                 int levels, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,7 @@
 // Host side of the C interface declared in include/tilt.h: argument
-// validation, transform normalisation (FP64), device workspace, and the
-// plain (step-by-step) and batched (fused persistent) drivers.
+// validation, transform normalisation (FP64), request planning (pyramid
+// levels, shapes, workspace layout), and the plain (step-by-step) and
+// batched (fused persistent) drivers.
 
 #include <hip/hip_runtime.h>
 
@@ -12,47 +13,33 @@
 #include <vector>
 
 #include "tilt.h"
+#include "tilt_host.h"
 #include "tilt_internal.h"
 
 using namespace tilt;
 
-namespace {
+namespace tilt {
+namespace host {
 
-constexpr int kStaticLdsMargin = 8 * 1024;  // static __shared__ use of the kernels (checked at launch)
-
-// ---------------------------------------------------------------------------
-// Device buffer that grows on demand.
-// ---------------------------------------------------------------------------
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    hipError_t reserve(size_t need) {
-        if (need <= bytes) return hipSuccess;
-        if (p) (void)hipFree(p);
+hipError_t DevBuf::reserve(size_t need) {
+    if (need <= bytes) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipMalloc(&p, need);
+    if (e != hipSuccess) {
         p = nullptr;
-        bytes = 0;
-        hipError_t e = hipMalloc(&p, need);
-        if (e != hipSuccess) {
-            p = nullptr;
-            return e;
-        }
-        bytes = need;
-        return hipSuccess;
+        return e;
     }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-};
+    bytes = need;
+    return hipSuccess;
+}
 
-// Shape-dependent launch configuration of the SVT for one patch.
-struct ShapeCfg {
-    int nc, nr, ldg, colmajor, cfg, ld, tb;
-    int sb, nsb, ncp;  // tiled SVT (sb = 0: the whole matrix is held in LDS)
-    size_t lds;
-    size_t ws_floats;
-};
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
 
 // Jacobi layout for a matrix of nc rows of nr4 float4 chunks: rows per
 // block (BS), lanes per block pair (LPP) and chunks per lane (NCH).  The
@@ -189,13 +176,7 @@ int shape_config(int m, int n, ShapeCfg* out) {
 // Predicted relative cost of a solve (one-sided Jacobi work per iteration).
 double predicted_cost(const PatchDesc& d) { return (double)d.nc * d.nc * d.nr; }
 
-// ---------------------------------------------------------------------------
-// Transform normalisation (FP64).
-// ---------------------------------------------------------------------------
-struct Norm {
-    double cx, cy, s;
-    double tau[MAXP];
-};
+namespace {
 
 bool finite9(const double* h) {
     for (int k = 0; k < 9; ++k)
@@ -203,59 +184,28 @@ bool finite9(const double* h) {
     return true;
 }
 
-int normalise(const double* Hpx, int m, int n, int model, Norm* out) {
+}  // namespace
+
+// Pixel homography -> scaled coordinates of the window and the p entries of
+// tau.  Affine transforms must have the last row (0, 0, 1).
+int normalise_window(const double* Hpx, int m, int n, int model, double* geo, double* tau) {
     if (!finite9(Hpx) || Hpx[8] == 0.0) return TILT_ERR_ARG;
     double H[9];
     for (int k = 0; k < 9; ++k) H[k] = Hpx[k] / Hpx[8];
     const double scale = std::fabs(H[0]) + std::fabs(H[1]) + std::fabs(H[3]) + std::fabs(H[4]);
     if (model == TILT_AFFINE && (std::fabs(H[6]) > 1e-12 * (1.0 + scale) || std::fabs(H[7]) > 1e-12 * (1.0 + scale)))
         return TILT_ERR_ARG;
-    const double s = std::max(m, n) / 2.0;
-    const double cx = H[2], cy = H[5];
-    // Hn = Timg^{-1} H diag(s, s, 1), Timg = [[s, 0, cx], [0, s, cy], [0, 0, 1]]
     double Hn[9];
-    for (int j = 0; j < 3; ++j) {
-        const double sc = (j < 2) ? s : 1.0;
-        Hn[0 * 3 + j] = (H[0 * 3 + j] - cx * H[2 * 3 + j]) / s * sc;
-        Hn[1 * 3 + j] = (H[1 * 3 + j] - cy * H[2 * 3 + j]) / s * sc;
-        Hn[2 * 3 + j] = H[2 * 3 + j] * sc;
-    }
-    const double h22n = Hn[8];
-    for (int k = 0; k < 9; ++k) Hn[k] /= h22n;
-    out->cx = cx;
-    out->cy = cy;
-    out->s = s;
-    out->tau[0] = Hn[0];
-    out->tau[1] = Hn[1];
-    out->tau[2] = Hn[2];
-    out->tau[3] = Hn[3];
-    out->tau[4] = Hn[4];
-    out->tau[5] = Hn[5];
-    out->tau[6] = model == TILT_PROJECTIVE ? Hn[6] : 0.0;
-    out->tau[7] = model == TILT_PROJECTIVE ? Hn[7] : 0.0;
-    const double det = Hn[0] * (Hn[4] * Hn[8] - Hn[5] * Hn[7]) - Hn[1] * (Hn[3] * Hn[8] - Hn[5] * Hn[6]) +
-                       Hn[2] * (Hn[3] * Hn[7] - Hn[4] * Hn[6]);
-    if (!(std::fabs(det) > 1e-12)) return TILT_ERR_ARG;
+    if (!normalise_h(H, m, n, geo, Hn)) return TILT_ERR_ARG;
+    for (int k = 0; k < 6; ++k) tau[k] = Hn[k];
+    tau[6] = model == TILT_PROJECTIVE ? Hn[6] : 0.0;
+    tau[7] = model == TILT_PROJECTIVE ? Hn[7] : 0.0;
     return TILT_OK;
 }
 
-void denormalise(const double* tau, int model, double cx, double cy, double s, double* Hpx) {
-    double Hn[9] = {tau[0], tau[1], tau[2], tau[3], tau[4], tau[5], 0.0, 0.0, 1.0};
-    if (model == TILT_PROJECTIVE) {
-        Hn[6] = tau[6];
-        Hn[7] = tau[7];
-    }
-    // H = Timg Hn diag(1/s, 1/s, 1)
-    double H[9];
-    for (int j = 0; j < 3; ++j) {
-        const double sc = (j < 2) ? 1.0 / s : 1.0;
-        H[0 * 3 + j] = (s * Hn[0 * 3 + j] + cx * Hn[2 * 3 + j]) * sc;
-        H[1 * 3 + j] = (s * Hn[1 * 3 + j] + cy * Hn[2 * 3 + j]) * sc;
-        H[2 * 3 + j] = Hn[2 * 3 + j] * sc;
-    }
-    const double h22 = H[8];
-    for (int k = 0; k < 9; ++k) Hpx[k] = H[k] / h22;
-}
+namespace {
+thread_local char g_last_error[512] = "";
+}  // namespace
 
 int validate_params(const tilt_params* p) {
     if (!p) return TILT_ERR_ARG;
@@ -264,6 +214,7 @@ int validate_params(const tilt_params* p) {
     if (p->max_inner < 1 || p->max_outer < 1 || p->max_sweeps < 1) return TILT_ERR_ARG;
     if (!(p->jacobi_tol > 0.f) || !(p->jacobi_tol < 1.f)) return TILT_ERR_ARG;
     if (p->svt_mode != 0) return TILT_ERR_ARG;
+    if (p->pyramid_levels < 0 || p->pyramid_levels > MAX_LEVELS) return TILT_ERR_ARG;
     if (!std::isfinite(p->lambda) || !std::isfinite(p->mu0)) return TILT_ERR_ARG;
     return TILT_OK;
 }
@@ -294,13 +245,13 @@ SolverParams to_solver(const tilt_params* p) {
     return s;
 }
 
-thread_local char g_last_error[512] = "";
-
 int record_hip_error(hipError_t e, const char* what, int line) {
-    std::snprintf(g_last_error, sizeof(g_last_error), "%s (%s) at tilt_api.cpp:%d: %s", hipGetErrorName(e),
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s (%s) at line %d: %s", hipGetErrorName(e),
                   hipGetErrorString(e), line, what);
     return TILT_ERR_DEVICE;
 }
+
+const char* last_error_text() { return g_last_error; }
 
 int worse(int a, int b) {
     // errors (negative) dominate warnings (positive) dominate OK
@@ -308,96 +259,93 @@ int worse(int a, int b) {
     return std::max(a, b);
 }
 
-}  // namespace
-
-// ---------------------------------------------------------------------------
-// Context
-// ---------------------------------------------------------------------------
-struct tilt_ctx {
-    int device = 0;
-    size_t budget = 0;
-    DevBuf descs, states, ws, queue, order, scratch, jobs, counters, img;
-    double wall_rate_khz = 100000.0;  // device wall clock
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    double last_kernel_ms = 0.0;
-};
-
-namespace {
-
-struct Prepared {
-    std::vector<PatchDesc> descs;
-    std::vector<PatchState> states;
-    std::vector<Norm> norms;
-    std::vector<int> status;  // per-patch preparation status
-    size_t max_lds = 0;
-    size_t ws_floats = 0;
-};
-
-// Build descriptors; images are device pointers; A/E outputs device pointers.
-int prepare(const tilt_problem* probs, int count, const tilt_params* prm, tilt_result* results, Prepared* P,
-            bool device_outputs) {
-    P->descs.resize(count);
-    P->states.assign(count, PatchState{});
-    P->norms.resize(count);
-    P->status.assign(count, TILT_OK);
-    size_t off = 0;
-    int worst = TILT_OK;
-    for (int i = 0; i < count; ++i) {
-        const tilt_problem& pr = probs[i];
-        int st = validate_problem(&pr);
-        ShapeCfg sc{};
-        if (st == TILT_OK) st = shape_config(pr.m, pr.n, &sc);
-        Norm nm{};
-        if (st == TILT_OK) st = normalise(pr.tau0, pr.m, pr.n, pr.model, &nm);
-        P->status[i] = st;
-        worst = worse(worst, st);
-        PatchDesc& d = P->descs[i];
-        std::memset(&d, 0, sizeof(d));
-        if (st != TILT_OK) continue;
-        d.image = pr.image;
-        d.stride = pr.row_stride;
-        d.H = pr.height;
-        d.W = pr.width;
-        d.m = pr.m;
-        d.n = pr.n;
+// Level l of a request: window ceil(m/2^l) x ceil(n/2^l) in an image of
+// ceil(H/2^l) x ceil(W/2^l) pixels.  The workspace holds the solver planes
+// (sized for the largest level) followed by the images of levels 1.. .
+int plan_request(const tilt_problem& pr, const tilt_params* prm, float* A_out, float* E_out, RequestPlan* out) {
+    int st = validate_problem(&pr);
+    if (st != TILT_OK) return st;
+    const int levels = std::max(1, prm->pyramid_levels);
+    RequestPlan& P = *out;
+    std::memset(&P, 0, sizeof(P));
+    P.levels = levels;
+    ShapeCfg sc[MAX_LEVELS];
+    int hl[MAX_LEVELS], wl[MAX_LEVELS], ml[MAX_LEVELS], nl[MAX_LEVELS];
+    size_t planes = 0;
+    for (int l = 0; l < levels; ++l) {
+        const int f = 1 << l;
+        ml[l] = (pr.m + f - 1) / f;
+        nl[l] = (pr.n + f - 1) / f;
+        hl[l] = l == 0 ? pr.height : (hl[l - 1] + 1) / 2;
+        wl[l] = l == 0 ? pr.width : (wl[l - 1] + 1) / 2;
+        if (ml[l] < 2 || nl[l] < 2 || hl[l] < 2 || wl[l] < 2) return TILT_ERR_ARG;
+        st = shape_config(ml[l], nl[l], &sc[l]);
+        if (st != TILT_OK) return st;
+        planes = std::max(planes, sc[l].ws_floats);
+        P.lds = std::max(P.lds, sc[l].lds);
+    }
+    size_t off = (planes + 63) & ~(size_t)63;
+    size_t img_off[MAX_LEVELS] = {0};
+    for (int l = 1; l < levels; ++l) {
+        img_off[l] = off;
+        off += ((size_t)hl[l] * wl[l] + 63) & ~(size_t)63;
+    }
+    P.ws_floats = off;
+    // initial transform at the coarsest level
+    double H[9];
+    for (int k = 0; k < 9; ++k) H[k] = pr.tau0[k];
+    for (int l = 1; l < levels; ++l) to_coarser_h(H);
+    PatchState& s0 = P.init;
+    st = normalise_window(H, ml[levels - 1], nl[levels - 1], pr.model, s0.geo, s0.tau);
+    if (st != TILT_OK) return st;
+    for (int l = 0; l < levels; ++l) {
+        PatchDesc& d = P.d[l];
+        d.image = l == 0 ? pr.image : reinterpret_cast<const float*>(img_off[l] * sizeof(float));
+        d.stride = l == 0 ? pr.row_stride : wl[l];
+        d.H = hl[l];
+        d.W = wl[l];
+        d.m = ml[l];
+        d.n = nl[l];
         d.model = pr.model;
         d.pp = pr.model - 3;
-        d.nc = sc.nc;
-        d.nr = sc.nr;
-        d.ldg = sc.ldg;
-        d.colmajor = sc.colmajor;
-        d.ld = sc.ld;
-        d.svt_cfg = sc.cfg;
-        d.tb = sc.tb;
-        d.sb = sc.sb;
-        d.nsb = sc.nsb;
-        d.ncp = sc.ncp;
-        d.cx = nm.cx;
-        d.cy = nm.cy;
-        d.s = nm.s;
-        d.lam = prm->lambda > 0 ? prm->lambda : 1.0 / std::sqrt((double)std::max(pr.m, pr.n));
-        d.ws = reinterpret_cast<float*>(off);  // offset, rebased after allocation
-        off += sc.ws_floats;
-        d.A_out = device_outputs && results ? results[i].A : nullptr;
-        d.E_out = device_outputs && results ? results[i].E : nullptr;
-        PatchState& s = P->states[i];
-        for (int k = 0; k < MAXP; ++k) s.tau[k] = nm.tau[k];
-        P->norms[i] = nm;
-        P->max_lds = std::max(P->max_lds, sc.lds);
+        d.nc = sc[l].nc;
+        d.nr = sc[l].nr;
+        d.ldg = sc[l].ldg;
+        d.colmajor = sc[l].colmajor;
+        d.ld = sc[l].ld;
+        d.svt_cfg = sc[l].cfg;
+        d.tb = sc[l].tb;
+        d.sb = sc[l].sb;
+        d.nsb = sc[l].nsb;
+        d.ncp = sc[l].ncp;
+        d.cx = s0.geo[0];
+        d.cy = s0.geo[1];
+        d.s = s0.geo[2];
+        d.lam = prm->lambda > 0 ? prm->lambda : 1.0 / std::sqrt((double)std::max(ml[l], nl[l]));
+        d.ws = nullptr;
+        d.A_out = l == 0 ? A_out : nullptr;
+        d.E_out = l == 0 ? E_out : nullptr;
     }
-    P->ws_floats = off;
-    return worst;
+    return TILT_OK;
 }
 
-void fill_result(const PatchDesc& d, const PatchState& s, const Norm& nm, int prep_status, tilt_result* r,
-                 double rate_khz, long long t0) {
-    if (prep_status != TILT_OK) {
-        r->status = prep_status;
-        return;
+void rebase_plan(RequestPlan* plan, float* ws) {
+    for (int l = 0; l < plan->levels; ++l) {
+        PatchDesc& d = plan->d[l];
+        d.ws = ws;
+        if (l > 0) d.image = ws + reinterpret_cast<size_t>(d.image) / sizeof(float);
     }
+}
+
+void fill_result(const PatchDesc& d0, const PatchState& s, tilt_result* r, double rate_khz, long long t0) {
     r->solve_ms = (double)(s.t_end - s.t_begin) / rate_khz;
     r->done_ms = (double)(s.t_end - t0) / rate_khz;
-    denormalise(s.tau, d.model, nm.cx, nm.cy, nm.s, r->tau);
+    double Hn[9] = {s.tau[0], s.tau[1], s.tau[2], s.tau[3], s.tau[4], s.tau[5], 0.0, 0.0, 1.0};
+    if (d0.model == TILT_PROJECTIVE) {
+        Hn[6] = s.tau[6];
+        Hn[7] = s.tau[7];
+    }
+    denormalise_h(Hn, s.geo, r->tau);
     r->outer_iters = s.outer;
     r->inner_iters_total = s.inner_total;
     r->svt_rank = s.svt_rank;
@@ -415,53 +363,108 @@ void fill_result(const PatchDesc& d, const PatchState& s, const Norm& nm, int pr
     r->counters.recon_rows = s.recon_rows;
 }
 
-#define HIP_TRY(x)                                                  \
-    do {                                                            \
-        hipError_t _e = (x);                                        \
-        if (_e != hipSuccess) return record_hip_error(_e, #x, __LINE__); \
-    } while (0)
+}  // namespace host
+}  // namespace tilt
 
-int upload(tilt_ctx* ctx, Prepared& P, hipStream_t stream) {
-    const int count = (int)P.descs.size();
-    if (P.ws_floats * sizeof(float) > ctx->budget) return TILT_ERR_NOMEM;
-    if (ctx->ws.reserve(std::max<size_t>(P.ws_floats * sizeof(float), 256)) != hipSuccess) return TILT_ERR_NOMEM;
-    if (ctx->descs.reserve(sizeof(PatchDesc) * count) != hipSuccess) return TILT_ERR_NOMEM;
+using namespace tilt::host;
+
+namespace {
+
+struct Prepared {
+    int levels = 1;
+    std::vector<RequestPlan> plans;
+    std::vector<int> status;  // per-problem preparation status
+    size_t max_lds = 0;
+    size_t ws_floats = 0;
+};
+
+// Plan every problem; images and A/E outputs are device pointers.
+int prepare(const tilt_problem* probs, int count, const tilt_params* prm, tilt_result* results, Prepared* P) {
+    P->levels = std::max(1, prm->pyramid_levels);
+    P->plans.resize(count);
+    P->status.assign(count, TILT_OK);
+    int worst = TILT_OK;
+    for (int i = 0; i < count; ++i) {
+        const int st = plan_request(probs[i], prm, results ? results[i].A : nullptr, results ? results[i].E : nullptr,
+                                    &P->plans[i]);
+        P->status[i] = st;
+        worst = worse(worst, st);
+    }
+    return worst;
+}
+
+// Device descriptors (levels per request, request-major), states and
+// workspace for the live requests.
+int upload(tilt_ctx* ctx, const Prepared& P, const std::vector<int>& live, std::vector<RequestPlan>* plans,
+           hipStream_t stream) {
+    const int count = (int)live.size();
+    const int L = P.levels;
+    size_t total = 0;
+    std::vector<size_t> off(count);
+    for (int k = 0; k < count; ++k) {
+        off[k] = total;
+        total += (P.plans[live[k]].ws_floats + 63) & ~(size_t)63;
+    }
+    if (total * sizeof(float) > ctx->budget) return TILT_ERR_NOMEM;
+    if (ctx->ws.reserve(std::max<size_t>(total * sizeof(float), 256)) != hipSuccess) return TILT_ERR_NOMEM;
+    if (ctx->descs.reserve(sizeof(PatchDesc) * L * count) != hipSuccess) return TILT_ERR_NOMEM;
     if (ctx->states.reserve(sizeof(PatchState) * count) != hipSuccess) return TILT_ERR_NOMEM;
     float* base = reinterpret_cast<float*>(ctx->ws.p);
-    for (auto& d : P.descs) d.ws = base + reinterpret_cast<size_t>(d.ws);
-    HIP_TRY(hipMemcpyAsync(ctx->descs.p, P.descs.data(), sizeof(PatchDesc) * count, hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipMemcpyAsync(ctx->states.p, P.states.data(), sizeof(PatchState) * count, hipMemcpyHostToDevice,
-                           stream));
+    std::vector<PatchDesc> descs((size_t)L * count);
+    std::vector<PatchState> states(count);
+    plans->resize(count);
+    for (int k = 0; k < count; ++k) {
+        RequestPlan pl = P.plans[live[k]];
+        rebase_plan(&pl, base + off[k]);
+        for (int l = 0; l < L; ++l) descs[(size_t)k * L + l] = pl.d[l];
+        states[k] = pl.init;
+        (*plans)[k] = pl;
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->descs.p, descs.data(), sizeof(PatchDesc) * L * count, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(ctx->states.p, states.data(), sizeof(PatchState) * count, hipMemcpyHostToDevice, stream));
     return TILT_OK;
 }
 
-// Host-driven loop over the step kernels for patch idx (mirrors solve_patch).
-int run_plain_patch(tilt_ctx* ctx, const Prepared& P, const SolverParams& sp, int idx, hipStream_t stream) {
-    const PatchDesc* dd = reinterpret_cast<const PatchDesc*>(ctx->descs.p);
-    PatchState* ds = reinterpret_cast<PatchState*>(ctx->states.p);
-    const size_t lds = P.max_lds;
+// Host-driven loop over the step kernels for request k (mirrors
+// solve_request on the device: pyramid, then levels coarse to fine).
+int run_plain_request(tilt_ctx* ctx, size_t lds, const SolverParams& sp, int L, int k, hipStream_t stream) {
+    const PatchDesc* dl = reinterpret_cast<const PatchDesc*>(ctx->descs.p) + (size_t)k * L;
+    PatchState* ds = reinterpret_cast<PatchState*>(ctx->states.p) + k;
     PatchState hs;
     auto fetch = [&]() -> int {
-        HIP_TRY(hipMemcpyAsync(&hs, ds + idx, sizeof(PatchState), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(&hs, ds, sizeof(PatchState), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         return TILT_OK;
     };
-    for (;;) {
-        HIP_TRY(launch_setup(dd, ds, sp, idx, lds, stream));
-        if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
-        if (hs.status < 0) break;
-        for (;;) {
-            HIP_TRY(launch_svt(dd, ds, sp, idx, lds, stream));
-            HIP_TRY(launch_update(dd, ds, sp, idx, stream));
+    HIP_TRY(launch_level_begin(dl + L - 1, ds, 1, stream));
+    if (L > 1) HIP_TRY(launch_pyramid_build(dl, L, stream));
+    for (int l = L - 1; l >= 0; --l) {
+        const PatchDesc* d = dl + l;
+        if (l < L - 1) {
             if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
-            if (hs.done_inner) break;
+            if (hs.status < 0) break;
+            HIP_TRY(launch_level_begin(d, ds, 0, stream));
+            if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
+            if (hs.status < 0) break;
         }
-        if (hs.status < 0) break;
-        HIP_TRY(launch_dtau(dd, ds, sp, idx, stream));
-        if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
-        if (hs.done_outer) break;
+        for (;;) {
+            HIP_TRY(launch_setup(d, ds, sp, lds, stream));
+            if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
+            if (hs.status < 0) break;
+            for (;;) {
+                HIP_TRY(launch_svt(d, ds, sp, lds, stream));
+                HIP_TRY(launch_update(d, ds, sp, stream));
+                if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
+                if (hs.done_inner) break;
+            }
+            if (hs.status < 0) break;
+            HIP_TRY(launch_dtau(d, ds, sp, stream));
+            if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
+            if (hs.done_outer) break;
+        }
+        HIP_TRY(launch_finalize(d, ds, 0, stream));
     }
-    HIP_TRY(launch_finalize(dd, ds, idx, stream));
+    HIP_TRY(launch_mark_end(ds, stream));
     return TILT_OK;
 }
 
@@ -474,26 +477,25 @@ int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const 
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     Prepared P;
-    int worst = prepare(probs, count, prm, results, &P, true);
-    // Only valid patches are sent to the device.
+    int worst = prepare(probs, count, prm, results, &P);
+    // Only valid problems are sent to the device.
     std::vector<int> live;
+    size_t max_lds = 0;
     for (int i = 0; i < count; ++i)
-        if (P.status[i] == TILT_OK) live.push_back(i);
-    if (!live.empty()) {
-        Prepared Q;
-        Q.max_lds = P.max_lds;
-        Q.ws_floats = P.ws_floats;
-        for (int i : live) {
-            Q.descs.push_back(P.descs[i]);
-            Q.states.push_back(P.states[i]);
+        if (P.status[i] == TILT_OK) {
+            live.push_back(i);
+            max_lds = std::max(max_lds, P.plans[i].lds);
         }
-        int u = upload(ctx, Q, stream);
+    if (!live.empty()) {
+        std::vector<RequestPlan> plans;
+        int u = upload(ctx, P, live, &plans, stream);
         if (u != TILT_OK) return u;
         const SolverParams sp = to_solver(prm);
         const int nlive = (int)live.size();
+        const int L = P.levels;
         if (plain) {
             for (int k = 0; k < nlive; ++k) {
-                int r = run_plain_patch(ctx, Q, sp, k, stream);
+                int r = run_plain_request(ctx, max_lds, sp, L, k, stream);
                 if (r != TILT_OK) return r;
             }
         } else {
@@ -503,21 +505,17 @@ int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const 
             std::vector<int> order(nlive);
             for (int k = 0; k < nlive; ++k) order[k] = k;
             std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-                return predicted_cost(Q.descs[a]) > predicted_cost(Q.descs[b]);
+                return predicted_cost(plans[a].d[0]) > predicted_cost(plans[b].d[0]);
             });
             HIP_TRY(hipMemcpyAsync(ctx->order.p, order.data(), sizeof(int) * nlive, hipMemcpyHostToDevice, stream));
             HIP_TRY(hipMemsetAsync(ctx->queue.p, 0, sizeof(int), stream));
-            int ncu = 256;
-            hipDeviceProp_t prop;
-            if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
-                ncu = prop.multiProcessorCount;
-            const int per_cu = std::max<int>(1, (int)(LDS_LIMIT / (Q.max_lds + kStaticLdsMargin)));
-            const int grid = std::max(1, std::min(nlive, ncu * std::min(per_cu, 2)));
+            const int per_cu = std::max<int>(1, (int)(LDS_LIMIT / (max_lds + kStaticLdsMargin)));
+            const int grid = std::max(1, std::min(nlive, ctx->num_cus * std::min(per_cu, 2)));
             HIP_TRY(hipEventRecord(ctx->ev0, stream));
             HIP_TRY(launch_fused(reinterpret_cast<const PatchDesc*>(ctx->descs.p),
-                                 reinterpret_cast<PatchState*>(ctx->states.p), sp, nlive,
+                                 reinterpret_cast<PatchState*>(ctx->states.p), sp, nlive, L,
                                  reinterpret_cast<const int*>(ctx->order.p), reinterpret_cast<int*>(ctx->queue.p),
-                                 grid, Q.max_lds, stream));
+                                 grid, max_lds, stream));
             HIP_TRY(hipEventRecord(ctx->ev1, stream));
         }
         std::vector<PatchState> out(nlive);
@@ -533,7 +531,7 @@ int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const 
         for (int k = 1; k < nlive; ++k) t0 = std::min(t0, out[k].t_begin);
         for (int k = 0; k < nlive; ++k) {
             const int i = live[k];
-            fill_result(P.descs[i], out[k], P.norms[i], TILT_OK, &results[i], ctx->wall_rate_khz, t0);
+            fill_result(plans[k].d[0], out[k], &results[i], ctx->wall_rate_khz, t0);
             worst = worse(worst, results[i].status);
         }
     }
@@ -565,6 +563,7 @@ void tilt_default_params(tilt_params* p) {
     p->svt_mode = 0;
     p->jacobi_tol = 1e-6f;
     p->max_sweeps = 40;
+    p->pyramid_levels = 1;
 }
 
 const char* tilt_status_string(int s) {
@@ -585,7 +584,7 @@ const char* tilt_status_string(int s) {
 
 const char* tilt_version(void) { return "tilt-mi355x 0.1 (gfx950)"; }
 
-const char* tilt_last_error(void) { return g_last_error; }
+const char* tilt_last_error(void) { return tilt::host::last_error_text(); }
 
 int tilt_tau_from_quad(const double quad[8], int m, int n, int model, double tau_out[9]) {
     if (!quad || !tau_out || m < 2 || n < 2) return TILT_ERR_ARG;
@@ -651,6 +650,9 @@ int tilt_ctx_create(tilt_ctx** ctx, int device, size_t hbm_budget_bytes) {
     if (!c) return TILT_ERR_NOMEM;
     c->device = device;
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : free_b / 2;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cus = prop.multiProcessorCount;
     int rate = 0;
     if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate > 0)
         c->wall_rate_khz = (double)rate;
@@ -665,6 +667,8 @@ int tilt_ctx_create(tilt_ctx** ctx, int device, size_t hbm_budget_bytes) {
 int tilt_ctx_destroy(tilt_ctx* ctx) {
     if (!ctx) return TILT_ERR_ARG;
     (void)hipSetDevice(ctx->device);
+    if (ctx->serve) serve_release(ctx->serve);
+    ctx->serve = nullptr;
     (void)hipDeviceSynchronize();
     ctx->descs.release();
     ctx->states.release();
@@ -835,26 +839,26 @@ int tilt_warp_jacobian(tilt_ctx* ctx, const tilt_problem* probs, const double* t
         int st = validate_problem(&pr);
         if (st != TILT_OK) return st;
         if (pr.m != m || pr.n != n || pr.model != model) return TILT_ERR_ARG;
-        Norm ref{}, cur{};
-        st = normalise(pr.tau0, m, n, model, &ref);
+        double geo[3], tau0n[MAXP];
+        st = normalise_window(pr.tau0, m, n, model, geo, tau0n);
         if (st != TILT_OK) return st;
         // The transform being evaluated, expressed in the window's scaled
         // coordinates (centre = image of the grid centre under tau0).
         double H[9];
         for (int k = 0; k < 9; ++k) H[k] = taus[9 * i + k];
-        if (!finite9(H) || H[8] == 0.0) return TILT_ERR_ARG;
+        if (!std::isfinite(H[0] + H[1] + H[2] + H[3] + H[4] + H[5] + H[6] + H[7] + H[8]) || H[8] == 0.0)
+            return TILT_ERR_ARG;
         for (int k = 0; k < 9; ++k) H[k] /= taus[9 * i + 8];
-        const double s = ref.s;
+        const double s = geo[2];
         double Hn[9];
         for (int j = 0; j < 3; ++j) {
             const double sc = (j < 2) ? s : 1.0;
-            Hn[0 * 3 + j] = (H[0 * 3 + j] - ref.cx * H[2 * 3 + j]) / s * sc;
-            Hn[1 * 3 + j] = (H[1 * 3 + j] - ref.cy * H[2 * 3 + j]) / s * sc;
+            Hn[0 * 3 + j] = (H[0 * 3 + j] - geo[0] * H[2 * 3 + j]) / s * sc;
+            Hn[1 * 3 + j] = (H[1 * 3 + j] - geo[1] * H[2 * 3 + j]) / s * sc;
             Hn[2 * 3 + j] = H[2 * 3 + j] * sc;
         }
         const double h22n = Hn[8];
         for (int k = 0; k < 9; ++k) Hn[k] /= h22n;
-        (void)cur;
         PatchDesc& d = descs[i];
         std::memset(&d, 0, sizeof(d));
         d.image = pr.image;
@@ -865,8 +869,8 @@ int tilt_warp_jacobian(tilt_ctx* ctx, const tilt_problem* probs, const double* t
         d.n = n;
         d.model = model;
         d.pp = model - 3;
-        d.cx = ref.cx;
-        d.cy = ref.cy;
+        d.cx = geo[0];
+        d.cy = geo[1];
         d.s = s;
         PatchState& ps = states[i];
         std::memset(&ps, 0, sizeof(ps));
@@ -884,6 +888,17 @@ int tilt_warp_jacobian(tilt_ctx* ctx, const tilt_problem* probs, const double* t
                            stream));
     HIP_TRY(launch_step1(reinterpret_cast<const PatchDesc*>(ctx->descs.p),
                          reinterpret_cast<PatchState*>(ctx->states.p), count, I_out, J_out, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return TILT_OK;
+}
+
+int tilt_pyramid(tilt_ctx* ctx, const float* image, int height, int width, long long row_stride, float* out,
+                 int levels, void* hip_stream) {
+    if (!ctx || !image || !out || height < 2 || width < 2 || row_stride < width) return TILT_ERR_ARG;
+    if (levels < 2 || levels > MAX_LEVELS) return TILT_ERR_ARG;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    HIP_TRY(launch_pyramid_jobs(image, height, width, row_stride, out, levels, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     return TILT_OK;
 }

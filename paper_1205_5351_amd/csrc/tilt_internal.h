@@ -12,6 +12,7 @@ constexpr int MAXP = 8;          // transform parameters (projective)
 constexpr int MAXPP = 5;         // free parameters after the 3 constraints
 constexpr int NPLANES = 6 + MAXP;
 constexpr int LDS_LIMIT = 160 * 1024;
+constexpr int MAX_LEVELS = 4;    // pyramid levels per request
 
 // Per-patch device planes, each nc * ldg floats in "X layout": the matrix
 // is stored with its shorter side as the outer index, so the vectors the
@@ -42,7 +43,8 @@ struct PatchDesc {
     int nsb;                  // tiled SVT: super-blocks (even)
     int ncp;                  // tiled SVT: rows of the working plane (nsb * sb >= nc)
     int pad0, pad1;
-    double cx, cy, s;
+    double cx, cy, s;         // scaled coordinates of the level being solved (the
+                              // kernels take them from PatchState::geo)
     double lam;
     float* ws;                // NPLANES planes (+ one ncp x ldg working plane when tiled)
     float* A_out;             // m x n row-major (may be null)
@@ -58,6 +60,7 @@ struct PatchState {
     int outer, inner, inner_total, done_inner, done_outer, status, svt_rank, warn;
     long long svt_calls, sweeps, pairs, rotations, recon_rows;
     long long t_begin, t_end;  // device wall clock at the start / end of the solve
+    double geo[3];             // cx, cy, s of the level being solved
 };
 
 struct SolverParams {
@@ -66,6 +69,64 @@ struct SolverParams {
     float jacobi_tol;
     int pad;
 };
+
+// Scaled coordinates of an m x n window (shared by host and device, FP64).
+// Hn = T^{-1} H diag(s, s, 1) with T = [[s, 0, cx], [0, s, cy], [0, 0, 1]],
+// (cx, cy) the image of the grid centre, s = max(m, n)/2, h33 = 1.
+// Returns false for a non-finite or singular H.
+__host__ __device__ inline bool normalise_h(const double* Hpx, int m, int n, double* geo, double* Hn) {
+    for (int k = 0; k < 9; ++k)
+        if (!(Hpx[k] == Hpx[k]) || Hpx[k] - Hpx[k] != 0.0) return false;
+    if (Hpx[8] == 0.0) return false;
+    double H[9];
+    for (int k = 0; k < 9; ++k) H[k] = Hpx[k] / Hpx[8];
+    const double s = (m > n ? m : n) / 2.0;
+    const double cx = H[2], cy = H[5];
+    for (int j = 0; j < 3; ++j) {
+        const double sc = (j < 2) ? s : 1.0;
+        Hn[0 * 3 + j] = (H[0 * 3 + j] - cx * H[2 * 3 + j]) / s * sc;
+        Hn[1 * 3 + j] = (H[1 * 3 + j] - cy * H[2 * 3 + j]) / s * sc;
+        Hn[2 * 3 + j] = H[2 * 3 + j] * sc;
+    }
+    const double h22 = Hn[8];
+    if (h22 == 0.0) return false;
+    for (int k = 0; k < 9; ++k) Hn[k] /= h22;
+    const double det = Hn[0] * (Hn[4] * Hn[8] - Hn[5] * Hn[7]) - Hn[1] * (Hn[3] * Hn[8] - Hn[5] * Hn[6]) +
+                       Hn[2] * (Hn[3] * Hn[7] - Hn[4] * Hn[6]);
+    if (!(det > 1e-12 || det < -1e-12)) return false;
+    geo[0] = cx;
+    geo[1] = cy;
+    geo[2] = s;
+    return true;
+}
+
+// Inverse of normalise_h: H = T Hn diag(1/s, 1/s, 1), scaled to h33 = 1.
+__host__ __device__ inline void denormalise_h(const double* Hn, const double* geo, double* Hpx) {
+    const double cx = geo[0], cy = geo[1], s = geo[2];
+    double H[9];
+    for (int j = 0; j < 3; ++j) {
+        const double sc = (j < 2) ? 1.0 / s : 1.0;
+        H[0 * 3 + j] = (s * Hn[0 * 3 + j] + cx * Hn[2 * 3 + j]) * sc;
+        H[1 * 3 + j] = (s * Hn[1 * 3 + j] + cy * Hn[2 * 3 + j]) * sc;
+        H[2 * 3 + j] = Hn[2 * 3 + j] * sc;
+    }
+    for (int k = 0; k < 9; ++k) Hpx[k] = H[k] / H[8];
+}
+
+// Pixel and centred grid coordinates halve from one pyramid level to the
+// next: H_coarse = S H_fine S^{-1} with S = diag(1/2, 1/2, 1).
+__host__ __device__ inline void to_coarser_h(double* H) {
+    H[2] *= 0.5;
+    H[5] *= 0.5;
+    H[6] *= 2.0;
+    H[7] *= 2.0;
+}
+__host__ __device__ inline void to_finer_h(double* H) {
+    H[2] *= 2.0;
+    H[5] *= 2.0;
+    H[6] *= 0.5;
+    H[7] *= 0.5;
+}
 
 // Launch shape of the SVT for one matrix shape.
 struct SvtShape {
@@ -91,18 +152,42 @@ __host__ __device__ inline int svt_make_cfg(int bs, int lpp, int nch) {
     return (bs - 1) * 64 + (lpp == 4 ? 0 : (lpp == 8 ? 1 : 2)) * 16 + (nch - 1);
 }
 
+// Serving ring: request slots and the control word live in pinned
+// (coherent) host memory; the host publishes requests by raising `tail`,
+// workgroups of the serving kernel claim them through a device counter and
+// set `done` = sequence number + 1 when the result is in place.
+struct ServeSlot {
+    PatchDesc d[MAX_LEVELS];  // level 0 (the window as given) .. levels-1
+    SolverParams prm;
+    PatchState init;          // tau, geo of the coarsest level
+    PatchState result;
+    int levels;
+    int pad[3];
+    unsigned long long done;
+};
+
+struct ServeCtl {
+    unsigned long long tail;  // requests published
+    int stop;                 // host: finish the current requests and exit
+    int pad;
+};
+
 // Kernel launchers (tilt_kernels.hip).
-hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count,
+hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, int levels,
                         const int* order, int* queue, int grid, size_t lds, hipStream_t s);
-hipError_t launch_setup(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx,
-                        size_t lds, hipStream_t s);
-hipError_t launch_svt(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx,
-                      size_t lds, hipStream_t s);
-hipError_t launch_update(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx,
-                         hipStream_t s);
-hipError_t launch_dtau(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx,
-                       hipStream_t s);
-hipError_t launch_finalize(const PatchDesc* d, PatchState* st, int idx, hipStream_t s);
+hipError_t launch_serve(ServeCtl* ctl, ServeSlot* slots, PatchDesc* ddesc, PatchState* dstates,
+                        unsigned long long* head, int ring, long long idle_ticks, int grid, size_t lds,
+                        hipStream_t s);
+hipError_t launch_pyramid_build(const PatchDesc* d, int levels, hipStream_t s);
+hipError_t launch_level_begin(const PatchDesc* d, PatchState* st, int first, hipStream_t s);
+hipError_t launch_pyramid_jobs(const float* image, int H, int W, long long stride, float* out, int levels,
+                               hipStream_t s);
+hipError_t launch_setup(const PatchDesc* d, PatchState* st, const SolverParams& prm, size_t lds, hipStream_t s);
+hipError_t launch_svt(const PatchDesc* d, PatchState* st, const SolverParams& prm, size_t lds, hipStream_t s);
+hipError_t launch_update(const PatchDesc* d, PatchState* st, const SolverParams& prm, hipStream_t s);
+hipError_t launch_dtau(const PatchDesc* d, PatchState* st, const SolverParams& prm, hipStream_t s);
+hipError_t launch_finalize(const PatchDesc* d, PatchState* st, int last, hipStream_t s);
+hipError_t launch_mark_end(PatchState* st, hipStream_t s);
 hipError_t launch_step1(const PatchDesc* d, PatchState* st, int count, float* I_out, float* J_out,
                         hipStream_t s);
 hipError_t launch_svt_jobs(const SvtJob* jobs, int count, const SvtShape& shape, float tol,

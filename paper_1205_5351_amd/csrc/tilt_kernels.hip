@@ -1482,9 +1482,19 @@ __device__ void dev_finalize(const PatchDesc& d, PatchState* st) {
 
 extern __shared__ float4 tilt_dyn_lds[];
 
+// The kernels read the scaled coordinates of the level being solved from
+// the state (the host sets them for the first level; level transitions
+// move them on the device).
+__device__ inline PatchDesc desc_at_level(const PatchDesc* dp, const PatchState* st) {
+    PatchDesc d = *dp;
+    d.cx = st->geo[0];
+    d.cy = st->geo[1];
+    d.s = st->geo[2];
+    return d;
+}
+
 __device__ void solve_patch(const PatchDesc& d, PatchState* st, const SolverParams& prm, float* lds) {
     __shared__ int sh_flag;
-    if (threadIdx.x == 0) st->t_begin = (long long)wall_clock64();
     for (;;) {
         dev_setup(d, st, prm, lds);
         if (threadIdx.x == 0) sh_flag = st->status < 0;
@@ -1506,15 +1516,108 @@ __device__ void solve_patch(const PatchDesc& d, PatchState* st, const SolverPara
         if (sh_flag) break;
     }
     dev_finalize(d, st);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-to-fine pyramid.  Level l+1 is level l blurred with the separable
+// binomial kernel [1 4 6 4 1]/16 (indices clamped at the borders) at every
+// second pixel; the window halves with it and transforms move between
+// levels by conjugation with diag(1/2, 1/2, 1).  Each level is solved cold
+// from the transform the coarser level returned.
+// ---------------------------------------------------------------------------
+
+__device__ void blur_decimate(const float* src, int Hs, int Ws, long long ss, float* dst, int Hd, int Wd) {
+    const float w[5] = {0.0625f, 0.25f, 0.375f, 0.25f, 0.0625f};
+    for (int e = threadIdx.x; e < Hd * Wd; e += NT) {
+        const int i = e / Wd, j = e - i * Wd;
+        int cols[5];
+#pragma unroll
+        for (int b = 0; b < 5; ++b) cols[b] = min(max(2 * j + b - 2, 0), Ws - 1);
+        float acc = 0.f;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            const float* row = src + (long long)min(max(2 * i + a - 2, 0), Hs - 1) * ss;
+            float r = 0.f;
+#pragma unroll
+            for (int b = 0; b < 5; ++b) r = fmaf(w[b], row[cols[b]], r);
+            acc = fmaf(w[a], r, acc);
+        }
+        dst[e] = acc;
+    }
+}
+
+// Build levels 1..levels-1 (dl[l].image points into the request workspace).
+__device__ void build_pyramid(const PatchDesc* dl, int levels) {
+    for (int l = 1; l < levels; ++l) {
+        blur_decimate(dl[l - 1].image, dl[l - 1].H, dl[l - 1].W, dl[l - 1].stride, const_cast<float*>(dl[l].image),
+                      dl[l].H, dl[l].W);
+        __syncthreads();
+    }
+}
+
+// Move the state from the solved coarser level to level `d` (thread 0).
+__device__ void level_transition(const PatchDesc& d, PatchState* st) {
+    if (threadIdx.x == 0) {
+        double Hn[9] = {st->tau[0], st->tau[1], st->tau[2], st->tau[3], st->tau[4], st->tau[5], 0.0, 0.0, 1.0};
+        if (d.model == 8) {
+            Hn[6] = st->tau[6];
+            Hn[7] = st->tau[7];
+        }
+        double H[9], geo[3], Hf[9];
+        denormalise_h(Hn, st->geo, H);
+        to_finer_h(H);
+        if (normalise_h(H, d.m, d.n, geo, Hf)) {
+            st->tau[0] = Hf[0];
+            st->tau[1] = Hf[1];
+            st->tau[2] = Hf[2];
+            st->tau[3] = Hf[3];
+            st->tau[4] = Hf[4];
+            st->tau[5] = Hf[5];
+            st->tau[6] = d.model == 8 ? Hf[6] : 0.0;
+            st->tau[7] = d.model == 8 ? Hf[7] : 0.0;
+            st->geo[0] = geo[0];
+            st->geo[1] = geo[1];
+            st->geo[2] = geo[2];
+        } else {
+            st->status = -5;
+        }
+        st->outer = 0;
+        st->inner = 0;
+        st->done_inner = 0;
+        st->done_outer = 0;
+    }
+    __syncthreads();
+}
+
+// One request: build its pyramid, then solve from the coarsest level to
+// level 0.  dl[0..levels-1] are the level descriptors.
+__device__ void solve_request(const PatchDesc* dl, int levels, PatchState* st, const SolverParams& prm, float* lds) {
+    __shared__ int sh_fail;
+    if (threadIdx.x == 0) st->t_begin = (long long)wall_clock64();
+    if (levels > 1) build_pyramid(dl, levels);
+    for (int l = levels - 1; l >= 0; --l) {
+        if (l < levels - 1) {
+            if (threadIdx.x == 0) sh_fail = st->status < 0;
+            __syncthreads();
+            if (sh_fail) break;
+            level_transition(dl[l], st);
+            if (threadIdx.x == 0) sh_fail = st->status < 0;
+            __syncthreads();
+            if (sh_fail) break;
+        }
+        const PatchDesc d = desc_at_level(dl + l, st);
+        solve_patch(d, st, prm, lds);
+    }
     if (threadIdx.x == 0) st->t_end = (long long)wall_clock64();
 }
 
-// Persistent solver: each workgroup takes the next patch from the queue
+// Persistent solver: each workgroup takes the next request from the queue
 // (in the order given by `order`, longest predicted solve first) until the
-// queue is exhausted.
+// queue is exhausted.  Request i has its level descriptors at
+// descs[i * levels ...].
 __global__ void __launch_bounds__(NT) k_fused(const PatchDesc* __restrict__ descs, PatchState* states,
-                                               SolverParams prm, int count, const int* __restrict__ order,
-                                               int* queue) {
+                                               SolverParams prm, int count, int levels,
+                                               const int* __restrict__ order, int* queue) {
     __shared__ int sh_idx;
     float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
     for (;;) {
@@ -1526,38 +1629,163 @@ __global__ void __launch_bounds__(NT) k_fused(const PatchDesc* __restrict__ desc
         const int idx = sh_idx;
         __syncthreads();
         if (idx >= count) break;
-        const PatchDesc d = descs[idx];
-        solve_patch(d, states + idx, prm, lds);
+        solve_request(descs + (size_t)idx * levels, levels, states + idx, prm, lds);
     }
 }
 
-__global__ void __launch_bounds__(NT) k_setup(const PatchDesc* descs, PatchState* states, SolverParams prm, int idx) {
+// ---------------------------------------------------------------------------
+// Serving kernel (continuous batching).  Each workgroup polls the ring for
+// published requests, claims the next one with a compare-and-swap on the
+// device counter `head`, copies its descriptors and initial state to device
+// memory, solves it and writes the final state back to the slot before
+// raising the slot's `done`.  A workgroup exits when the host sets `stop`
+// or after `idle_ticks` of the device wall clock without work, so every
+// wave reaches an exit; the host relaunches the kernel when requests are
+// outstanding and it has ended.
+//
+// Workspaces are recycled between requests that may run on different
+// XCDs: an agent-scope fence at the start of a request drops stale cached
+// lines, and a system-scope fence before `done` makes the results (state,
+// A, E) visible to the host.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(NT) k_serve(ServeCtl* ctl, ServeSlot* slots, PatchDesc* ddesc, PatchState* dstates,
+                                               unsigned long long* head, int ring, long long idle_ticks) {
+    __shared__ long long sh_seq;
     float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
-    const PatchDesc d = descs[idx];
-    if (threadIdx.x == 0 && states[idx].outer == 0) states[idx].t_begin = (long long)wall_clock64();
-    dev_setup(d, states + idx, prm, lds);
+    const int tid = threadIdx.x;
+    long long idle_since = (long long)wall_clock64();
+    for (;;) {
+        if (tid == 0) {
+            long long seq = -1;
+            const unsigned long long tail =
+                __hip_atomic_load(&ctl->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+            unsigned long long h = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while (h < tail) {
+                if (__hip_atomic_compare_exchange_strong(head, &h, h + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)) {
+                    seq = (long long)h;
+                    break;
+                }
+            }
+            if (seq < 0) {
+                const int stop = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                if (stop || (long long)wall_clock64() - idle_since > idle_ticks) seq = -2;
+            }
+            sh_seq = seq;
+        }
+        __syncthreads();
+        const long long seq = sh_seq;
+        __syncthreads();
+        if (seq == -2) break;
+        if (seq < 0) {
+            if (tid == 0) {
+                for (int k = 0; k < 8; ++k) __builtin_amdgcn_s_sleep(127);
+            }
+            __syncthreads();
+            continue;
+        }
+        const int slot = (int)(seq % ring);
+        ServeSlot* sl = slots + slot;
+        PatchDesc* dl = ddesc + (size_t)slot * MAX_LEVELS;
+        PatchState* st = dstates + slot;
+        __threadfence();
+        const int levels = sl->levels;
+        {
+            const unsigned long long* src = reinterpret_cast<const unsigned long long*>(sl->d);
+            unsigned long long* dst = reinterpret_cast<unsigned long long*>(dl);
+            const int nw = (int)(sizeof(PatchDesc) * MAX_LEVELS / 8);
+            for (int k = tid; k < nw; k += NT) dst[k] = src[k];
+            const unsigned long long* s0 = reinterpret_cast<const unsigned long long*>(&sl->init);
+            unsigned long long* s1 = reinterpret_cast<unsigned long long*>(st);
+            for (int k = tid; k < (int)(sizeof(PatchState) / 8); k += NT) s1[k] = s0[k];
+        }
+        __shared__ SolverParams sh_prm;
+        if (tid == 0) sh_prm = sl->prm;
+        __syncthreads();
+        const SolverParams prm = sh_prm;
+        solve_request(dl, levels, st, prm, lds);
+        __syncthreads();
+        {
+            const unsigned long long* s0 = reinterpret_cast<const unsigned long long*>(st);
+            unsigned long long* s1 = reinterpret_cast<unsigned long long*>(&sl->result);
+            for (int k = tid; k < (int)(sizeof(PatchState) / 8); k += NT) s1[k] = s0[k];
+        }
+        __threadfence_system();
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(&sl->done, (unsigned long long)seq + 1ull, __ATOMIC_RELEASE,
+                                         __HIP_MEMORY_SCOPE_SYSTEM);
+        idle_since = (long long)wall_clock64();
+    }
 }
 
-__global__ void __launch_bounds__(NT) k_svt(const PatchDesc* descs, PatchState* states, SolverParams prm, int idx) {
+// Plain (step-by-step) kernels: one workgroup, one patch; `d` and `st`
+// point at the level descriptor and the patch state.
+__global__ void __launch_bounds__(NT) k_setup(const PatchDesc* dp, PatchState* st, SolverParams prm) {
     float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
-    const PatchDesc d = descs[idx];
-    dev_svt(d, states + idx, prm, lds);
+    const PatchDesc d = desc_at_level(dp, st);
+    dev_setup(d, st, prm, lds);
 }
 
-__global__ void __launch_bounds__(NT) k_update(const PatchDesc* descs, PatchState* states, SolverParams prm, int idx) {
-    const PatchDesc d = descs[idx];
-    dev_update(d, states + idx, prm);
+__global__ void __launch_bounds__(NT) k_svt(const PatchDesc* dp, PatchState* st, SolverParams prm) {
+    float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
+    const PatchDesc d = desc_at_level(dp, st);
+    dev_svt(d, st, prm, lds);
 }
 
-__global__ void __launch_bounds__(NT) k_dtau(const PatchDesc* descs, PatchState* states, SolverParams prm, int idx) {
-    const PatchDesc d = descs[idx];
-    dev_dtau(d, states + idx, prm);
+__global__ void __launch_bounds__(NT) k_update(const PatchDesc* dp, PatchState* st, SolverParams prm) {
+    const PatchDesc d = desc_at_level(dp, st);
+    dev_update(d, st, prm);
 }
 
-__global__ void __launch_bounds__(NT) k_finalize(const PatchDesc* descs, PatchState* states, int idx) {
-    const PatchDesc d = descs[idx];
-    dev_finalize(d, states + idx);
-    if (threadIdx.x == 0) states[idx].t_end = (long long)wall_clock64();
+__global__ void __launch_bounds__(NT) k_dtau(const PatchDesc* dp, PatchState* st, SolverParams prm) {
+    const PatchDesc d = desc_at_level(dp, st);
+    dev_dtau(d, st, prm);
+}
+
+__global__ void __launch_bounds__(NT) k_finalize(const PatchDesc* dp, PatchState* st, int last) {
+    const PatchDesc d = desc_at_level(dp, st);
+    dev_finalize(d, st);
+    if (threadIdx.x == 0 && last) st->t_end = (long long)wall_clock64();
+}
+
+__global__ void __launch_bounds__(NT) k_mark_end(PatchState* st) {
+    if (threadIdx.x == 0) st->t_end = (long long)wall_clock64();
+}
+
+// Plain path, pyramid: build the level images of one request (dl[0..levels-1]).
+__global__ void __launch_bounds__(NT) k_pyramid_build(const PatchDesc* dl, int levels) {
+    build_pyramid(dl, levels);
+}
+
+// Plain path: start a level (transition from the coarser level's result;
+// for the first level only the start time is recorded).
+__global__ void __launch_bounds__(NT) k_level_begin(const PatchDesc* dp, PatchState* st, int first) {
+    if (first) {
+        if (threadIdx.x == 0) st->t_begin = (long long)wall_clock64();
+    } else {
+        level_transition(*dp, st);
+    }
+}
+
+// Component kernel: pyramid levels 1..levels-1 of one image, stored one
+// after the other (level l is ceil(H/2^l) x ceil(W/2^l), row-major).
+__global__ void __launch_bounds__(NT) k_pyramid_jobs(const float* image, int H, int W, long long stride, float* out,
+                                                     int levels) {
+    const float* src = image;
+    int Hs = H, Ws = W;
+    long long ss = stride;
+    float* dst = out;
+    for (int l = 1; l < levels; ++l) {
+        const int Hd = (Hs + 1) / 2, Wd = (Ws + 1) / 2;
+        blur_decimate(src, Hs, Ws, ss, dst, Hd, Wd);
+        __syncthreads();
+        src = dst;
+        Hs = Hd;
+        Ws = Wd;
+        ss = Wd;
+        dst += (size_t)Hd * Wd;
+    }
 }
 
 // Component kernel: normalised warp and Jacobian (Alg. 1 Step 1); one
@@ -1678,42 +1906,70 @@ static hipError_t set_lds(const void* fn, size_t lds) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, const int* order,
-                        int* queue, int grid, size_t lds, hipStream_t s) {
+hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, int levels,
+                        const int* order, int* queue, int grid, size_t lds, hipStream_t s) {
     hipError_t e = set_lds((const void*)k_fused, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(NT), lds, s, d, st, prm, count, order, queue);
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(NT), lds, s, d, st, prm, count, levels, order, queue);
     return hipGetLastError();
 }
 
-hipError_t launch_setup(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx, size_t lds,
+hipError_t launch_serve(ServeCtl* ctl, ServeSlot* slots, PatchDesc* ddesc, PatchState* dstates,
+                        unsigned long long* head, int ring, long long idle_ticks, int grid, size_t lds,
                         hipStream_t s) {
+    hipError_t e = set_lds((const void*)k_serve, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_serve, dim3(grid), dim3(NT), lds, s, ctl, slots, ddesc, dstates, head, ring, idle_ticks);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(const PatchDesc* d, PatchState* st, const SolverParams& prm, size_t lds, hipStream_t s) {
     hipError_t e = set_lds((const void*)k_setup, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(NT), lds, s, d, st, prm, idx);
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(NT), lds, s, d, st, prm);
     return hipGetLastError();
 }
 
-hipError_t launch_svt(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx, size_t lds,
-                      hipStream_t s) {
+hipError_t launch_svt(const PatchDesc* d, PatchState* st, const SolverParams& prm, size_t lds, hipStream_t s) {
     hipError_t e = set_lds((const void*)k_svt, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_svt, dim3(1), dim3(NT), lds, s, d, st, prm, idx);
+    hipLaunchKernelGGL(k_svt, dim3(1), dim3(NT), lds, s, d, st, prm);
     return hipGetLastError();
 }
 
-hipError_t launch_update(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx, hipStream_t s) {
-    hipLaunchKernelGGL(k_update, dim3(1), dim3(NT), 0, s, d, st, prm, idx);
+hipError_t launch_update(const PatchDesc* d, PatchState* st, const SolverParams& prm, hipStream_t s) {
+    hipLaunchKernelGGL(k_update, dim3(1), dim3(NT), 0, s, d, st, prm);
     return hipGetLastError();
 }
 
-hipError_t launch_dtau(const PatchDesc* d, PatchState* st, const SolverParams& prm, int idx, hipStream_t s) {
-    hipLaunchKernelGGL(k_dtau, dim3(1), dim3(NT), 0, s, d, st, prm, idx);
+hipError_t launch_dtau(const PatchDesc* d, PatchState* st, const SolverParams& prm, hipStream_t s) {
+    hipLaunchKernelGGL(k_dtau, dim3(1), dim3(NT), 0, s, d, st, prm);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const PatchDesc* d, PatchState* st, int idx, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NT), 0, s, d, st, idx);
+hipError_t launch_finalize(const PatchDesc* d, PatchState* st, int last, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NT), 0, s, d, st, last);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_end(PatchState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_mark_end, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_pyramid_build(const PatchDesc* d, int levels, hipStream_t s) {
+    hipLaunchKernelGGL(k_pyramid_build, dim3(1), dim3(NT), 0, s, d, levels);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_begin(const PatchDesc* d, PatchState* st, int first, hipStream_t s) {
+    hipLaunchKernelGGL(k_level_begin, dim3(1), dim3(NT), 0, s, d, st, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_pyramid_jobs(const float* image, int H, int W, long long stride, float* out, int levels,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_pyramid_jobs, dim3(1), dim3(NT), 0, s, image, H, W, stride, out, levels);
     return hipGetLastError();
 }
 

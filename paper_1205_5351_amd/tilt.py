@@ -73,6 +73,7 @@ class Params(C.Structure):
         ("svt_mode", C.c_int),
         ("jacobi_tol", C.c_float),
         ("max_sweeps", C.c_int),
+        ("pyramid_levels", C.c_int),
     ]
 
 
@@ -153,12 +154,22 @@ _lib.tilt_svt_batch.restype = C.c_int
 _lib.tilt_warp_jacobian.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(C.c_double), C.c_int,
                                     C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.tilt_warp_jacobian.restype = C.c_int
+_lib.tilt_submit.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(Params), C.c_void_p, C.c_void_p,
+                             C.POINTER(C.c_ulonglong)]
+_lib.tilt_submit.restype = C.c_int
+_lib.tilt_poll.argtypes = [C.c_void_p, C.c_ulonglong, C.POINTER(Result)]
+_lib.tilt_poll.restype = C.c_int
+_lib.tilt_serve_stop.argtypes = [C.c_void_p]
+_lib.tilt_serve_stop.restype = C.c_int
+_lib.tilt_pyramid.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_longlong, C.c_void_p, C.c_int,
+                              C.c_void_p]
+_lib.tilt_pyramid.restype = C.c_int
 
 EXPORTS = [
     "tilt_default_params", "tilt_status_string", "tilt_version", "tilt_tau_from_quad", "tilt_solve",
     "tilt_ctx_create", "tilt_ctx_destroy", "tilt_workspace_bytes", "tilt_solve_batch",
     "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_warp_jacobian", "tilt_last_error",
-    "tilt_ctx_last_kernel_ms",
+    "tilt_ctx_last_kernel_ms", "tilt_submit", "tilt_poll", "tilt_serve_stop", "tilt_pyramid",
 ]
 
 
@@ -343,6 +354,39 @@ class Context:
         return list(ranks), dict(svt_calls=cnt.svt_calls, jacobi_sweeps=cnt.jacobi_sweeps,
                                  jacobi_pairs=cnt.jacobi_pairs, jacobi_rotations=cnt.jacobi_rotations,
                                  recon_rows=cnt.recon_rows)
+
+    # -- serving ---------------------------------------------------------
+    def submit(self, problem: Problem, params: Optional[Params] = None, A_ptr: int = 0, E_ptr: int = 0) -> int:
+        """Queue one problem (device image, device A/E or 0); returns its ticket."""
+        prm = params if params is not None else default_params()
+        t = C.c_ulonglong()
+        rc = _lib.tilt_submit(self._h, C.byref(problem), C.byref(prm), C.c_void_p(int(A_ptr)) if A_ptr else None,
+                              C.c_void_p(int(E_ptr)) if E_ptr else None, C.byref(t))
+        if rc != TILT_OK:
+            raise TiltError(rc, "tilt_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """None while pending, else (status, result dict)."""
+        r = Result()
+        rc = _lib.tilt_poll(self._h, C.c_ulonglong(int(ticket)), C.byref(r))
+        if rc == TILT_PENDING:
+            return None
+        if rc in (TILT_ERR_NOT_FOUND, TILT_ERR_DEVICE, TILT_ERR_ARG):
+            raise TiltError(rc, "tilt_poll")
+        return rc, result_dict(r)
+
+    def serve_stop(self):
+        rc = _lib.tilt_serve_stop(self._h)
+        if rc != TILT_OK:
+            raise TiltError(rc, "tilt_serve_stop")
+
+    def pyramid(self, image_ptr: int, height: int, width: int, row_stride: int, out_ptr: int, levels: int,
+                stream=None):
+        rc = _lib.tilt_pyramid(self._h, C.c_void_p(int(image_ptr)), int(height), int(width), int(row_stride),
+                               C.c_void_p(int(out_ptr)), int(levels), C.c_void_p(_stream_ptr(stream)))
+        if rc != TILT_OK:
+            raise TiltError(rc, "tilt_pyramid")
 
     def warp_jacobian(self, problems: List[Problem], taus, I_ptr: int, J_ptr: int, stream=None):
         n = len(problems)
