@@ -243,6 +243,64 @@ __device__ inline bool rotate_rows(float4* x, float4* y, float& nx, float& ny, f
     return true;
 }
 
+// Two independent rotations (disjoint rows) computed side by side so that
+// their dependency chains (dot, cross-lane sum, rotation parameters)
+// overlap.  A pair that is already orthogonal to tolerance gets s = tau = 0,
+// which leaves its rows and norms bit-for-bit unchanged.
+template <int LPP, int NCH>
+__device__ inline void rotate_two(float4* x1, float4* y1, float& nx1, float& ny1, bool& f1, float4* x2, float4* y2,
+                                  float& nx2, float& ny2, bool& f2, float tol) {
+    float p0 = 0.f, p1 = 0.f, q0 = 0.f, q1 = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCH; c += 2) {
+        p0 = dot4(x1[c], y1[c], p0);
+        q0 = dot4(x2[c], y2[c], q0);
+    }
+#pragma unroll
+    for (int c = 1; c < NCH; c += 2) {
+        p1 = dot4(x1[c], y1[c], p1);
+        q1 = dot4(x2[c], y2[c], q1);
+    }
+    const float g1 = group_sum<LPP>(p0 + p1);
+    const float g2 = group_sum<LPP>(q0 + q1);
+    f1 = fabsf(g1) > tol * (__builtin_amdgcn_sqrtf(nx1) * __builtin_amdgcn_sqrtf(ny1));
+    f2 = fabsf(g2) > tol * (__builtin_amdgcn_sqrtf(nx2) * __builtin_amdgcn_sqrtf(ny2));
+    if (!(f1 || f2)) return;
+    float s1, h1, t1, s2, h2, t2;
+    jacobi_rotation(nx1, ny1, f1 ? g1 : 1.0f, s1, h1, t1);
+    jacobi_rotation(nx2, ny2, f2 ? g2 : 1.0f, s2, h2, t2);
+    if (!f1) s1 = h1 = t1 = 0.f;
+    if (!f2) s2 = h2 = t2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const float4 a = x1[c], b = y1[c], u = x2[c], v = y2[c];
+        x1[c].x = fmaf(-s1, fmaf(h1, a.x, b.x), a.x);
+        x1[c].y = fmaf(-s1, fmaf(h1, a.y, b.y), a.y);
+        x1[c].z = fmaf(-s1, fmaf(h1, a.z, b.z), a.z);
+        x1[c].w = fmaf(-s1, fmaf(h1, a.w, b.w), a.w);
+        x2[c].x = fmaf(-s2, fmaf(h2, u.x, v.x), u.x);
+        x2[c].y = fmaf(-s2, fmaf(h2, u.y, v.y), u.y);
+        x2[c].z = fmaf(-s2, fmaf(h2, u.z, v.z), u.z);
+        x2[c].w = fmaf(-s2, fmaf(h2, u.w, v.w), u.w);
+        y1[c].x = fmaf(s1, fmaf(-h1, b.x, a.x), b.x);
+        y1[c].y = fmaf(s1, fmaf(-h1, b.y, a.y), b.y);
+        y1[c].z = fmaf(s1, fmaf(-h1, b.z, a.z), b.z);
+        y1[c].w = fmaf(s1, fmaf(-h1, b.w, a.w), b.w);
+        y2[c].x = fmaf(s2, fmaf(-h2, v.x, u.x), v.x);
+        y2[c].y = fmaf(s2, fmaf(-h2, v.y, u.y), v.y);
+        y2[c].z = fmaf(s2, fmaf(-h2, v.z, u.z), v.z);
+        y2[c].w = fmaf(s2, fmaf(-h2, v.w, u.w), v.w);
+    }
+    if (f1) {
+        nx1 = fmaxf(fmaf(-t1, g1, nx1), 0.f);
+        ny1 = fmaxf(fmaf(t1, g1, ny1), 0.f);
+    }
+    if (f2) {
+        nx2 = fmaxf(fmaf(-t2, g2, nx2), 0.f);
+        ny2 = fmaxf(fmaf(t2, g2, ny2), 0.f);
+    }
+}
+
 // Squared norms of rows 0..nrows-1 of B into s2 (LDS).
 template <int LPP, int NCH>
 __device__ void row_norms(const float* B, int nrows, int ld, float* s2) {
@@ -327,21 +385,15 @@ __device__ int jacobi_rows(float* B, int nc, int ld, float tol, int max_sweeps, 
                     load_row<LPP, NCH>(pb, b1);
                     load_row<LPP, NCH>(pb + ld, b2);
                     float na1 = nrm[2 * I], na2 = nrm[2 * I + 1], nb1 = nrm[2 * J], nb2 = nrm[2 * J + 1];
-                    bool d0 = false, d1 = false, d2 = false, d3 = false, f;
+                    bool d0 = false, d1 = false, d2 = false, d3 = false, f, g;
                     if (r == 0) {
-                        f = rotate_rows<LPP, NCH>(a1, a2, na1, na2, tol);
-                        d0 |= f; d1 |= f; rots += f;
-                        f = rotate_rows<LPP, NCH>(b1, b2, nb1, nb2, tol);
-                        d2 |= f; d3 |= f; rots += f;
+                        rotate_two<LPP, NCH>(a1, a2, na1, na2, f, b1, b2, nb1, nb2, g, tol);
+                        d0 |= f; d1 |= f; d2 |= g; d3 |= g; rots += f; rots += g;
                     }
-                    f = rotate_rows<LPP, NCH>(a1, b1, na1, nb1, tol);
-                    d0 |= f; d2 |= f; rots += f;
-                    f = rotate_rows<LPP, NCH>(a2, b2, na2, nb2, tol);
-                    d1 |= f; d3 |= f; rots += f;
-                    f = rotate_rows<LPP, NCH>(a1, b2, na1, nb2, tol);
-                    d0 |= f; d3 |= f; rots += f;
-                    f = rotate_rows<LPP, NCH>(a2, b1, na2, nb1, tol);
-                    d1 |= f; d2 |= f; rots += f;
+                    rotate_two<LPP, NCH>(a1, b1, na1, nb1, f, a2, b2, na2, nb2, g, tol);
+                    d0 |= f; d2 |= f; d1 |= g; d3 |= g; rots += f; rots += g;
+                    rotate_two<LPP, NCH>(a1, b2, na1, nb2, f, a2, b1, na2, nb1, g, tol);
+                    d0 |= f; d3 |= f; d1 |= g; d2 |= g; rots += f; rots += g;
                     if (d0 | d1 | d2 | d3) any = 1;
                     if (d0) store_row<LPP, NCH>(pa, a1);
                     if (d1) store_row<LPP, NCH>(pa + ld, a2);

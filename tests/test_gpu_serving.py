@@ -70,7 +70,7 @@ def test_pyramid_fixed_iterations_match_oracle(tilt, ctx, device, idx):
     assert np.linalg.norm(r["A"] - ref.A) <= 1e-4 * np.linalg.norm(ref.A)
 
 
-@pytest.mark.parametrize("idx", [15])
+@pytest.mark.parametrize("idx", [15, 42, 70, 84, 86])
 def test_pyramid_full_solve_matches_oracle(tilt, ctx, device, idx):
     p = ts.make_batch(4, [idx])[0]
     tp = tilt.default_params(pyramid_levels=3)
