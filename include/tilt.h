@@ -72,7 +72,14 @@ typedef struct {
     int max_outer;      /* default 50                                         */
     int fixed_iters;    /* 1: run exactly max_outer x max_inner iterations
                            (stop tests evaluated but ignored)                 */
-    int svt_mode;       /* 0: cold one-sided Jacobi SVT every iteration       */
+    int svt_mode;       /* 0: cold one-sided Jacobi SVT every iteration.
+                           1: warm start: each SVT starts from the previous
+                           SVT's accumulated rotation applied to the new
+                           iterate (re-orthonormalised by a Newton-Schulz
+                           step every 4 calls); same result to rounding,
+                           fewer sweeps.  Used where the Jacobi rows and the
+                           rotation fit in LDS together (about
+                           min(m,n) * max(m,n) <= 18k); cold elsewhere.       */
     float jacobi_tol;   /* rotate a pair when |a.b| > tol ||a|| ||b||; 1e-6   */
     int max_sweeps;     /* Jacobi sweep cap, default 40                       */
     int pyramid_levels; /* 1 (default): solve the window as given.  L in 2..4:

@@ -128,6 +128,8 @@ int shape_config(int m, int n, ShapeCfg* out) {
     c.nr = std::max(m, n);
     c.ldg = (c.nr + 3) & ~3;
     c.sb = c.nsb = c.ncp = 0;
+    c.warm_tb = 0;
+    c.warm_lds = 0;
     const int nc4 = (c.nc + 3) & ~3;
     const size_t budget = (size_t)LDS_LIMIT - kStaticLdsMargin;
     if (nc4 <= SVT_MAX_ROWS) {
@@ -139,6 +141,19 @@ int shape_config(int m, int n, ShapeCfg* out) {
                 c.lds = lds_bytes(c.nc, c.ld, c.tb);
                 if (c.lds <= budget) {
                     c.ws_floats = (size_t)NPLANES * c.nc * c.ldg;
+                    // warm start: the rotation rows share the layout of the
+                    // Jacobi rows and need their own nc4 x ld LDS area
+                    if (svt_nch(c.cfg) <= 4) {
+                        for (int wtb = 32; wtb >= 16; wtb -= 16) {
+                            const size_t front = std::max((size_t)nc4 * c.ld, (size_t)wtb * c.ld + (size_t)nc4 * wtb);
+                            const size_t wl = sizeof(float) * ((size_t)nc4 * c.ld + front + 3 * (size_t)nc4);
+                            if (wl <= budget) {
+                                c.warm_tb = wtb;
+                                c.warm_lds = wl;
+                                break;
+                            }
+                        }
+                    }
                     *out = c;
                     return TILT_OK;
                 }
@@ -213,7 +228,7 @@ int validate_params(const tilt_params* p) {
     if (!(p->rho0 >= 1.0) || !(p->mu_max > 0)) return TILT_ERR_ARG;
     if (p->max_inner < 1 || p->max_outer < 1 || p->max_sweeps < 1) return TILT_ERR_ARG;
     if (!(p->jacobi_tol > 0.f) || !(p->jacobi_tol < 1.f)) return TILT_ERR_ARG;
-    if (p->svt_mode != 0) return TILT_ERR_ARG;
+    if (p->svt_mode != 0 && p->svt_mode != 1) return TILT_ERR_ARG;
     if (p->pyramid_levels < 0 || p->pyramid_levels > MAX_LEVELS) return TILT_ERR_ARG;
     if (!std::isfinite(p->lambda) || !std::isfinite(p->mu0)) return TILT_ERR_ARG;
     return TILT_OK;
@@ -241,7 +256,7 @@ SolverParams to_solver(const tilt_params* p) {
     s.fixed_iters = p->fixed_iters ? 1 : 0;
     s.max_sweeps = p->max_sweeps;
     s.jacobi_tol = p->jacobi_tol;
-    s.pad = 0;
+    s.ns_every = 4;
     return s;
 }
 
@@ -282,7 +297,8 @@ int plan_request(const tilt_problem& pr, const tilt_params* prm, float* A_out, f
         st = shape_config(ml[l], nl[l], &sc[l]);
         if (st != TILT_OK) return st;
         planes = std::max(planes, sc[l].ws_floats);
-        P.lds = std::max(P.lds, sc[l].lds);
+        const bool warm = prm->svt_mode == 1 && sc[l].warm_lds > 0;
+        P.lds = std::max(P.lds, warm ? sc[l].warm_lds : sc[l].lds);
     }
     size_t off = (planes + 63) & ~(size_t)63;
     size_t img_off[MAX_LEVELS] = {0};
@@ -314,7 +330,8 @@ int plan_request(const tilt_problem& pr, const tilt_params* prm, float* A_out, f
         d.colmajor = sc[l].colmajor;
         d.ld = sc[l].ld;
         d.svt_cfg = sc[l].cfg;
-        d.tb = sc[l].tb;
+        d.warm = (prm->svt_mode == 1 && sc[l].warm_lds > 0) ? 1 : 0;
+        d.tb = d.warm ? sc[l].warm_tb : sc[l].tb;
         d.sb = sc[l].sb;
         d.nsb = sc[l].nsb;
         d.ncp = sc[l].ncp;

@@ -29,6 +29,8 @@ struct ShapeCfg {
     int sb, nsb, ncp;  // tiled SVT (sb = 0: the whole matrix is held in LDS)
     size_t lds;
     size_t ws_floats;
+    int warm_tb;       // warm-started SVT: reconstruction block rows (0: not possible)
+    size_t warm_lds;   // warm-started SVT: dynamic LDS bytes
 };
 
 int shape_config(int m, int n, ShapeCfg* out);

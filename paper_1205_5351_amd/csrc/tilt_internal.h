@@ -10,14 +10,16 @@ constexpr int NT = 256;          // threads per workgroup, every kernel
 constexpr int NWAVE = NT / 64;   // wavefronts per workgroup
 constexpr int MAXP = 8;          // transform parameters (projective)
 constexpr int MAXPP = 5;         // free parameters after the 3 constraints
-constexpr int NPLANES = 6 + MAXP;
+constexpr int NPLANES = 7 + MAXP;
 constexpr int LDS_LIMIT = 160 * 1024;
 constexpr int MAX_LEVELS = 4;    // pyramid levels per request
 
 // Per-patch device planes, each nc * ldg floats in "X layout": the matrix
 // is stored with its shorter side as the outer index, so the vectors the
 // one-sided Jacobi orthogonalises (length nr = max(m, n)) are contiguous.
-enum Plane { PL_I = 0, PL_A = 1, PL_E = 2, PL_Y = 3, PL_R = 4, PL_M = 5, PL_Q = 6 };
+// PL_V holds the accumulated Jacobi rotation of the warm-started SVT
+// (nc x nc in the first nc columns); it persists across inner iterations.
+enum Plane { PL_I = 0, PL_A = 1, PL_E = 2, PL_Y = 3, PL_R = 4, PL_M = 5, PL_Q = 6, PL_V = 6 + MAXP };
 
 // Jacobi variants: cfg = (BS - 1) * 64 + (log2(LPP) - 2) * 16 + (NCH - 1)
 // with BS rows per block (1 or 2), LPP lanes per block pair (4, 8 or 16)
@@ -42,7 +44,8 @@ struct PatchDesc {
     int sb;                   // tiled SVT: rows per super-block (0: whole matrix in LDS)
     int nsb;                  // tiled SVT: super-blocks (even)
     int ncp;                  // tiled SVT: rows of the working plane (nsb * sb >= nc)
-    int pad0, pad1;
+    int warm;                 // 1: SVT warm-started from the previous rotation
+    int pad1;
     double cx, cy, s;         // scaled coordinates of the level being solved (the
                               // kernels take them from PatchState::geo)
     double lam;
@@ -61,13 +64,15 @@ struct PatchState {
     long long svt_calls, sweeps, pairs, rotations, recon_rows;
     long long t_begin, t_end;  // device wall clock at the start / end of the solve
     double geo[3];             // cx, cy, s of the level being solved
+    int warm_ok;               // PL_V holds a rotation for this level's shape
+    int warm_count;            // warm-started SVTs since the rotation was reset
 };
 
 struct SolverParams {
     double eps1, eps2, eps_outer, mu0, rho0, mu_max;
     int max_inner, max_outer, fixed_iters, max_sweeps;
     float jacobi_tol;
-    int pad;
+    int ns_every;  // warm SVT: Newton-Schulz re-orthonormalisation of the rotation every ns_every SVTs
 };
 
 // Scaled coordinates of an m x n window (shared by host and device, FP64).

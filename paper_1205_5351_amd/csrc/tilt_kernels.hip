@@ -219,10 +219,11 @@ __device__ inline float group_dot(const float4* a, const float4* b) {
 // to tolerance; updates their squared norms.  The decision is uniform over
 // the group (all lanes hold identical sums).
 template <int LPP, int NCH>
-__device__ inline bool rotate_rows(float4* x, float4* y, float& nx, float& ny, float tol) {
+__device__ inline bool rotate_rows(float4* x, float4* y, float& nx, float& ny, float tol, float& sn, float& ta) {
+    sn = ta = 0.f;
     const float ga = group_dot<LPP, NCH>(x, y);
     if (!(fabsf(ga) > tol * (__builtin_amdgcn_sqrtf(nx) * __builtin_amdgcn_sqrtf(ny)))) return false;
-    float sn, ta, t;
+    float t;
     jacobi_rotation(nx, ny, ga, sn, ta, t);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -249,7 +250,9 @@ __device__ inline bool rotate_rows(float4* x, float4* y, float& nx, float& ny, f
 // which leaves its rows and norms bit-for-bit unchanged.
 template <int LPP, int NCH>
 __device__ inline void rotate_two(float4* x1, float4* y1, float& nx1, float& ny1, bool& f1, float4* x2, float4* y2,
-                                  float& nx2, float& ny2, bool& f2, float tol) {
+                                  float& nx2, float& ny2, bool& f2, float tol, float& s1, float& h1, float& s2,
+                                  float& h2) {
+    s1 = h1 = s2 = h2 = 0.f;
     float p0 = 0.f, p1 = 0.f, q0 = 0.f, q1 = 0.f;
 #pragma unroll
     for (int c = 0; c < NCH; c += 2) {
@@ -266,7 +269,7 @@ __device__ inline void rotate_two(float4* x1, float4* y1, float& nx1, float& ny1
     f1 = fabsf(g1) > tol * (__builtin_amdgcn_sqrtf(nx1) * __builtin_amdgcn_sqrtf(ny1));
     f2 = fabsf(g2) > tol * (__builtin_amdgcn_sqrtf(nx2) * __builtin_amdgcn_sqrtf(ny2));
     if (!(f1 || f2)) return;
-    float s1, h1, t1, s2, h2, t2;
+    float t1, t2;
     jacobi_rotation(nx1, ny1, f1 ? g1 : 1.0f, s1, h1, t1);
     jacobi_rotation(nx2, ny2, f2 ? g2 : 1.0f, s2, h2, t2);
     if (!f1) s1 = h1 = t1 = 0.f;
@@ -298,6 +301,27 @@ __device__ inline void rotate_two(float4* x1, float4* y1, float& nx1, float& ny1
     if (f2) {
         nx2 = fmaxf(fmaf(-t2, g2, nx2), 0.f);
         ny2 = fmaxf(fmaf(t2, g2, ny2), 0.f);
+    }
+}
+
+// Apply a rotation (s, tau) to two rows held in LDS (the lane's chunks).
+template <int LPP, int NCH>
+__device__ inline void rotate_lds_rows(float* pa, float* pb, float s, float h) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const float4 a = *reinterpret_cast<const float4*>(pa + 4 * LPP * c);
+        const float4 b = *reinterpret_cast<const float4*>(pb + 4 * LPP * c);
+        float4 x, y;
+        x.x = fmaf(-s, fmaf(h, a.x, b.x), a.x);
+        x.y = fmaf(-s, fmaf(h, a.y, b.y), a.y);
+        x.z = fmaf(-s, fmaf(h, a.z, b.z), a.z);
+        x.w = fmaf(-s, fmaf(h, a.w, b.w), a.w);
+        y.x = fmaf(s, fmaf(-h, b.x, a.x), b.x);
+        y.y = fmaf(s, fmaf(-h, b.y, a.y), b.y);
+        y.z = fmaf(s, fmaf(-h, b.z, a.z), b.z);
+        y.w = fmaf(s, fmaf(-h, b.w, a.w), b.w);
+        *reinterpret_cast<float4*>(pa + 4 * LPP * c) = x;
+        *reinterpret_cast<float4*>(pb + 4 * LPP * c) = y;
     }
 }
 
@@ -333,9 +357,11 @@ __device__ inline void store_row(float* p, const float4* x) {
     for (int c = 0; c < NCH; ++c) *reinterpret_cast<float4*>(p + 4 * LPP * c) = x[c];
 }
 
-// Returns 1 (uniform over the workgroup) if any pair was rotated.
-template <int BS, int LPP, int NCH>
-__device__ int jacobi_rows(float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js) {
+// Returns 1 (uniform over the workgroup) if any pair was rotated.  WARM:
+// every rotation is also applied to the rows of Rm (same layout), which
+// accumulates the product of the rotations.
+template <int BS, int LPP, int NCH, bool WARM>
+__device__ int jacobi_rows(float* B, float* Rm, int nc, int ld, float tol, int max_sweeps, JacobiStats& js) {
     float* nrm = tilt_jacobi_nrm;
     const int tid = threadIdx.x;
     const int g = tid / LPP, q = tid % LPP;
@@ -367,7 +393,9 @@ __device__ int jacobi_rows(float* B, int nc, int ld, float tol, int max_sweeps, 
                     load_row<LPP, NCH>(pa, a1);
                     load_row<LPP, NCH>(pb, b1);
                     float na1 = nrm[I], nb1 = nrm[J];
-                    const bool f = rotate_rows<LPP, NCH>(a1, b1, na1, nb1, tol);
+                    float sr, hr;
+                    const bool f = rotate_rows<LPP, NCH>(a1, b1, na1, nb1, tol, sr, hr);
+                    if (WARM && f) rotate_lds_rows<LPP, NCH>(Rm + I * ld + 4 * q, Rm + J * ld + 4 * q, sr, hr);
                     if (f) {
                         any = 1;
                         rots += 1;
@@ -386,13 +414,22 @@ __device__ int jacobi_rows(float* B, int nc, int ld, float tol, int max_sweeps, 
                     load_row<LPP, NCH>(pb + ld, b2);
                     float na1 = nrm[2 * I], na2 = nrm[2 * I + 1], nb1 = nrm[2 * J], nb2 = nrm[2 * J + 1];
                     bool d0 = false, d1 = false, d2 = false, d3 = false, f, g;
+                    float s1, h1, s2, h2;
+                    float* ra1 = WARM ? Rm + (BS * I) * ld + 4 * q : nullptr;
+                    float* rb1 = WARM ? Rm + (BS * J) * ld + 4 * q : nullptr;
                     if (r == 0) {
-                        rotate_two<LPP, NCH>(a1, a2, na1, na2, f, b1, b2, nb1, nb2, g, tol);
+                        rotate_two<LPP, NCH>(a1, a2, na1, na2, f, b1, b2, nb1, nb2, g, tol, s1, h1, s2, h2);
+                        if (WARM && f) rotate_lds_rows<LPP, NCH>(ra1, ra1 + ld, s1, h1);
+                        if (WARM && g) rotate_lds_rows<LPP, NCH>(rb1, rb1 + ld, s2, h2);
                         d0 |= f; d1 |= f; d2 |= g; d3 |= g; rots += f; rots += g;
                     }
-                    rotate_two<LPP, NCH>(a1, b1, na1, nb1, f, a2, b2, na2, nb2, g, tol);
+                    rotate_two<LPP, NCH>(a1, b1, na1, nb1, f, a2, b2, na2, nb2, g, tol, s1, h1, s2, h2);
+                    if (WARM && f) rotate_lds_rows<LPP, NCH>(ra1, rb1, s1, h1);
+                    if (WARM && g) rotate_lds_rows<LPP, NCH>(ra1 + ld, rb1 + ld, s2, h2);
                     d0 |= f; d2 |= f; d1 |= g; d3 |= g; rots += f; rots += g;
-                    rotate_two<LPP, NCH>(a1, b2, na1, nb2, f, a2, b1, na2, nb1, g, tol);
+                    rotate_two<LPP, NCH>(a1, b2, na1, nb2, f, a2, b1, na2, nb1, g, tol, s1, h1, s2, h2);
+                    if (WARM && f) rotate_lds_rows<LPP, NCH>(ra1, rb1 + ld, s1, h1);
+                    if (WARM && g) rotate_lds_rows<LPP, NCH>(ra1 + ld, rb1, s2, h2);
                     d0 |= f; d3 |= f; d1 |= g; d2 |= g; rots += f; rots += g;
                     if (d0 | d1 | d2 | d3) any = 1;
                     if (d0) store_row<LPP, NCH>(pa, a1);
@@ -421,16 +458,17 @@ __device__ int jacobi_rows(float* B, int nc, int ld, float tol, int max_sweeps, 
     return rotated;
 }
 
-template <int BS, int LPP, int NCH>
-__device__ void jacobi_svd_rows(float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js, float* s2) {
-    jacobi_rows<BS, LPP, NCH>(B, nc, ld, tol, max_sweeps, js);
+template <int BS, int LPP, int NCH, bool WARM>
+__device__ void jacobi_svd_rows(float* B, float* Rm, int nc, int ld, float tol, int max_sweeps, JacobiStats& js,
+                                float* s2) {
+    jacobi_rows<BS, LPP, NCH, WARM>(B, Rm, nc, ld, tol, max_sweeps, js);
     row_norms<LPP, NCH>(B, nc, ld, s2);
 }
 
 // cfg = (BS - 1) * 64 + (log2(LPP) - 2) * 16 + (NCH - 1)
 #define TILT_SVT_CASE(S, L, C)                                                            \
     case ((S - 1) * 64 + (L == 4 ? 0 : (L == 8 ? 1 : 2)) * 16 + (C - 1)):                  \
-        jacobi_svd_rows<S, L, C>(B, nc, ld, tol, max_sweeps, js, s2);                       \
+        jacobi_svd_rows<S, L, C, false>(B, nullptr, nc, ld, tol, max_sweeps, js, s2);       \
         break;
 #define TILT_SVT_CASES8(S, L)                                                              \
     TILT_SVT_CASE(S, L, 1) TILT_SVT_CASE(S, L, 2) TILT_SVT_CASE(S, L, 3) TILT_SVT_CASE(S, L, 4) \
@@ -447,6 +485,27 @@ __device__ void jacobi_dispatch(int cfg, float* B, int nc, int ld, float tol, in
             break;
     }
 }
+
+// Warm variants (rotation rows Rm in LDS, same layout as B): chunks per
+// lane up to 4.
+#define TILT_WARM_CASE(S, L, C)                                                           \
+    case ((S - 1) * 64 + (L == 4 ? 0 : (L == 8 ? 1 : 2)) * 16 + (C - 1)):                  \
+        jacobi_svd_rows<S, L, C, true>(B, Rm, nc, ld, tol, max_sweeps, js, s2);             \
+        break;
+#define TILT_WARM_CASES4(S, L) \
+    TILT_WARM_CASE(S, L, 1) TILT_WARM_CASE(S, L, 2) TILT_WARM_CASE(S, L, 3) TILT_WARM_CASE(S, L, 4)
+
+__device__ void jacobi_dispatch_warm(int cfg, float* B, float* Rm, int nc, int ld, float tol, int max_sweeps,
+                                     JacobiStats& js, float* s2) {
+    switch (cfg) {
+        TILT_WARM_CASES4(1, 4) TILT_WARM_CASES4(1, 8) TILT_WARM_CASES4(1, 16)
+        TILT_WARM_CASES4(2, 4) TILT_WARM_CASES4(2, 8) TILT_WARM_CASES4(2, 16)
+        default:
+            break;
+    }
+}
+#undef TILT_WARM_CASES4
+#undef TILT_WARM_CASE
 #undef TILT_SVT_CASES4
 #undef TILT_SVT_CASES8
 #undef TILT_SVT_CASE
@@ -454,7 +513,7 @@ __device__ void jacobi_dispatch(int cfg, float* B, int nc, int ld, float tol, in
 // One sweep over all pairs of the nrows rows of B (LDS); 1 if any rotated.
 #define TILT_SWEEP_CASE(S, L, C)                                                          \
     case ((S - 1) * 64 + (L == 4 ? 0 : (L == 8 ? 1 : 2)) * 16 + (C - 1)):                  \
-        return jacobi_rows<S, L, C>(B, nrows, ld, tol, 1, js);
+        return jacobi_rows<S, L, C, false>(B, nullptr, nrows, ld, tol, 1, js);
 #define TILT_SWEEP_CASES8(S, L)                                                                    \
     TILT_SWEEP_CASE(S, L, 1) TILT_SWEEP_CASE(S, L, 2) TILT_SWEEP_CASE(S, L, 3) TILT_SWEEP_CASE(S, L, 4) \
     TILT_SWEEP_CASE(S, L, 5) TILT_SWEEP_CASE(S, L, 6) TILT_SWEEP_CASE(S, L, 7) TILT_SWEEP_CASE(S, L, 8)
@@ -1247,6 +1306,155 @@ __device__ void dev_setup(const PatchDesc& d, PatchState* st, const SolverParams
 }
 
 // ---------------------------------------------------------------------------
+// Warm-started SVT.  The rows of R (nc x nc, orthonormal) are the product of
+// all Jacobi rotations applied so far; the decomposition of the next
+// iterate starts from B = R M, whose rows are already nearly orthogonal
+// when M changed little, and the new rotations are accumulated into R.
+// Rounding slowly erodes the orthonormality of R, so every few calls one
+// Newton-Schulz step R <- 1.5 R - 0.5 (R R^T) R restores it.  The SVT
+// result is built from B and M as in the cold case, so its accuracy rests
+// on R being orthogonal to rounding level, not on the quality of the start.
+// ---------------------------------------------------------------------------
+
+// LDS: B (nc4 x ld) | R (nc4 x ld), with the reconstruction blocks reusing
+// the R area after R has been saved | s2, w, act.
+__device__ inline SvtLds carve_lds_warm(float* base, int nc, int ld, int tb, float** Rl) {
+    SvtLds L;
+    const int nc4 = (nc + 3) & ~3;
+    L.B = base;
+    *Rl = base + nc4 * ld;
+    L.xblk = *Rl;
+    L.cwt = L.xblk + tb * ld;
+    L.s2 = *Rl + max(nc4 * ld, tb * ld + nc4 * tb);
+    L.w = L.s2 + nc4;
+    L.act = reinterpret_cast<int*>(L.w + nc4);
+    return L;
+}
+
+// B = R X for the nc4 rows of R (LDS, stride ld; rows >= nc are zero) and
+// the X-layout plane X (nc rows, stride ldg); tiles of 4 rows x 4 columns,
+// k summed in order.
+__device__ void warm_start_rows(const float* Rl, int ld, const float* X, int ldg, float* B, int nc, int nr4) {
+    const int nc4 = (nc + 3) & ~3;
+    const int tiles = (nc4 >> 2) * nr4;
+    for (int t = threadIdx.x; t < tiles; t += NT) {
+        const int i4 = t / nr4, c = t - i4 * nr4;
+        const float* r0 = Rl + (4 * i4) * ld;
+        float4 acc[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc[a] = f4(0.f);
+        for (int k = 0; k < nc; ++k) {
+            const float4 x = reinterpret_cast<const float4*>(X + (size_t)k * ldg)[c];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const float ra = r0[a * ld + k];
+                acc[a].x = fmaf(ra, x.x, acc[a].x);
+                acc[a].y = fmaf(ra, x.y, acc[a].y);
+                acc[a].z = fmaf(ra, x.z, acc[a].z);
+                acc[a].w = fmaf(ra, x.w, acc[a].w);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) *reinterpret_cast<float4*>(B + (4 * i4 + a) * ld + 4 * c) = acc[a];
+    }
+}
+
+// R <- 1.5 R - 0.5 (R R^T) R on the nc x nc rotation in LDS (stride ld).
+// G = R R^T goes to Gs (LDS, stride ld), T = G R to the device plane T
+// (stride ldg).
+__device__ void newton_schulz_rows(float* Rl, int ld, int nc, float* Gs, float* T, int ldg) {
+    const int n4 = (nc + 3) >> 2;
+    for (int t = threadIdx.x; t < n4 * n4; t += NT) {
+        const int i4 = t / n4, j4 = t - i4 * n4;
+        float acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+        for (int k4 = 0; k4 < n4; ++k4) {
+            float4 ra[4], rb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                ra[a] = *reinterpret_cast<const float4*>(Rl + (4 * i4 + a) * ld + 4 * k4);
+                rb[a] = *reinterpret_cast<const float4*>(Rl + (4 * j4 + a) * ld + 4 * k4);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = dot4(ra[a], rb[b], acc[a][b]);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            *reinterpret_cast<float4*>(Gs + (4 * i4 + a) * ld + 4 * j4) =
+                make_float4(acc[a][0], acc[a][1], acc[a][2], acc[a][3]);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n4 * n4; t += NT) {
+        const int i4 = t / n4, c = t - i4 * n4;
+        float4 acc[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc[a] = f4(0.f);
+        for (int k = 0; k < nc; ++k) {
+            const float4 x = *reinterpret_cast<const float4*>(Rl + k * ld + 4 * c);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const float g = Gs[(4 * i4 + a) * ld + k];
+                acc[a].x = fmaf(g, x.x, acc[a].x);
+                acc[a].y = fmaf(g, x.y, acc[a].y);
+                acc[a].z = fmaf(g, x.z, acc[a].z);
+                acc[a].w = fmaf(g, x.w, acc[a].w);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int row = 4 * i4 + a;
+            if (row < nc) *reinterpret_cast<float4*>(T + (size_t)row * ldg + 4 * c) = acc[a];
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nc * n4; e += NT) {
+        const int i = e / n4, c = e - i * n4;
+        float4* pr = reinterpret_cast<float4*>(Rl + i * ld + 4 * c);
+        const float4 r = *pr;
+        const float4 tt = *reinterpret_cast<const float4*>(T + (size_t)i * ldg + 4 * c);
+        float4 o;
+        o.x = fmaf(-0.5f, tt.x, 1.5f * r.x);
+        o.y = fmaf(-0.5f, tt.y, 1.5f * r.y);
+        o.z = fmaf(-0.5f, tt.z, 1.5f * r.z);
+        o.w = fmaf(-0.5f, tt.w, 1.5f * r.w);
+        *pr = o;
+    }
+    __syncthreads();
+}
+
+// Load the saved rotation (or the identity) into the R area: rows and
+// columns beyond nc are zero.
+__device__ void load_rotation(float* Rl, int ld, int nc, const float* V, int ldg, bool saved) {
+    const int nc4 = (nc + 3) & ~3;
+    const int ld4 = ld >> 2;
+    for (int e = threadIdx.x; e < nc4 * ld4; e += NT) {
+        const int i = e / ld4, c = e - i * ld4;
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = 4 * c + u;
+            v[u] = 0.f;
+            if (i < nc && j < nc) v[u] = saved ? V[(size_t)i * ldg + j] : (i == j ? 1.f : 0.f);
+        }
+        *reinterpret_cast<float4*>(Rl + i * ld + 4 * c) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    __syncthreads();
+}
+
+__device__ void save_rotation(const float* Rl, int ld, int nc, float* V, int ldg) {
+    for (int e = threadIdx.x; e < nc * nc; e += NT) {
+        const int i = e / nc, j = e - i * nc;
+        V[(size_t)i * ldg + j] = Rl[i * ld + j];
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // A-update: M = A - R - Y/mu, A <- S_{1/mu}(M)
 // ---------------------------------------------------------------------------
 
@@ -1262,8 +1470,10 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
     const double mu = st->mu;
     const float inv_mu = (float)(1.0 / mu);
     const bool tiled = d.sb > 0;
+    const bool warm = d.warm != 0;
     float* Bg = d.ws + NPLANES * np;
-    const SvtLds L = carve_for(d, lds);
+    float* Rl = nullptr;
+    const SvtLds L = warm ? carve_lds_warm(lds, nc, ld, d.tb, &Rl) : carve_for(d, lds);
 
     // M_k = A_k - J~perp(A_k + E_k - I) - Y_k/mu_k, with R = J~perp(A_k + E_k - I).
     for (int idx = tid; idx < nc * nr4; idx += NT) {
@@ -1278,10 +1488,25 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
         mm.z = fmaf(-y.z, inv_mu, a.z - r.z);
         mm.w = fmaf(-y.w, inv_mu, a.w - r.w);
         *reinterpret_cast<float4*>(M + o) = mm;
-        if (!tiled) *reinterpret_cast<float4*>(L.B + row * ld + 4 * c) = mm;
+        if (!tiled && !warm) *reinterpret_cast<float4*>(L.B + row * ld + 4 * c) = mm;
     }
     JacobiStats js{0, 0, 0};
-    if (tiled) {
+    if (warm) {
+        float* V = d.ws + PL_V * np;
+        const bool saved = st->warm_ok != 0;
+        load_rotation(Rl, ld, nc, V, ldg, saved);
+        if (saved && prm.ns_every > 0 && st->warm_count % prm.ns_every == 0)
+            newton_schulz_rows(Rl, ld, nc, L.B, d.ws + (PL_Q + 6) * np, ldg);
+        warm_start_rows(Rl, ld, M, ldg, L.B, nc, nr4);
+        clear_lds_padding(L.B, nc, ldg, ld);
+        __syncthreads();
+        jacobi_dispatch_warm(d.svt_cfg, L.B, Rl, nc, ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
+        save_rotation(Rl, ld, nc, V, ldg);
+        if (threadIdx.x == 0) {
+            st->warm_ok = 1;
+            st->warm_count += 1;
+        }
+    } else if (tiled) {
         __syncthreads();
         svd_rows(d, M, Bg, L, prm.jacobi_tol, prm.max_sweeps, js);
     } else {
@@ -1637,6 +1862,8 @@ __device__ void level_transition(const PatchDesc& d, PatchState* st) {
         st->inner = 0;
         st->done_inner = 0;
         st->done_outer = 0;
+        st->warm_ok = 0;
+        st->warm_count = 0;
     }
     __syncthreads();
 }

@@ -268,3 +268,50 @@ def test_ragged_shapes_fixed_iters(tilt, ctx, device, m, n, model):
     assert r["status"] == 0
     assert np.linalg.norm(r["A"] - ref.A) <= 1e-4 * np.linalg.norm(ref.A)
     assert O.tau_rel_err(r["tau"], ref.tau_px, m, n) <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# a5 warm: SVT started from the previous iteration's accumulated rotation
+# (svt_mode = 1).  It computes the same shrinkage, so the oracle and the
+# tolerances are those of the cold path.
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("cfg,idx,outer,inner", [(0, 0, 2, 25), (1, 0, 1, 40), (2, 19, 2, 20), (2, 11, 1, 30)])
+def test_warm_svt_fixed_iterations_match_oracle(tilt, ctx, device, cfg, idx, outer, inner):
+    p = ts.make_batch(cfg, [idx])[0]
+    tp = tilt.default_params(fixed_iters=1, max_outer=outer, max_inner=inner, lam=p.lam, svt_mode=1)
+    rc, res = solve_on_device(tilt, ctx, [p], device, tp)
+    r = res[0]
+    assert r["status"] == 0, r
+    ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
+    errA = np.linalg.norm(r["A"] - ref.A) / np.linalg.norm(ref.A)
+    assert errA <= 1e-4, errA
+    assert O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n) <= 1e-5
+    assert abs(r["objective"] - ref.objective) <= 1e-4 * ref.objective
+
+
+@pytest.mark.parametrize("cfg,idx", [(0, 1), (1, 0), (2, 2), (2, 8)])
+def test_warm_svt_full_solve_matches_oracle(tilt, ctx, device, cfg, idx):
+    p = ts.make_batch(cfg, [idx])[0]
+    tp = tilt.default_params(lam=p.lam, svt_mode=1)
+    rc, res = solve_on_device(tilt, ctx, [p], device, tp)
+    r = res[0]
+    assert r["status"] >= 0, r
+    ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
+    assert ref.outer_iters < tp.max_outer and r["outer_iters"] < tp.max_outer
+    assert O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n) <= 1e-4
+    assert abs(r["objective"] - ref.objective) <= 1e-4 * ref.objective
+    assert O.numerical_rank(r["A"]) == O.numerical_rank(ref.A)
+
+
+def test_warm_svt_needs_fewer_sweeps(tilt, ctx, device):
+    p = ts.make_batch(1, [0])[0]
+    cold = tilt.default_params(fixed_iters=1, max_outer=2, max_inner=60, lam=p.lam)
+    warm = tilt.default_params(fixed_iters=1, max_outer=2, max_inner=60, lam=p.lam, svt_mode=1)
+    _, rc = solve_on_device(tilt, ctx, [p], device, cold)
+    _, rw = solve_on_device(tilt, ctx, [p], device, warm)
+    sc = rc[0]["counters"]["jacobi_sweeps"] / rc[0]["counters"]["svt_calls"]
+    sw = rw[0]["counters"]["jacobi_sweeps"] / rw[0]["counters"]["svt_calls"]
+    assert sw < 0.7 * sc, (sw, sc)
+    assert np.linalg.norm(rw[0]["A"] - rc[0]["A"]) <= 2e-5 * np.linalg.norm(rc[0]["A"])
