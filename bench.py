@@ -52,18 +52,25 @@ def tau_rel_err(Ha, Hb, tau0, m, n):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def solve_flops(res, p):
+def solve_flops(res, p, warm=False):
     """Algorithmic FP32 flops of one patch's solve, from its work counters.
 
-    Jacobi: every examined pair costs three length-nr inner products (6 nr);
-    every rotated pair costs 6 nr more (two rows: 4 mul + 2 add per entry).
-    Shrinkage: C = X B^T and A = (C W) B over the k kept rows, 4 nc nr k.
-    Updates: about (20 + 8 p') flops per entry per inner iteration."""
+    Jacobi: every examined pair costs one length-nr inner product (2 nr; the
+    squared norms are updated in O(1) per rotation); every rotated pair
+    costs a 2x2 rotation of two length-nr rows (6 nr).  Shrinkage:
+    C = X B^T and A = (C W) B over the k kept rows, 4 nc nr k.  Updates:
+    about (20 + 8 p') flops per entry per inner iteration.  Warm start: the
+    product R M (2 nc^2 nr per SVT) and the rotation rows (6 nc per
+    rotation); the Newton-Schulz steps are not counted.  Pyramid levels are
+    counted at the level-0 shape (an upper bound)."""
     nr, nc = max(p.m, p.n), min(p.m, p.n)
     c = res["counters"]
     pp = p.model - 3
-    return (6.0 * nr * (c["jacobi_pairs"] + c["jacobi_rotations"]) + 4.0 * nc * nr * c["recon_rows"]
-            + (20.0 + 8.0 * pp) * nc * nr * c["inner_iters"])
+    f = (2.0 * nr * c["jacobi_pairs"] + 6.0 * nr * c["jacobi_rotations"] + 4.0 * nc * nr * c["recon_rows"]
+         + (20.0 + 8.0 * pp) * nc * nr * c["inner_iters"])
+    if warm:
+        f += 2.0 * nc * nc * nr * c["inner_iters"] + 6.0 * nc * c["jacobi_rotations"]
+    return f
 
 
 def profiled_traffic(workload: str):
@@ -93,9 +100,14 @@ def _oracle_worker(args):
     import oracle as O
     import tilt_synth as ts
 
+    prm_kw = dict(prm_kw)
+    levels = prm_kw.pop("levels", 1)
     p = ts.make_batch(cfg, [idx])[0]
     t0 = time.perf_counter()
-    r = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, O.Params(**prm_kw), lam=p.lam)
+    if levels > 1:
+        r, _ = O.pyramid.tilt_solve_pyramid(p.image, p.tau0, p.m, p.n, p.model, O.Params(**prm_kw), levels=levels)
+    else:
+        r = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, O.Params(**prm_kw), lam=p.lam)
     return time.perf_counter() - t0, r.outer_iters, sum(r.inner_iters)
 
 
@@ -122,6 +134,16 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=8, help="patches re-solved by the plain path")
     ap.add_argument("--cpu-sample", type=int, default=4, help="patches solved by the CPU oracle")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--svt-mode", type=int, default=0, choices=(0, 1),
+                    help="0: cold Jacobi SVT every iteration (the workload's definition); 1: warm start")
+    ap.add_argument("--pyramid", type=int, default=1, help="pyramid levels (1 = none)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving mode: Poisson arrivals through tilt_submit/tilt_poll (workload 4 by default)")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
+                    help="arrival window per rate in serving mode")
+    ap.add_argument("--serve-max-outer", type=int, default=20,
+                    help="outer iterations per pyramid level in serving mode")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the solve, copy a buffer of this many MiB on the device (a plain copy of "
                          "known size, used to calibrate HBM byte counters in profiles)")
@@ -139,6 +161,8 @@ def main():
     import tilt_synth as ts
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.serve:
+        return serve_main(args)
     dev = torch.device("cuda:0")
     names = ts.config_names()
     t_gen = time.perf_counter()
@@ -151,7 +175,7 @@ def main():
     outA = [torch.zeros((p.m, p.n), dtype=torch.float32, device=dev) for p in patches]
     outE = [torch.zeros((p.m, p.n), dtype=torch.float32, device=dev) for p in patches]
     lam = patches[0].lam if all(abs(p.lam - patches[0].lam) < 1e-15 for p in patches) else -1.0
-    prm = T.default_params(lam=lam)
+    prm = T.default_params(lam=lam, svt_mode=args.svt_mode, pyramid_levels=args.pyramid)
     ctx = T.Context(0)
     stream = torch.cuda.current_stream()
     Ap = [a.data_ptr() for a in outA]
@@ -205,7 +229,7 @@ def main():
     solve_ms = np.array([r["solve_ms"] for r in res])
     done_ms = np.array([r["done_ms"] for r in res])
 
-    flops = sum(solve_flops(r, p) for r, p in zip(res, patches))
+    flops = sum(solve_flops(r, p, warm=args.svt_mode == 1) for r, p in zip(res, patches))
     k_ms = float(np.mean(kernel_ms))
     achieved = flops / (k_ms * 1e-3) / 1e12
     outer = np.array([r["outer_iters"] for r in res])
@@ -216,7 +240,8 @@ def main():
     if not args.no_cpu and args.cpu_sample > 0:
         idx = (sample or list(range(len(patches))))[: args.cpu_sample]
         prm_kw = dict(eps1=prm.eps1, eps2=prm.eps2, eps_outer=prm.eps_outer, mu0=prm.mu0, rho0=prm.rho0,
-                      mu_max=prm.mu_max, max_inner=prm.max_inner, max_outer=prm.max_outer)
+                      mu_max=prm.mu_max, max_inner=prm.max_inner, max_outer=prm.max_outer,
+                      levels=args.pyramid)
         workers = len(idx)
         log(f"CPU oracle on {len(idx)} patches with {workers} worker processes ...")
         cwall, cout = cpu_baseline(args.workload, idx, prm_kw, workers)
@@ -252,7 +277,9 @@ def main():
             "n": p0.n if len({(p.m, p.n) for p in patches}) == 1 else "mixed",
             "model": "projective" if all(p.model == 8 for p in patches) else "mixed",
             "lambda": lam if lam > 0 else "1/sqrt(max(m,n))",
-            "svt": "cold one-sided Jacobi every inner iteration",
+            "svt": ("cold one-sided Jacobi every inner iteration" if args.svt_mode == 0
+                    else "one-sided Jacobi warm-started from the previous rotation"),
+            "pyramid_levels": args.pyramid,
             "eps1": prm.eps1, "eps2": prm.eps2, "eps_outer": prm.eps_outer, "rho0": prm.rho0,
         },
         "latency_ms": {
@@ -279,6 +306,109 @@ def main():
             "flops_per_launch": flops,
         },
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def serve_main(args):
+    """Serving workload: requests arrive as a Poisson process and go through
+    tilt_submit / tilt_poll (continuous batching on one GPU).  First the
+    saturation throughput (all requests submitted at once), then arrival
+    rates of 0.25, 0.5, 0.75 and 0.9 times it; latency is arrival -> result
+    seen by the polling host thread."""
+    import numpy as np
+    import torch
+
+    import paper_1205_5351_amd as T
+    import tilt_synth as ts
+
+    dev = torch.device("cuda:0")
+    names = ts.config_names()
+    wl = args.workload if args.workload != 1 else 4
+    patches = ts.make_config(wl, count=args.serve_requests)
+    imgs = [torch.from_numpy(p.image).to(dev) for p in patches]
+    probs = [T.make_problem(im.data_ptr(), p.height, p.width, p.width, p.m, p.n, p.model, p.tau0)
+             for im, p in zip(imgs, patches)]
+    outA = [torch.zeros((p.m, p.n), dtype=torch.float32, device=dev) for p in patches]
+    outE = [torch.zeros((p.m, p.n), dtype=torch.float32, device=dev) for p in patches]
+    levels = args.pyramid if args.pyramid > 1 else 3
+    prm = T.default_params(svt_mode=args.svt_mode, pyramid_levels=levels, max_outer=args.serve_max_outer)
+    ctx = T.Context(0)
+    torch.cuda.synchronize()
+
+    def run(arrivals):
+        """arrivals: seconds after start for request k (k cycles over the set)."""
+        pending = {}
+        lat, solve_ms, statuses = [], [], []
+        t0 = time.perf_counter()
+        nxt = 0
+        last_log = t0
+        while nxt < len(arrivals) or pending:
+            now = time.perf_counter() - t0
+            while nxt < len(arrivals) and arrivals[nxt] <= now:
+                k = nxt % len(probs)
+                t = ctx.submit(probs[k], prm, outA[k].data_ptr(), outE[k].data_ptr())
+                pending[t] = arrivals[nxt]
+                nxt += 1
+            for t in list(pending):
+                out = ctx.poll(t)
+                if out is not None:
+                    done = time.perf_counter() - t0
+                    lat.append(1000.0 * (done - pending.pop(t)))
+                    solve_ms.append(out[1]["solve_ms"])
+                    statuses.append(out[0])
+            if time.perf_counter() - last_log > 20:
+                log(f"  {len(lat)} done, {len(pending)} in flight")
+                last_log = time.perf_counter()
+            time.sleep(0.0005)
+        wall = time.perf_counter() - t0
+        return wall, np.array(lat), np.array(solve_ms), statuses
+
+    n = len(probs)
+    log(f"serving: {n} requests of '{names[wl]}', {levels} pyramid levels")
+    run([0.0] * min(n, 16))  # warm-up
+    wall, lat, sms, st = run([0.0] * n)
+    sat = n / wall
+    log(f"saturation: {sat:.2f} requests/s (all {n} submitted at once, {wall:.1f} s)")
+    rng = np.random.default_rng(20250)
+    rates = []
+    for f in (0.25, 0.5, 0.75, 0.9):
+        lam_arr = f * sat
+        count = max(8, int(lam_arr * args.serve_seconds))
+        arrivals = np.cumsum(rng.exponential(1.0 / lam_arr, size=count)).tolist()
+        w, l, s_ms, stt = run(arrivals)
+        rates.append({"load": f, "arrival_per_s": round(lam_arr, 3), "requests": count,
+                      "patches_per_s": round(count / w, 3),
+                      "latency_p50_ms": round(float(np.percentile(l, 50)), 1),
+                      "latency_p99_ms": round(float(np.percentile(l, 99)), 1),
+                      "solve_p50_ms": round(float(np.percentile(s_ms, 50)), 1),
+                      "ok": int(sum(1 for x in stt if x >= 0))})
+        log(f"load {f}: {rates[-1]}")
+    headline = next(r for r in rates if r["load"] == 0.75)
+    out = {
+        "metric": METRIC,
+        "value": round(sat, 3),
+        "unit": "patches/s",
+        "n_gpus": 1,
+        "steps": len(rates),
+        "warmup": 1,
+        "ms_per_step": round(1000.0 * wall / n, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": names[wl], "requests": n, "pyramid_levels": levels,
+                   "max_outer_per_level": args.serve_max_outer,
+                   "svt": "cold" if args.svt_mode == 0 else "warm",
+                   "value_is": "saturation throughput (all requests in flight)"},
+        "latency_ms": {"p50_at_0.75": headline["latency_p50_ms"], "p99_at_0.75": headline["latency_p99_ms"],
+                       "saturation_p50": round(float(np.percentile(lat, 50)), 1),
+                       "saturation_p99": round(float(np.percentile(lat, 99)), 1)},
+        "rates": rates,
+        "roofline": None,
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
