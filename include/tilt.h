@@ -246,6 +246,19 @@ int tilt_svt_batch(tilt_ctx* ctx, const float* M, float* A, float* sigma, int co
 int tilt_warp_jacobian(tilt_ctx* ctx, const tilt_problem* probs, const double* taus, int count,
                        float* I_out, float* J_out, void* hip_stream);
 
+/* The LADMAP inner loop alone (Sec. 3.2 in the form of Sec. 4.2; the
+ * setting of Table 1): for `count` problems of one shape,
+ *     min ||A||_* + lambda ||E||_1  s.t.  I + J dtau = A + E
+ * with I (count x m x n, row-major) and J (count x p x m x n, one m x n
+ * plane per column) given as DEVICE arrays, 1 <= p <= 5.  No
+ * normalisation and no extra constraints; starts from A = I, E = Y = 0
+ * with mu_0 from params (<= 0: 1.25/||I||_2).  A, E (count x m x n,
+ * DEVICE) may be NULL.  Fills inner_iters_total, objective, mu, cond1,
+ * cond2, svt_rank, status, solve_ms and the counters of results[i]; tau is
+ * zero.  max(m, n) <= 512; pyramid_levels must be 1. */
+int tilt_inner_batch(tilt_ctx* ctx, const float* I, const float* J, int count, int m, int n, int p,
+                     const tilt_params* prm, float* A, float* E, tilt_result* results, void* hip_stream);
+
 /* Pyramid levels 1..levels-1 of one image (DEVICE pointers), as used when
  * pyramid_levels = levels: level l (ceil(H/2^l) x ceil(W/2^l), row-major,
  * contiguous) follows level l-1 in `out`.  levels in 2..4. */

@@ -920,4 +920,81 @@ int tilt_pyramid(tilt_ctx* ctx, const float* image, int height, int width, long 
     return TILT_OK;
 }
 
+int tilt_inner_batch(tilt_ctx* ctx, const float* I, const float* J, int count, int m, int n, int p,
+                     const tilt_params* prm, float* A, float* E, tilt_result* results, void* hip_stream) {
+    if (!ctx || !I || !J || !prm || !results || count < 0 || m < 2 || n < 2 || p < 1 || p > MAXPP)
+        return TILT_ERR_ARG;
+    int st = validate_params(prm);
+    if (st != TILT_OK) return st;
+    if (prm->pyramid_levels > 1) return TILT_ERR_ARG;
+    if (count == 0) return TILT_OK;
+    ShapeCfg sc{};
+    st = shape_config(m, n, &sc);
+    if (st != TILT_OK) return st;
+    const bool warm = prm->svt_mode == 1 && sc.warm_lds > 0;
+    const size_t lds = warm ? sc.warm_lds : sc.lds;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    const size_t per = (sc.ws_floats + 63) & ~(size_t)63;
+    if (per * count * sizeof(float) > ctx->budget) return TILT_ERR_NOMEM;
+    if (ctx->ws.reserve(per * count * sizeof(float)) != hipSuccess ||
+        ctx->descs.reserve(sizeof(PatchDesc) * count) != hipSuccess ||
+        ctx->states.reserve(sizeof(PatchState) * count) != hipSuccess)
+        return TILT_ERR_NOMEM;
+    const size_t mn = (size_t)m * n;
+    std::vector<PatchDesc> descs(count);
+    std::vector<PatchState> states(count);
+    for (int i = 0; i < count; ++i) {
+        PatchDesc& d = descs[i];
+        std::memset(&d, 0, sizeof(d));
+        d.m = m;
+        d.n = n;
+        d.model = p + 3;
+        d.pp = p;
+        d.nc = sc.nc;
+        d.nr = sc.nr;
+        d.ldg = sc.ldg;
+        d.colmajor = sc.colmajor;
+        d.ld = sc.ld;
+        d.svt_cfg = sc.cfg;
+        d.warm = warm ? 1 : 0;
+        d.tb = warm ? sc.warm_tb : sc.tb;
+        d.sb = sc.sb;
+        d.nsb = sc.nsb;
+        d.ncp = sc.ncp;
+        d.s = 1.0;
+        d.lam = prm->lambda > 0 ? prm->lambda : 1.0 / std::sqrt((double)std::max(m, n));
+        d.ws = reinterpret_cast<float*>(ctx->ws.p) + per * i;
+        d.A_out = A ? A + mn * i : nullptr;
+        d.E_out = E ? E + mn * i : nullptr;
+        std::memset(&states[i], 0, sizeof(PatchState));
+        states[i].geo[2] = 1.0;
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->descs.p, descs.data(), sizeof(PatchDesc) * count, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(ctx->states.p, states.data(), sizeof(PatchState) * count, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventRecord(ctx->ev0, stream));
+    HIP_TRY(launch_inner(reinterpret_cast<const PatchDesc*>(ctx->descs.p), reinterpret_cast<PatchState*>(ctx->states.p),
+                         to_solver(prm), I, J, count, lds, stream));
+    HIP_TRY(hipEventRecord(ctx->ev1, stream));
+    HIP_TRY(hipMemcpyAsync(states.data(), ctx->states.p, sizeof(PatchState) * count, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->last_kernel_ms = ms;
+    int worst = TILT_OK;
+    long long t0 = states[0].t_begin;
+    for (int i = 1; i < count; ++i) t0 = std::min(t0, states[i].t_begin);
+    for (int i = 0; i < count; ++i) {
+        tilt_result& r = results[i];
+        float* hA = r.A;
+        float* hE = r.E;
+        fill_result(descs[i], states[i], &r, ctx->wall_rate_khz, t0);
+        for (int k = 0; k < 9; ++k) r.tau[k] = 0.0;
+        r.A = hA;
+        r.E = hE;
+        worst = worse(worst, r.status);
+    }
+    return worst;
+}
+
 }  // extern "C"

@@ -193,6 +193,8 @@ hipError_t launch_update(const PatchDesc* d, PatchState* st, const SolverParams&
 hipError_t launch_dtau(const PatchDesc* d, PatchState* st, const SolverParams& prm, hipStream_t s);
 hipError_t launch_finalize(const PatchDesc* d, PatchState* st, int last, hipStream_t s);
 hipError_t launch_mark_end(PatchState* st, hipStream_t s);
+hipError_t launch_inner(const PatchDesc* d, PatchState* st, const SolverParams& prm, const float* I, const float* J,
+                        int count, size_t lds, hipStream_t s);
 hipError_t launch_step1(const PatchDesc* d, PatchState* st, int count, float* I_out, float* J_out,
                         hipStream_t s);
 hipError_t launch_svt_jobs(const SvtJob* jobs, int count, const SvtShape& shape, float tol,

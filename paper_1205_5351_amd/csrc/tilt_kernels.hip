@@ -167,33 +167,36 @@ struct JacobiStats {
 };
 
 // Rotation that zeroes a.b for norms al = ||a||^2, be = ||b||^2 and
-// ga = a.b (Hestenes / Rutishauser: t = sgn(z)/(|z| + sqrt(1 + z^2)),
-// z = (be - al)/(2 ga)), returned as t, s = sin = t/r and the half-angle
-// tangent tau = s/(1 + c) = t/(1 + r), r = sqrt(1 + t^2).  The rows are
-// then updated as a' = a - s (b + tau a), b' = b + s (a - tau b), whose
-// effective cosine 1 - s tau never rounds to 1 for small angles.  Any t
-// gives an orthogonal rotation, so t comes from hardware estimates; r, s
-// and tau each get one Newton correction (r from the residual of
-// r^2 = 1 + t^2 without rounding 1 + t^2) so that the transformation stays
-// orthogonal to within rounding with no systematic shrink or growth of the
-// rows over the thousands of rotations of a decomposition.
+// ga = a.b (Hestenes / Rutishauser), returned as t = tan of the angle,
+// s = sin = t/r and the half-angle tangent tau = s/(1 + c) = t/(1 + r),
+// r = sqrt(1 + t^2).  With d = be - al, t = sgn(d) 2 ga/(|d| + sqrt(d^2 +
+// 4 ga^2)), the smaller root of the rotation's quadratic.  The rows are
+// updated as a' = a - s (b + tau a), b' = b + s (a - tau b), whose effective
+// cosine 1 - s tau never rounds to 1 for small angles.  Any t is a valid
+// rotation, so t comes straight from hardware estimates; 1/r (reciprocal
+// square-root estimate) and tau (reciprocal estimate) each get one Newton
+// correction, which keeps the transformation orthogonal to rounding level
+// with no systematic shrink or growth of the rows over the thousands of
+// rotations of a decomposition.  Four transcendental instructions per pair.
 __device__ inline void jacobi_rotation(float al, float be, float ga, float& sn, float& ta, float& tn) {
-    const float zeta = (be - al) * __builtin_amdgcn_rcpf(2.0f * ga);
-    const float root = __builtin_amdgcn_sqrtf(fmaf(zeta, zeta, 1.0f));
-    const float t = copysignf(__builtin_amdgcn_rcpf(fabsf(zeta) + root), zeta);
-    float r = __builtin_amdgcn_sqrtf(fmaf(t, t, 1.0f));
-    const float res = fmaf(t, t, fmaf(-r, r, 1.0f));
-    r = fmaf(0.5f * res, __builtin_amdgcn_rcpf(r), r);
-    const float rr = __builtin_amdgcn_rcpf(r);
-    float s = t * rr;
-    s = fmaf(fmaf(-s, r, t), rr, s);
-    const float onep = 1.0f + r;
-    const float ro = __builtin_amdgcn_rcpf(onep);
-    float h = t * ro;
-    h = fmaf(fmaf(-h, onep, t), ro, h);
-    sn = s;
-    ta = h;
+    const float d = be - al;
+    const float dd = __builtin_amdgcn_sqrtf(fmaf(d, d, 4.0f * ga * ga));
+    const float t = copysignf(1.0f, d) * (2.0f * ga) * __builtin_amdgcn_rcpf(fabsf(d) + dd);
+    const float q = fmaf(t, t, 1.0f);
+    float y = __builtin_amdgcn_rsqf(q);
+    y = fmaf(y, fmaf(-0.5f * q * y, y, 0.5f), y);
+    const float r = q * y;
+    const float op = 1.0f + r;
+    const float ro = __builtin_amdgcn_rcpf(op);
+    const float h = t * ro;
+    sn = t * y;
+    ta = fmaf(fmaf(-h, op, t), ro, h);
     tn = t;
+}
+
+// Rotation test: |a.b| > tol ||a|| ||b||, squared (no square roots).
+__device__ inline bool needs_rotation(float ga, float nx, float ny, float tol) {
+    return ga * ga > (tol * tol) * (nx * ny);
 }
 
 __device__ inline float dot4(const float4& a, const float4& b, float acc) {
@@ -222,7 +225,7 @@ template <int LPP, int NCH>
 __device__ inline bool rotate_rows(float4* x, float4* y, float& nx, float& ny, float tol, float& sn, float& ta) {
     sn = ta = 0.f;
     const float ga = group_dot<LPP, NCH>(x, y);
-    if (!(fabsf(ga) > tol * (__builtin_amdgcn_sqrtf(nx) * __builtin_amdgcn_sqrtf(ny)))) return false;
+    if (!needs_rotation(ga, nx, ny, tol)) return false;
     float t;
     jacobi_rotation(nx, ny, ga, sn, ta, t);
 #pragma unroll
@@ -266,8 +269,8 @@ __device__ inline void rotate_two(float4* x1, float4* y1, float& nx1, float& ny1
     }
     const float g1 = group_sum<LPP>(p0 + p1);
     const float g2 = group_sum<LPP>(q0 + q1);
-    f1 = fabsf(g1) > tol * (__builtin_amdgcn_sqrtf(nx1) * __builtin_amdgcn_sqrtf(ny1));
-    f2 = fabsf(g2) > tol * (__builtin_amdgcn_sqrtf(nx2) * __builtin_amdgcn_sqrtf(ny2));
+    f1 = needs_rotation(g1, nx1, ny1, tol);
+    f2 = needs_rotation(g2, nx2, ny2, tol);
     if (!(f1 || f2)) return;
     float t1, t2;
     jacobi_rotation(nx1, ny1, f1 ? g1 : 1.0f, s1, h1, t1);
@@ -1045,12 +1048,13 @@ __device__ inline void solve_row_upper(const double* R, int pp, const double* y,
 // Step 1 + constraints + warm start
 // ---------------------------------------------------------------------------
 
+__device__ void dev_factor(const PatchDesc& d, PatchState* st, const SolverParams& prm, float* lds,
+                           const double* gram);
+
 __device__ void dev_setup(const PatchDesc& d, PatchState* st, const SolverParams& prm, float* lds) {
     __shared__ double sh_sIJ[MAXP];
     __shared__ double sh_norm;
     __shared__ double sh_NQ[MAXP * MAXPP];
-    __shared__ double sh_R[MAXPP * MAXPP];
-    __shared__ double sh_R1[MAXPP * MAXPP];
     __shared__ int sh_fail;
 
     const int tid = threadIdx.x;
@@ -1155,6 +1159,28 @@ __device__ void dev_setup(const PatchDesc& d, PatchState* st, const SolverParams
                 if (l <= l2 && l2 < pp) gram[tri(l, l2)] += jt[l] * jt[l2];
     }
     block_sum_d<NTRI>(gram);
+    dev_factor(d, st, prm, lds, gram);
+}
+
+// Passes C-E of the set-up, shared with the inner-loop-only entry: given
+// the Gram sums of J~ (upper triangle, FP64), the Cholesky-QR2 basis Qb of
+// J~ (stored over J~), the factor R (J~ = Qb R), the warm-start projection
+// of Y, R_0 = J~perp(A + E - I), c = ||J~perp I||_F and mu_0.
+__device__ void dev_factor(const PatchDesc& d, PatchState* st, const SolverParams& prm, float* lds,
+                           const double* gram) {
+    __shared__ double sh_R[MAXPP * MAXPP];
+    __shared__ double sh_R1[MAXPP * MAXPP];
+    __shared__ int sh_fail;
+    const int tid = threadIdx.x;
+    const int pp = d.pp;
+    const int ldg = d.ldg, nr = d.nr, nc = d.nc;
+    const size_t np = (size_t)nc * ldg;
+    float* I = d.ws + PL_I * np;
+    float* A = d.ws + PL_A * np;
+    float* E = d.ws + PL_E * np;
+    float* Y = d.ws + PL_Y * np;
+    float* R = d.ws + PL_R * np;
+    float* Qp = d.ws + PL_Q * np;
     if (tid == 0) {
         double G[MAXPP * MAXPP];
         for (int l = 0; l < MAXPP; ++l)
@@ -1176,8 +1202,9 @@ __device__ void dev_setup(const PatchDesc& d, PatchState* st, const SolverParams
     }
 
     // Pass C: second Gram of J~ R1^{-1} (Cholesky-QR, second pass).
+    double gram2[NTRI];
 #pragma unroll
-    for (int k = 0; k < NTRI; ++k) gram[k] = 0.0;
+    for (int k = 0; k < NTRI; ++k) gram2[k] = 0.0;
     for (size_t e = tid; e < np; e += NT) {
         const int row = (int)(e / ldg), col = (int)(e - (size_t)row * ldg);
         if (col >= nr) continue;
@@ -1189,15 +1216,15 @@ __device__ void dev_setup(const PatchDesc& d, PatchState* st, const SolverParams
         for (int l = 0; l < MAXPP; ++l)
             #pragma unroll
             for (int l2 = 0; l2 < MAXPP; ++l2)
-                if (l <= l2 && l2 < pp) gram[tri(l, l2)] += x[l] * x[l2];
+                if (l <= l2 && l2 < pp) gram2[tri(l, l2)] += x[l] * x[l2];
     }
-    block_sum_d<NTRI>(gram);
+    block_sum_d<NTRI>(gram2);
     if (tid == 0) {
         double G[MAXPP * MAXPP], R2[MAXPP * MAXPP];
         for (int l = 0; l < MAXPP; ++l)
             for (int l2 = l; l2 < MAXPP; ++l2) {
-                G[l * MAXPP + l2] = gram[tri(l, l2)];
-                G[l2 * MAXPP + l] = gram[tri(l, l2)];
+                G[l * MAXPP + l2] = gram2[tri(l, l2)];
+                G[l2 * MAXPP + l] = gram2[tri(l, l2)];
             }
         const bool ok = cholesky_upper(G, pp, R2);
         sh_fail = ok ? 0 : 1;
@@ -1303,6 +1330,59 @@ __device__ void dev_setup(const PatchDesc& d, PatchState* st, const SolverParams
         }
     }
     __syncthreads();
+}
+
+// Inner loop alone (the setting of Table 1): I (row-major m x n) and the p
+// columns of J (parameter-major, p x m x n) are given; no normalisation and
+// no extra constraints (J~ = J, p <= 5); A = I, E = Y = 0; then the
+// factorisation of the set-up.
+__device__ void dev_setup_given(const PatchDesc& d, PatchState* st, const SolverParams& prm, float* lds,
+                                const float* Iin, const float* Jin) {
+    const int tid = threadIdx.x;
+    const int pp = d.pp;
+    const int ldg = d.ldg, nr = d.nr, nc = d.nc;
+    const size_t np = (size_t)nc * ldg;
+    const size_t mn = (size_t)d.m * d.n;
+    float* I = d.ws + PL_I * np;
+    float* A = d.ws + PL_A * np;
+    float* E = d.ws + PL_E * np;
+    float* Y = d.ws + PL_Y * np;
+    float* Qp = d.ws + PL_Q * np;
+    double gram[NTRI];
+#pragma unroll
+    for (int k = 0; k < NTRI; ++k) gram[k] = 0.0;
+    for (size_t e = tid; e < np; e += NT) {
+        const int row = (int)(e / ldg), col = (int)(e - (size_t)row * ldg);
+        if (col >= nr) {
+            I[e] = A[e] = E[e] = Y[e] = 0.f;
+#pragma unroll
+            for (int l = 0; l < MAXPP; ++l) if (l < pp) Qp[l * np + e] = 0.f;
+            continue;
+        }
+        int i, j;
+        xlayout_to_ij(d, row, col, i, j);
+        const size_t src = (size_t)i * d.n + j;
+        const float iv = Iin[src];
+        I[e] = iv;
+        A[e] = iv;
+        E[e] = 0.f;
+        Y[e] = 0.f;
+        double jt[MAXPP];
+#pragma unroll
+        for (int l = 0; l < MAXPP; ++l)
+            if (l < pp) {
+                const float f = Jin[(size_t)l * mn + src];
+                Qp[l * np + e] = f;
+                jt[l] = (double)f;
+            }
+#pragma unroll
+        for (int l = 0; l < MAXPP; ++l)
+#pragma unroll
+            for (int l2 = 0; l2 < MAXPP; ++l2)
+                if (l <= l2 && l2 < pp) gram[tri(l, l2)] += jt[l] * jt[l2];
+    }
+    block_sum_d<NTRI>(gram);
+    dev_factor(d, st, prm, lds, gram);
 }
 
 // ---------------------------------------------------------------------------
@@ -2028,6 +2108,32 @@ __global__ void __launch_bounds__(NT) k_finalize(const PatchDesc* dp, PatchState
     if (threadIdx.x == 0 && last) st->t_end = (long long)wall_clock64();
 }
 
+// Inner loop alone for `count` problems of one shape (one workgroup each).
+__global__ void __launch_bounds__(NT) k_inner(const PatchDesc* descs, PatchState* states, SolverParams prm,
+                                               const float* Iall, const float* Jall) {
+    __shared__ int sh_flag;
+    float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
+    const int idx = blockIdx.x;
+    PatchState* st = states + idx;
+    const PatchDesc d = desc_at_level(descs + idx, st);
+    const size_t mn = (size_t)d.m * d.n;
+    if (threadIdx.x == 0) st->t_begin = (long long)wall_clock64();
+    dev_setup_given(d, st, prm, lds, Iall + idx * mn, Jall + (size_t)idx * d.pp * mn);
+    if (threadIdx.x == 0) sh_flag = st->status < 0;
+    __syncthreads();
+    if (!sh_flag) {
+        for (;;) {
+            dev_svt(d, st, prm, lds);
+            dev_update(d, st, prm);
+            if (threadIdx.x == 0) sh_flag = st->done_inner;
+            __syncthreads();
+            if (sh_flag) break;
+        }
+    }
+    dev_finalize(d, st);
+    if (threadIdx.x == 0) st->t_end = (long long)wall_clock64();
+}
+
 __global__ void __launch_bounds__(NT) k_mark_end(PatchState* st) {
     if (threadIdx.x == 0) st->t_end = (long long)wall_clock64();
 }
@@ -2228,6 +2334,14 @@ hipError_t launch_dtau(const PatchDesc* d, PatchState* st, const SolverParams& p
 
 hipError_t launch_finalize(const PatchDesc* d, PatchState* st, int last, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NT), 0, s, d, st, last);
+    return hipGetLastError();
+}
+
+hipError_t launch_inner(const PatchDesc* d, PatchState* st, const SolverParams& prm, const float* I, const float* J,
+                        int count, size_t lds, hipStream_t s) {
+    hipError_t e = set_lds((const void*)k_inner, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_inner, dim3(count), dim3(NT), lds, s, d, st, prm, I, J);
     return hipGetLastError();
 }
 

@@ -164,12 +164,16 @@ _lib.tilt_serve_stop.restype = C.c_int
 _lib.tilt_pyramid.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_longlong, C.c_void_p, C.c_int,
                               C.c_void_p]
 _lib.tilt_pyramid.restype = C.c_int
+_lib.tilt_inner_batch.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                                  C.POINTER(Params), C.c_void_p, C.c_void_p, C.POINTER(Result), C.c_void_p]
+_lib.tilt_inner_batch.restype = C.c_int
 
 EXPORTS = [
     "tilt_default_params", "tilt_status_string", "tilt_version", "tilt_tau_from_quad", "tilt_solve",
     "tilt_ctx_create", "tilt_ctx_destroy", "tilt_workspace_bytes", "tilt_solve_batch",
     "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_warp_jacobian", "tilt_last_error",
     "tilt_ctx_last_kernel_ms", "tilt_submit", "tilt_poll", "tilt_serve_stop", "tilt_pyramid",
+    "tilt_inner_batch",
 ]
 
 
@@ -380,6 +384,19 @@ class Context:
         rc = _lib.tilt_serve_stop(self._h)
         if rc != TILT_OK:
             raise TiltError(rc, "tilt_serve_stop")
+
+    def inner_batch(self, I_ptr: int, J_ptr: int, count: int, m: int, n: int, p: int,
+                    params: Optional[Params] = None, A_ptr: int = 0, E_ptr: int = 0, stream=None):
+        """LADMAP inner loop alone on given I (count x m x n) and J (count x p x m x n)."""
+        prm = params if params is not None else default_params()
+        rarr = (Result * count)()
+        rc = _lib.tilt_inner_batch(self._h, C.c_void_p(int(I_ptr)), C.c_void_p(int(J_ptr)), int(count), int(m),
+                                   int(n), int(p), C.byref(prm), C.c_void_p(int(A_ptr)) if A_ptr else None,
+                                   C.c_void_p(int(E_ptr)) if E_ptr else None, rarr,
+                                   C.c_void_p(_stream_ptr(stream)))
+        if rc < 0 and rc not in (TILT_ERR_SINGULAR, TILT_ERR_NONFINITE):
+            raise TiltError(rc, "tilt_inner_batch")
+        return rc, [result_dict(rarr[i]) for i in range(count)]
 
     def pyramid(self, image_ptr: int, height: int, width: int, row_stride: int, out_ptr: int, levels: int,
                 stream=None):

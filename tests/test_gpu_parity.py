@@ -315,3 +315,46 @@ def test_warm_svt_needs_fewer_sweeps(tilt, ctx, device):
     sw = rw[0]["counters"]["jacobi_sweeps"] / rw[0]["counters"]["svt_calls"]
     assert sw < 0.7 * sc, (sw, sc)
     assert np.linalg.norm(rw[0]["A"] - rc[0]["A"]) <= 2e-5 * np.linalg.norm(rc[0]["A"])
+
+
+# ---------------------------------------------------------------------------
+# The LADMAP inner loop alone (the setting of Table 1; its random inputs'
+# distributions are not given, so the table's values stay unpinned).
+# ---------------------------------------------------------------------------
+
+
+def _inner_ref(I, J, prm, lam):
+    mn = I.size
+    Jm = J.reshape(J.shape[0], mn).T.astype(np.float64)
+    Jp = O.Annihilator(Jm)
+    I64 = I.astype(np.float64)
+    Z = np.zeros_like(I64)
+    return O.ladmap_inner(I64, Jp, lam, I64, Z, Z, prm)
+
+
+@pytest.mark.parametrize("m,n,p,fixed", [(10, 10, 5, True), (50, 50, 5, True), (37, 81, 3, True),
+                                         (100, 100, 5, False), (50, 50, 5, False), (200, 170, 5, True)])
+def test_inner_loop_alone_matches_oracle(tilt, ctx, device, m, n, p, fixed):
+    import torch
+
+    count = 3
+    Is, Js = zip(*[ts.inner_problem(k, m, n, p) for k in range(count)])
+    dI = to_device(np.stack(Is), device)
+    dJ = to_device(np.stack(Js), device)
+    dA = torch.zeros_like(dI)
+    dE = torch.zeros_like(dI)
+    tp = tilt.default_params(fixed_iters=1 if fixed else 0, max_inner=25 if fixed else 2000)
+    rc, res = ctx.inner_batch(dI.data_ptr(), dJ.data_ptr(), count, m, n, p, tp, dA.data_ptr(), dE.data_ptr())
+    A = dA.cpu().numpy()
+    lam = 1.0 / math.sqrt(max(m, n))
+    for k in range(count):
+        ref = _inner_ref(Is[k], Js[k], oracle_params(O, tp), lam)
+        r = res[k]
+        assert r["status"] >= 0
+        assert np.linalg.norm(A[k] - ref.A) <= 1e-4 * np.linalg.norm(ref.A)
+        obj = O.objective(ref.A, ref.E, lam)
+        assert abs(r["objective"] - obj) <= 1e-4 * obj
+        if fixed:
+            assert r["inner_iters_total"] == 25
+        else:
+            assert abs(r["inner_iters_total"] - ref.iters) <= 2, (r["inner_iters_total"], ref.iters)

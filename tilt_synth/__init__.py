@@ -15,4 +15,5 @@ from .textures import (  # noqa: F401
     config_names,
     MASTER_SEED,
     patch_rng,
+    inner_problem,
 )

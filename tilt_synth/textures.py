@@ -252,3 +252,14 @@ def make_config(config_index: int, count: Optional[int] = None, start: int = 0) 
 
 def make_batch(config_index: int, indices) -> List[Patch]:
     return [_config_patch(config_index, int(i)) for i in indices]
+
+
+def inner_problem(index: int, m: int, n: int, p: int = 5):
+    """Inputs of the inner-loop-only workload (the setting of Table 1, whose
+    distributions the paper does not state): I ~ U(0, 1) entries (m x n) and
+    J with N(0, 1) entries (p planes of m x n), float32, seeded by the
+    workload index 5 and `index`."""
+    rng = patch_rng(5, index * 100003 + m * 1009 + n * 13 + p)
+    I = rng.uniform(0.0, 1.0, (m, n)).astype(np.float32)
+    J = rng.standard_normal((p, m, n)).astype(np.float32)
+    return I, J
