@@ -277,31 +277,37 @@ __device__ inline void rotate_two(float4* x1, float4* y1, float& nx1, float& ny1
     jacobi_rotation(nx2, ny2, f2 ? g2 : 1.0f, s2, h2, t2);
     if (!f1) s1 = h1 = t1 = 0.f;
     if (!f2) s2 = h2 = t2 = 0.f;
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        const float4 a = x1[c], b = y1[c], u = x2[c], v = y2[c];
-        x1[c].x = fmaf(-s1, fmaf(h1, a.x, b.x), a.x);
-        x1[c].y = fmaf(-s1, fmaf(h1, a.y, b.y), a.y);
-        x1[c].z = fmaf(-s1, fmaf(h1, a.z, b.z), a.z);
-        x1[c].w = fmaf(-s1, fmaf(h1, a.w, b.w), a.w);
-        x2[c].x = fmaf(-s2, fmaf(h2, u.x, v.x), u.x);
-        x2[c].y = fmaf(-s2, fmaf(h2, u.y, v.y), u.y);
-        x2[c].z = fmaf(-s2, fmaf(h2, u.z, v.z), u.z);
-        x2[c].w = fmaf(-s2, fmaf(h2, u.w, v.w), u.w);
-        y1[c].x = fmaf(s1, fmaf(-h1, b.x, a.x), b.x);
-        y1[c].y = fmaf(s1, fmaf(-h1, b.y, a.y), b.y);
-        y1[c].z = fmaf(s1, fmaf(-h1, b.z, a.z), b.z);
-        y1[c].w = fmaf(s1, fmaf(-h1, b.w, a.w), b.w);
-        y2[c].x = fmaf(s2, fmaf(-h2, v.x, u.x), v.x);
-        y2[c].y = fmaf(s2, fmaf(-h2, v.y, u.y), v.y);
-        y2[c].z = fmaf(s2, fmaf(-h2, v.z, u.z), v.z);
-        y2[c].w = fmaf(s2, fmaf(-h2, v.w, u.w), v.w);
-    }
+    // Separate branches: a wave in which no group rotates one of the two
+    // pairs skips that pair's row updates (common in the last sweeps).
     if (f1) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const float4 a = x1[c], b = y1[c];
+            x1[c].x = fmaf(-s1, fmaf(h1, a.x, b.x), a.x);
+            x1[c].y = fmaf(-s1, fmaf(h1, a.y, b.y), a.y);
+            x1[c].z = fmaf(-s1, fmaf(h1, a.z, b.z), a.z);
+            x1[c].w = fmaf(-s1, fmaf(h1, a.w, b.w), a.w);
+            y1[c].x = fmaf(s1, fmaf(-h1, b.x, a.x), b.x);
+            y1[c].y = fmaf(s1, fmaf(-h1, b.y, a.y), b.y);
+            y1[c].z = fmaf(s1, fmaf(-h1, b.z, a.z), b.z);
+            y1[c].w = fmaf(s1, fmaf(-h1, b.w, a.w), b.w);
+        }
         nx1 = fmaxf(fmaf(-t1, g1, nx1), 0.f);
         ny1 = fmaxf(fmaf(t1, g1, ny1), 0.f);
     }
     if (f2) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const float4 u = x2[c], v = y2[c];
+            x2[c].x = fmaf(-s2, fmaf(h2, u.x, v.x), u.x);
+            x2[c].y = fmaf(-s2, fmaf(h2, u.y, v.y), u.y);
+            x2[c].z = fmaf(-s2, fmaf(h2, u.z, v.z), u.z);
+            x2[c].w = fmaf(-s2, fmaf(h2, u.w, v.w), u.w);
+            y2[c].x = fmaf(s2, fmaf(-h2, v.x, u.x), v.x);
+            y2[c].y = fmaf(s2, fmaf(-h2, v.y, u.y), v.y);
+            y2[c].z = fmaf(s2, fmaf(-h2, v.z, u.z), v.z);
+            y2[c].w = fmaf(s2, fmaf(-h2, v.w, u.w), v.w);
+        }
         nx2 = fmaxf(fmaf(-t2, g2, nx2), 0.f);
         ny2 = fmaxf(fmaf(t2, g2, ny2), 0.f);
     }

@@ -357,4 +357,37 @@ def test_inner_loop_alone_matches_oracle(tilt, ctx, device, m, n, p, fixed):
         if fixed:
             assert r["inner_iters_total"] == 25
         else:
-            assert abs(r["inner_iters_total"] - ref.iters) <= 2, (r["inner_iters_total"], ref.iters)
+            # The stopping index is not unique under rounding: the penalty
+            # grows whenever the Cond2 quantity falls below eps2, and FP32
+            # and FP64 can cross that threshold an iteration apart, which
+            # shifts the schedule.  The solution itself is compared above.
+            assert abs(r["inner_iters_total"] - ref.iters) <= max(3, 0.1 * ref.iters), (r["inner_iters_total"],
+                                                                                        ref.iters)
+
+
+# ---------------------------------------------------------------------------
+# Range of convergence (checkerboard, affine deformations): the GPU and the
+# oracle agree on success at points well inside and well outside the basin.
+# ---------------------------------------------------------------------------
+
+
+def _rect_err(G, Hn):
+    M = np.linalg.inv(G) @ Hn
+    M = M / M[2, 2]
+    a = np.abs(M[:2, :2])
+    return min(max(a[0, 1], a[1, 0]) / min(a[0, 0], a[1, 1]), max(a[0, 0], a[1, 1]) / max(min(a[0, 1], a[1, 0]), 1e-300))
+
+
+@pytest.mark.parametrize("k,j", [(0, 0), (2, 2), (3, 4), (10, 20)])
+def test_convergence_sweep_points_agree_with_oracle(tilt, ctx, device, k, j):
+    theta, t = k * math.pi / 60.0, j * 0.05
+    p = ts.checkerboard_patch(theta, t)
+    tp = tilt.default_params(max_outer=50)
+    _, res = solve_on_device(tilt, ctx, [p], device, tp)
+    ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp))
+    Hn, c, s = O.normalise_transform(res[0]["tau"], p.m, p.n)
+    gpu_ok = _rect_err(p.meta["G_norm"], Hn) < 2e-2
+    ref_ok = _rect_err(p.meta["G_norm"], ref.tau_norm) < 2e-2
+    assert gpu_ok == ref_ok
+    if ref_ok and ref.outer_iters < tp.max_outer and res[0]["outer_iters"] < tp.max_outer:
+        assert O.tau_rel_err(res[0]["tau"], ref.tau_px, p.m, p.n) <= 1e-4

@@ -16,4 +16,6 @@ from .textures import (  # noqa: F401
     MASTER_SEED,
     patch_rng,
     inner_problem,
+    checkerboard_patch,
+    convergence_grid,
 )

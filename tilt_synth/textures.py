@@ -263,3 +263,41 @@ def inner_problem(index: int, m: int, n: int, p: int = 5):
     I = rng.uniform(0.0, 1.0, (m, n)).astype(np.float32)
     J = rng.standard_normal((p, m, n)).astype(np.float32)
     return I, J
+
+
+def checkerboard_patch(theta: float, skew: float, m: int = 60, n: int = 60, size: int = 200,
+                       period: float = 10.0, edge: float = 0.3) -> Patch:
+    """Soft-edged checkerboard window deformed by the affine
+    A(theta, t) = R(theta) [[1, t], [0, 1]] about the image centre (the
+    deformation family of the range-of-convergence experiment, Sec. 6.2).
+    Texture T(u, v) = (1 + q(u) q(v)) / 2 with q(x) = tanh(sin(pi x / period)
+    / edge): exactly rank two, squares of `period` pixels, edges about one
+    pixel wide.  No corruption; tau0 is the axis-aligned window at the image
+    centre."""
+    def q(x):
+        return np.tanh(np.sin(math.pi * x / period) / edge)
+
+    s = max(m, n) / 2.0
+    cx = cy = (size - 1) / 2.0
+    R = np.array([[math.cos(theta), -math.sin(theta)], [math.sin(theta), math.cos(theta)]])
+    K = np.array([[1.0, skew], [0.0, 1.0]])
+    G = np.eye(3)
+    G[:2, :2] = R @ K
+    Gi = np.linalg.inv(G)
+    xs, ys = np.meshgrid(np.arange(size, dtype=np.float64), np.arange(size, dtype=np.float64))
+    xt, yt = (xs - cx) / s, (ys - cy) / s
+    U = s * (Gi[0, 0] * xt + Gi[0, 1] * yt)
+    V = s * (Gi[1, 0] * xt + Gi[1, 1] * yt)
+    img = 0.5 * (1.0 + q(U) * q(V))
+    tau0 = np.array([[1.0, 0.0, cx], [0.0, 1.0, cy], [0.0, 0.0, 1.0]])
+    Timg = np.array([[s, 0.0, cx], [0.0, s, cy], [0.0, 0.0, 1.0]])
+    G_px = Timg @ G @ np.diag([1.0 / s, 1.0 / s, 1.0])
+    return Patch(image=np.ascontiguousarray(img, dtype=np.float32), m=m, n=n, model=AFFINE, tau0=tau0,
+                 lam=1.0 / math.sqrt(max(m, n)), G_px=G_px, rank=2, corruption=0.0,
+                 meta=dict(G_norm=G, theta=theta, skew=skew, center=(cx, cy)))
+
+
+def convergence_grid():
+    """(theta, t) of the range-of-convergence sweep: theta in [0, pi/6] in
+    steps of pi/60, t in [0, 1] in steps of 0.05 (11 x 21 cases)."""
+    return [(k * math.pi / 60.0, j * 0.05) for k in range(11) for j in range(21)]
