@@ -247,10 +247,42 @@ __device__ inline bool rotate_rows(float4* x, float4* y, float& nx, float& ny, f
     return true;
 }
 
+// Rotate two rows in place by (s, tau): a' = a - s (b + tau a),
+// b' = b + s (a - tau b).  Both temporaries are formed before either row is
+// overwritten, so the update needs no register copies; s = tau = 0 leaves
+// the rows bit-for-bit unchanged.
+template <int NCH>
+__device__ inline void apply_rotation(float4* x, float4* y, float s, float h) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        float4 u, v;
+        u.x = fmaf(h, x[c].x, y[c].x);
+        u.y = fmaf(h, x[c].y, y[c].y);
+        u.z = fmaf(h, x[c].z, y[c].z);
+        u.w = fmaf(h, x[c].w, y[c].w);
+        v.x = fmaf(-h, y[c].x, x[c].x);
+        v.y = fmaf(-h, y[c].y, x[c].y);
+        v.z = fmaf(-h, y[c].z, x[c].z);
+        v.w = fmaf(-h, y[c].w, x[c].w);
+        x[c].x = fmaf(-s, u.x, x[c].x);
+        x[c].y = fmaf(-s, u.y, x[c].y);
+        x[c].z = fmaf(-s, u.z, x[c].z);
+        x[c].w = fmaf(-s, u.w, x[c].w);
+        y[c].x = fmaf(s, v.x, y[c].x);
+        y[c].y = fmaf(s, v.y, y[c].y);
+        y[c].z = fmaf(s, v.z, y[c].z);
+        y[c].w = fmaf(s, v.w, y[c].w);
+    }
+}
+
 // Two independent rotations (disjoint rows) computed side by side so that
 // their dependency chains (dot, cross-lane sum, rotation parameters)
-// overlap.  A pair that is already orthogonal to tolerance gets s = tau = 0,
-// which leaves its rows and norms bit-for-bit unchanged.
+// overlap.  The skip test is uniform over the wavefront (no group of the
+// wave rotates either pair); otherwise both updates run for every lane,
+// with s = tau = 0 for a pair that is already orthogonal to tolerance,
+// which leaves its rows and norms bit-for-bit unchanged.  Keeping the
+// updates free of divergent branches lets the rows stay in their
+// registers.
 template <int LPP, int NCH>
 __device__ inline void rotate_two(float4* x1, float4* y1, float& nx1, float& ny1, bool& f1, float4* x2, float4* y2,
                                   float& nx2, float& ny2, bool& f2, float tol, float& s1, float& h1, float& s2,
@@ -271,46 +303,22 @@ __device__ inline void rotate_two(float4* x1, float4* y1, float& nx1, float& ny1
     const float g2 = group_sum<LPP>(q0 + q1);
     f1 = needs_rotation(g1, nx1, ny1, tol);
     f2 = needs_rotation(g2, nx2, ny2, tol);
-    if (!(f1 || f2)) return;
+    if (!__any(f1 || f2)) return;
     float t1, t2;
     jacobi_rotation(nx1, ny1, f1 ? g1 : 1.0f, s1, h1, t1);
     jacobi_rotation(nx2, ny2, f2 ? g2 : 1.0f, s2, h2, t2);
-    if (!f1) s1 = h1 = t1 = 0.f;
-    if (!f2) s2 = h2 = t2 = 0.f;
-    // Separate branches: a wave in which no group rotates one of the two
-    // pairs skips that pair's row updates (common in the last sweeps).
-    if (f1) {
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            const float4 a = x1[c], b = y1[c];
-            x1[c].x = fmaf(-s1, fmaf(h1, a.x, b.x), a.x);
-            x1[c].y = fmaf(-s1, fmaf(h1, a.y, b.y), a.y);
-            x1[c].z = fmaf(-s1, fmaf(h1, a.z, b.z), a.z);
-            x1[c].w = fmaf(-s1, fmaf(h1, a.w, b.w), a.w);
-            y1[c].x = fmaf(s1, fmaf(-h1, b.x, a.x), b.x);
-            y1[c].y = fmaf(s1, fmaf(-h1, b.y, a.y), b.y);
-            y1[c].z = fmaf(s1, fmaf(-h1, b.z, a.z), b.z);
-            y1[c].w = fmaf(s1, fmaf(-h1, b.w, a.w), b.w);
-        }
-        nx1 = fmaxf(fmaf(-t1, g1, nx1), 0.f);
-        ny1 = fmaxf(fmaf(t1, g1, ny1), 0.f);
-    }
-    if (f2) {
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            const float4 u = x2[c], v = y2[c];
-            x2[c].x = fmaf(-s2, fmaf(h2, u.x, v.x), u.x);
-            x2[c].y = fmaf(-s2, fmaf(h2, u.y, v.y), u.y);
-            x2[c].z = fmaf(-s2, fmaf(h2, u.z, v.z), u.z);
-            x2[c].w = fmaf(-s2, fmaf(h2, u.w, v.w), u.w);
-            y2[c].x = fmaf(s2, fmaf(-h2, v.x, u.x), v.x);
-            y2[c].y = fmaf(s2, fmaf(-h2, v.y, u.y), v.y);
-            y2[c].z = fmaf(s2, fmaf(-h2, v.z, u.z), v.z);
-            y2[c].w = fmaf(s2, fmaf(-h2, v.w, u.w), v.w);
-        }
-        nx2 = fmaxf(fmaf(-t2, g2, nx2), 0.f);
-        ny2 = fmaxf(fmaf(t2, g2, ny2), 0.f);
-    }
+    s1 = f1 ? s1 : 0.f;
+    h1 = f1 ? h1 : 0.f;
+    t1 = f1 ? t1 : 0.f;
+    s2 = f2 ? s2 : 0.f;
+    h2 = f2 ? h2 : 0.f;
+    t2 = f2 ? t2 : 0.f;
+    apply_rotation<NCH>(x1, y1, s1, h1);
+    apply_rotation<NCH>(x2, y2, s2, h2);
+    nx1 = f1 ? fmaxf(fmaf(-t1, g1, nx1), 0.f) : nx1;
+    ny1 = f1 ? fmaxf(fmaf(t1, g1, ny1), 0.f) : ny1;
+    nx2 = f2 ? fmaxf(fmaf(-t2, g2, nx2), 0.f) : nx2;
+    ny2 = f2 ? fmaxf(fmaf(t2, g2, ny2), 0.f) : ny2;
 }
 
 // Apply a rotation (s, tau) to two rows held in LDS (the lane's chunks).
@@ -366,6 +374,85 @@ __device__ inline void store_row(float* p, const float4* x) {
     for (int c = 0; c < NCH; ++c) *reinterpret_cast<float4*>(p + 4 * LPP * c) = x[c];
 }
 
+// One round of the circle ordering: every lane group takes block pairs
+// k = g, g + G, ... of round r.  FIRST (round 0 of a sweep) also rotates
+// the pairs inside each block of two rows; it is a separate instance so the
+// other rounds carry no conditional stage.
+template <int BS, int LPP, int NCH, bool WARM, bool FIRST>
+__device__ inline void jacobi_round(float* B, float* Rm, float* nrm, int ld, int r, int Nb, int Pb, int g, int q,
+                                    float tol, int& any, long long& rots) {
+    constexpr int G = NT / LPP;
+    for (int k = g; k < Pb; k += G) {
+        int I, J;
+        if (k == 0) {
+            I = Nb;
+            J = r;
+        } else {
+            I = r + k;
+            if (I >= Nb) I -= Nb;
+            J = r - k;
+            if (J < 0) J += Nb;
+        }
+        float* pa = B + (BS * I) * ld + 4 * q;
+        float* pb = B + (BS * J) * ld + 4 * q;
+        if (BS == 1) {
+            float4 a1[NCH], b1[NCH];
+            load_row<LPP, NCH>(pa, a1);
+            load_row<LPP, NCH>(pb, b1);
+            float na1 = nrm[I], nb1 = nrm[J];
+            float sr, hr;
+            const bool f = rotate_rows<LPP, NCH>(a1, b1, na1, nb1, tol, sr, hr);
+            if (WARM && f) rotate_lds_rows<LPP, NCH>(Rm + I * ld + 4 * q, Rm + J * ld + 4 * q, sr, hr);
+            if (f) {
+                any = 1;
+                rots += 1;
+                store_row<LPP, NCH>(pa, a1);
+                store_row<LPP, NCH>(pb, b1);
+                if (q == 0) {
+                    nrm[I] = na1;
+                    nrm[J] = nb1;
+                }
+            }
+        } else {
+            float4 a1[NCH], a2[NCH], b1[NCH], b2[NCH];
+            load_row<LPP, NCH>(pa, a1);
+            load_row<LPP, NCH>(pa + ld, a2);
+            load_row<LPP, NCH>(pb, b1);
+            load_row<LPP, NCH>(pb + ld, b2);
+            float na1 = nrm[2 * I], na2 = nrm[2 * I + 1], nb1 = nrm[2 * J], nb2 = nrm[2 * J + 1];
+            bool d0 = false, d1 = false, d2 = false, d3 = false, f, h;
+            float s1, h1, s2, h2;
+            float* ra1 = WARM ? Rm + (BS * I) * ld + 4 * q : nullptr;
+            float* rb1 = WARM ? Rm + (BS * J) * ld + 4 * q : nullptr;
+            if (FIRST) {
+                rotate_two<LPP, NCH>(a1, a2, na1, na2, f, b1, b2, nb1, nb2, h, tol, s1, h1, s2, h2);
+                if (WARM && f) rotate_lds_rows<LPP, NCH>(ra1, ra1 + ld, s1, h1);
+                if (WARM && h) rotate_lds_rows<LPP, NCH>(rb1, rb1 + ld, s2, h2);
+                d0 |= f; d1 |= f; d2 |= h; d3 |= h; rots += f; rots += h;
+            }
+            rotate_two<LPP, NCH>(a1, b1, na1, nb1, f, a2, b2, na2, nb2, h, tol, s1, h1, s2, h2);
+            if (WARM && f) rotate_lds_rows<LPP, NCH>(ra1, rb1, s1, h1);
+            if (WARM && h) rotate_lds_rows<LPP, NCH>(ra1 + ld, rb1 + ld, s2, h2);
+            d0 |= f; d2 |= f; d1 |= h; d3 |= h; rots += f; rots += h;
+            rotate_two<LPP, NCH>(a1, b2, na1, nb2, f, a2, b1, na2, nb1, h, tol, s1, h1, s2, h2);
+            if (WARM && f) rotate_lds_rows<LPP, NCH>(ra1, rb1 + ld, s1, h1);
+            if (WARM && h) rotate_lds_rows<LPP, NCH>(ra1 + ld, rb1, s2, h2);
+            d0 |= f; d3 |= f; d1 |= h; d2 |= h; rots += f; rots += h;
+            if (d0 | d1 | d2 | d3) any = 1;
+            if (d0) store_row<LPP, NCH>(pa, a1);
+            if (d1) store_row<LPP, NCH>(pa + ld, a2);
+            if (d2) store_row<LPP, NCH>(pb, b1);
+            if (d3) store_row<LPP, NCH>(pb + ld, b2);
+            if (q == 0) {
+                nrm[2 * I] = na1;
+                nrm[2 * I + 1] = na2;
+                nrm[2 * J] = nb1;
+                nrm[2 * J + 1] = nb2;
+            }
+        }
+    }
+}
+
 // Returns 1 (uniform over the workgroup) if any pair was rotated.  WARM:
 // every rotation is also applied to the rows of Rm (same layout), which
 // accumulates the product of the rotations.
@@ -374,7 +461,6 @@ __device__ int jacobi_rows(float* B, float* Rm, int nc, int ld, float tol, int m
     float* nrm = tilt_jacobi_nrm;
     const int tid = threadIdx.x;
     const int g = tid / LPP, q = tid % LPP;
-    constexpr int G = NT / LPP;
     const int nc4 = (nc + 3) & ~3;
     const int nb = nc4 / BS;          // blocks (even)
     const int Pb = nb >> 1, Nb = nb - 1;
@@ -383,76 +469,10 @@ __device__ int jacobi_rows(float* B, float* Rm, int nc, int ld, float tol, int m
     for (int sw = 0; sw < max_sweeps; ++sw) {
         row_norms<LPP, NCH>(B, nc4, ld, nrm);
         int any = 0;
-        for (int r = 0; r < Nb; ++r) {
-            for (int k = g; k < Pb; k += G) {
-                int I, J;
-                if (k == 0) {
-                    I = Nb;
-                    J = r;
-                } else {
-                    I = r + k;
-                    if (I >= Nb) I -= Nb;
-                    J = r - k;
-                    if (J < 0) J += Nb;
-                }
-                float* pa = B + (BS * I) * ld + 4 * q;
-                float* pb = B + (BS * J) * ld + 4 * q;
-                if (BS == 1) {
-                    float4 a1[NCH], b1[NCH];
-                    load_row<LPP, NCH>(pa, a1);
-                    load_row<LPP, NCH>(pb, b1);
-                    float na1 = nrm[I], nb1 = nrm[J];
-                    float sr, hr;
-                    const bool f = rotate_rows<LPP, NCH>(a1, b1, na1, nb1, tol, sr, hr);
-                    if (WARM && f) rotate_lds_rows<LPP, NCH>(Rm + I * ld + 4 * q, Rm + J * ld + 4 * q, sr, hr);
-                    if (f) {
-                        any = 1;
-                        rots += 1;
-                        store_row<LPP, NCH>(pa, a1);
-                        store_row<LPP, NCH>(pb, b1);
-                        if (q == 0) {
-                            nrm[I] = na1;
-                            nrm[J] = nb1;
-                        }
-                    }
-                } else {
-                    float4 a1[NCH], a2[NCH], b1[NCH], b2[NCH];
-                    load_row<LPP, NCH>(pa, a1);
-                    load_row<LPP, NCH>(pa + ld, a2);
-                    load_row<LPP, NCH>(pb, b1);
-                    load_row<LPP, NCH>(pb + ld, b2);
-                    float na1 = nrm[2 * I], na2 = nrm[2 * I + 1], nb1 = nrm[2 * J], nb2 = nrm[2 * J + 1];
-                    bool d0 = false, d1 = false, d2 = false, d3 = false, f, g;
-                    float s1, h1, s2, h2;
-                    float* ra1 = WARM ? Rm + (BS * I) * ld + 4 * q : nullptr;
-                    float* rb1 = WARM ? Rm + (BS * J) * ld + 4 * q : nullptr;
-                    if (r == 0) {
-                        rotate_two<LPP, NCH>(a1, a2, na1, na2, f, b1, b2, nb1, nb2, g, tol, s1, h1, s2, h2);
-                        if (WARM && f) rotate_lds_rows<LPP, NCH>(ra1, ra1 + ld, s1, h1);
-                        if (WARM && g) rotate_lds_rows<LPP, NCH>(rb1, rb1 + ld, s2, h2);
-                        d0 |= f; d1 |= f; d2 |= g; d3 |= g; rots += f; rots += g;
-                    }
-                    rotate_two<LPP, NCH>(a1, b1, na1, nb1, f, a2, b2, na2, nb2, g, tol, s1, h1, s2, h2);
-                    if (WARM && f) rotate_lds_rows<LPP, NCH>(ra1, rb1, s1, h1);
-                    if (WARM && g) rotate_lds_rows<LPP, NCH>(ra1 + ld, rb1 + ld, s2, h2);
-                    d0 |= f; d2 |= f; d1 |= g; d3 |= g; rots += f; rots += g;
-                    rotate_two<LPP, NCH>(a1, b2, na1, nb2, f, a2, b1, na2, nb1, g, tol, s1, h1, s2, h2);
-                    if (WARM && f) rotate_lds_rows<LPP, NCH>(ra1, rb1 + ld, s1, h1);
-                    if (WARM && g) rotate_lds_rows<LPP, NCH>(ra1 + ld, rb1, s2, h2);
-                    d0 |= f; d3 |= f; d1 |= g; d2 |= g; rots += f; rots += g;
-                    if (d0 | d1 | d2 | d3) any = 1;
-                    if (d0) store_row<LPP, NCH>(pa, a1);
-                    if (d1) store_row<LPP, NCH>(pa + ld, a2);
-                    if (d2) store_row<LPP, NCH>(pb, b1);
-                    if (d3) store_row<LPP, NCH>(pb + ld, b2);
-                    if (q == 0) {
-                        nrm[2 * I] = na1;
-                        nrm[2 * I + 1] = na2;
-                        nrm[2 * J] = nb1;
-                        nrm[2 * J + 1] = nb2;
-                    }
-                }
-            }
+        jacobi_round<BS, LPP, NCH, WARM, true>(B, Rm, nrm, ld, 0, Nb, Pb, g, q, tol, any, rots);
+        __syncthreads();
+        for (int r = 1; r < Nb; ++r) {
+            jacobi_round<BS, LPP, NCH, WARM, false>(B, Rm, nrm, ld, r, Nb, Pb, g, q, tol, any, rots);
             __syncthreads();
         }
         ++sweeps;
