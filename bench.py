@@ -146,6 +146,13 @@ def main():
                     help="outer iterations per pyramid level in serving mode")
     ap.add_argument("--convergence", action="store_true",
                     help="range-of-convergence sweep (checkerboard, 11 x 21 affine deformations, one batch)")
+    ap.add_argument("--components", action="store_true",
+                    help="run the component kernels once each for profiling: a 1 GiB device copy (counter "
+                         "calibration), warp + Jacobian and SVT on the default workload's windows, and a short "
+                         "plain-path solve of one patch; prints their kernel times")
+    ap.add_argument("--precision", action="store_true",
+                    help="precision study on the 128x128 workload: cold, warm FP32, warm bfloat16 + FP32 "
+                         "refinement, warm bfloat16; tau and objective errors against the FP64 oracle")
     ap.add_argument("--inner", action="store_true",
                     help="inner-loop-only mode (random I and J, the setting of Table 1)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -169,6 +176,10 @@ def main():
         return serve_main(args)
     if args.inner:
         return inner_main(args)
+    if args.precision:
+        return precision_main(args)
+    if args.components:
+        return components_main(args)
     if args.convergence:
         return convergence_main(args)
     dev = torch.device("cuda:0")
@@ -416,6 +427,130 @@ def _convergence_oracle_worker(theta_t):
     p = ts.checkerboard_patch(*theta_t)
     r = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, O.Params(max_outer=50))
     return rectification_error(p.meta["G_norm"], r.tau_norm)
+
+
+def _precision_oracle_worker(idx):
+    import oracle as O
+    import tilt_synth as ts
+
+    p = ts.make_batch(3, [idx])[0]
+    r = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, O.Params(), lam=p.lam)
+    return r.tau_px, r.objective, r.outer_iters
+
+
+def precision_main(args):
+    """512 projective 128x128 windows (rank 4, 15 % corruption) with four
+    SVT variants; per-patch tau and objective error against the FP64 oracle
+    on a sample solved on the host in parallel."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    import paper_1205_5351_amd as T
+    import tilt_synth as ts
+
+    dev = torch.device("cuda:0")
+    count = args.patches or 512
+    patches = ts.make_config(3, count=count)
+    imgs = [torch.from_numpy(p.image).to(dev) for p in patches]
+    probs = [T.make_problem(im.data_ptr(), p.height, p.width, p.width, p.m, p.n, p.model, p.tau0)
+             for im, p in zip(imgs, patches)]
+    ctx = T.Context(0)
+    sample = list(range(0, count, max(1, count // 12)))[:12]
+    ref = None
+    if not args.no_cpu:
+        import multiprocessing as mp
+
+        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            os.environ[k] = "1"
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(len(sample)) as pool:
+            ref = pool.map(_precision_oracle_worker, sample)
+        log(f"oracle on {len(sample)} patches: {time.perf_counter() - t0:.1f} s")
+    modes = []
+    names = {0: "cold FP32", 1: "warm FP32 (MFMA f32)", 2: "warm BF16 MFMA + FP32 refinement", 3: "warm BF16 MFMA"}
+    for mode in (0, 1, 2, 3):
+        prm = T.default_params(lam=patches[0].lam, svt_mode=mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, res = ctx.solve_batch(probs, prm)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        row = {"svt_mode": mode, "name": names[mode], "patches_per_s": round(count / wall, 3),
+               "kernel_ms": round(ctx.last_kernel_ms(), 1),
+               "sweeps_per_svd": round(sum(r["counters"]["jacobi_sweeps"] for r in res) /
+                                       max(1, sum(r["counters"]["svt_calls"] for r in res)), 2)}
+        if ref is not None:
+            terr = [O.tau_rel_err(res[i]["tau"], rt[0], patches[i].m, patches[i].n) for i, rt in zip(sample, ref)]
+            oerr = [abs(res[i]["objective"] - rt[1]) / rt[1] for i, rt in zip(sample, ref)]
+            conv = [rt[2] < 50 and res[i]["outer_iters"] < 50 for i, rt in zip(sample, ref)]
+            row.update(tau_err_max=float(np.max(terr)), tau_err_median=float(np.median(terr)),
+                       tau_err_max_converged=float(max([e for e, c in zip(terr, conv) if c], default=0.0)),
+                       objective_err_max=float(np.max(oerr)), per_patch_tau_err=[float(e) for e in terr])
+        modes.append(row)
+        log(f"{names[mode]}: {row['patches_per_s']} patches/s")
+    out = {
+        "metric": "precision study: patches/s and error vs FP64 oracle per SVT variant",
+        "value": next(m for m in modes if m["svt_mode"] == 2)["patches_per_s"],
+        "unit": "patches/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": next(m for m in modes if m["svt_mode"] == 2)["kernel_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32", "data": "synthetic",
+        "config": {"workload": "batch-512x128x128-projective", "patches": count, "oracle_sample": sample},
+        "modes": modes, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def components_main(args):
+    """Component kernels on the 256 x 100x100 workload, for rocprofv3."""
+    import numpy as np
+    import torch
+
+    import paper_1205_5351_amd as T
+    import tilt_synth as ts
+
+    dev = torch.device("cuda:0")
+    ctx = T.Context(0)
+    ps = ts.make_config(1)
+    nel = (1 << 30) // 4
+    src = torch.ones(nel, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    log("copy probe: 1024 MiB read + 1024 MiB written")
+    imgs = [torch.from_numpy(p.image).to(dev) for p in ps]
+    probs = [T.make_problem(im.data_ptr(), p.height, p.width, p.width, p.m, p.n, p.model, p.tau0)
+             for im, p in zip(imgs, ps)]
+    m, n, pm = ps[0].m, ps[0].n, ps[0].model
+    dI = torch.zeros((len(ps), m, n), dtype=torch.float32, device=dev)
+    dJ = torch.zeros((len(ps), pm, m, n), dtype=torch.float32, device=dev)
+    taus = np.stack([p.tau0 for p in ps])
+    out = {}
+    for name, fn in (("warp_jacobian", lambda: ctx.warp_jacobian(probs, taus, dI.data_ptr(), dJ.data_ptr())),
+                     ("svt", lambda: ctx.svt_batch(dI.data_ptr(), dA.data_ptr(), 0, len(ps), m, n,
+                                                   np.full(len(ps), 0.02, np.float32)))):
+        if name == "svt":
+            dA = torch.zeros_like(dI)
+        ts_ = []
+        for rep in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts_.append(1000 * (time.perf_counter() - t0))
+        out[name + "_ms"] = round(min(ts_), 3)
+        log(f"{name}: {min(ts_):.3f} ms per call ({len(ps)} windows)")
+    prm = T.default_params(lam=ps[0].lam, fixed_iters=1, max_outer=2, max_inner=50)
+    t0 = time.perf_counter()
+    ctx.solve_batch_plain(probs[:1], prm)
+    torch.cuda.synchronize()
+    out["plain_2x50_ms"] = round(1000 * (time.perf_counter() - t0), 1)
+    log(f"plain path, one patch, 2 x 50 iterations: {out['plain_2x50_ms']} ms")
+    print(json.dumps({"components": out}), flush=True)
+    ctx.close()
 
 
 # LADMAP column of Table 1 (MATLAB, one Xeon E5540 core): seconds per

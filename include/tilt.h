@@ -79,7 +79,14 @@ typedef struct {
                            step every 4 calls); same result to rounding,
                            fewer sweeps.  Used where the Jacobi rows and the
                            rotation fit in LDS together (about
-                           min(m,n) * max(m,n) <= 18k); cold elsewhere.       */
+                           min(m,n) * max(m,n) <= 18k); cold elsewhere.
+                           2: as 1, with the start product formed from
+                           bfloat16 operands on the matrix cores (FP32
+                           accumulation), then refined: the product is
+                           recomputed in FP32 with the accumulated rotation
+                           and the Jacobi continues (FP32 accuracy).
+                           3: bfloat16 start without refinement (precision
+                           study; errors of order 1e-3).                      */
     float jacobi_tol;   /* rotate a pair when |a.b| > tol ||a|| ||b||; 1e-6   */
     int max_sweeps;     /* Jacobi sweep cap, default 40                       */
     int pyramid_levels; /* 1 (default): solve the window as given.  L in 2..4:

@@ -228,7 +228,7 @@ int validate_params(const tilt_params* p) {
     if (!(p->rho0 >= 1.0) || !(p->mu_max > 0)) return TILT_ERR_ARG;
     if (p->max_inner < 1 || p->max_outer < 1 || p->max_sweeps < 1) return TILT_ERR_ARG;
     if (!(p->jacobi_tol > 0.f) || !(p->jacobi_tol < 1.f)) return TILT_ERR_ARG;
-    if (p->svt_mode != 0 && p->svt_mode != 1) return TILT_ERR_ARG;
+    if (p->svt_mode < 0 || p->svt_mode > 3) return TILT_ERR_ARG;
     if (p->pyramid_levels < 0 || p->pyramid_levels > MAX_LEVELS) return TILT_ERR_ARG;
     if (!std::isfinite(p->lambda) || !std::isfinite(p->mu0)) return TILT_ERR_ARG;
     return TILT_OK;
@@ -297,7 +297,7 @@ int plan_request(const tilt_problem& pr, const tilt_params* prm, float* A_out, f
         st = shape_config(ml[l], nl[l], &sc[l]);
         if (st != TILT_OK) return st;
         planes = std::max(planes, sc[l].ws_floats);
-        const bool warm = prm->svt_mode == 1 && sc[l].warm_lds > 0;
+        const bool warm = prm->svt_mode >= 1 && sc[l].warm_lds > 0;
         P.lds = std::max(P.lds, warm ? sc[l].warm_lds : sc[l].lds);
     }
     size_t off = (planes + 63) & ~(size_t)63;
@@ -330,7 +330,7 @@ int plan_request(const tilt_problem& pr, const tilt_params* prm, float* A_out, f
         d.colmajor = sc[l].colmajor;
         d.ld = sc[l].ld;
         d.svt_cfg = sc[l].cfg;
-        d.warm = (prm->svt_mode == 1 && sc[l].warm_lds > 0) ? 1 : 0;
+        d.warm = (prm->svt_mode >= 1 && sc[l].warm_lds > 0) ? prm->svt_mode : 0;
         d.tb = d.warm ? sc[l].warm_tb : sc[l].tb;
         d.sb = sc[l].sb;
         d.nsb = sc[l].nsb;
@@ -931,7 +931,7 @@ int tilt_inner_batch(tilt_ctx* ctx, const float* I, const float* J, int count, i
     ShapeCfg sc{};
     st = shape_config(m, n, &sc);
     if (st != TILT_OK) return st;
-    const bool warm = prm->svt_mode == 1 && sc.warm_lds > 0;
+    const bool warm = prm->svt_mode >= 1 && sc.warm_lds > 0;
     const size_t lds = warm ? sc.warm_lds : sc.lds;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -957,7 +957,7 @@ int tilt_inner_batch(tilt_ctx* ctx, const float* I, const float* J, int count, i
         d.colmajor = sc.colmajor;
         d.ld = sc.ld;
         d.svt_cfg = sc.cfg;
-        d.warm = warm ? 1 : 0;
+        d.warm = warm ? prm->svt_mode : 0;
         d.tb = warm ? sc.warm_tb : sc.tb;
         d.sb = sc.sb;
         d.nsb = sc.nsb;

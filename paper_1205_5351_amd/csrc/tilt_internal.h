@@ -44,7 +44,8 @@ struct PatchDesc {
     int sb;                   // tiled SVT: rows per super-block (0: whole matrix in LDS)
     int nsb;                  // tiled SVT: super-blocks (even)
     int ncp;                  // tiled SVT: rows of the working plane (nsb * sb >= nc)
-    int warm;                 // 1: SVT warm-started from the previous rotation
+    int warm;                 // SVT warm-started from the previous rotation: 1 FP32 start,
+                              // 2 bfloat16 start + FP32 refinement, 3 bfloat16 start
     int pad1;
     double cx, cy, s;         // scaled coordinates of the level being solved (the
                               // kernels take them from PatchState::geo)

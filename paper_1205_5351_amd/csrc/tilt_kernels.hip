@@ -1437,31 +1437,80 @@ __device__ inline SvtLds carve_lds_warm(float* base, int nc, int ld, int tb, flo
     return L;
 }
 
-// B = R X for the nc4 rows of R (LDS, stride ld; rows >= nc are zero) and
-// the X-layout plane X (nc rows, stride ldg); tiles of 4 rows x 4 columns,
-// k summed in order.
-__device__ void warm_start_rows(const float* Rl, int ld, const float* X, int ldg, float* B, int nc, int nr4) {
-    const int nc4 = (nc + 3) & ~3;
-    const int tiles = (nc4 >> 2) * nr4;
-    for (int t = threadIdx.x; t < tiles; t += NT) {
-        const int i4 = t / nr4, c = t - i4 * nr4;
-        const float* r0 = Rl + (4 * i4) * ld;
-        float4 acc[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) acc[a] = f4(0.f);
-        for (int k = 0; k < nc; ++k) {
-            const float4 x = reinterpret_cast<const float4*>(X + (size_t)k * ldg)[c];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const float ra = r0[a * ld + k];
-                acc[a].x = fmaf(ra, x.x, acc[a].x);
-                acc[a].y = fmaf(ra, x.y, acc[a].y);
-                acc[a].z = fmaf(ra, x.z, acc[a].z);
-                acc[a].w = fmaf(ra, x.w, acc[a].w);
-            }
+typedef float tilt_floatx4 __attribute__((ext_vector_type(4)));
+
+// C = A B on the matrix cores (FP32 in, FP32 accumulate): C is M x N, A is
+// M x K (row stride lda), B is K x N with B[k][j] = Bm[k * ldb + j], or
+// Bm[j * ldb + k] when BT.  16 x 16 output tiles, one wavefront per tile,
+// v_mfma_f32_16x16x4f32 over k in steps of 4: lane l supplies
+// A[i0 + l % 16][k0 + l / 16] and B[k0 + l / 16][j0 + l % 16] and receives
+// rows i0 + 4 (l / 16) + r, r = 0..3, of column j0 + l % 16.  Operands
+// outside M, N, K read as 0 and results outside M x N are not stored.
+template <bool BT>
+__device__ void mfma_gemm(const float* A, int lda, int M, const float* Bm, int ldb, int N, int K, float* C,
+                          int ldc) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ti = (M + 15) >> 4, tj = (N + 15) >> 4;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int t = wv; t < ti * tj; t += NWAVE) {
+        const int tr = t / tj;
+        const int i0 = tr * 16, j0 = (t - tr * tj) * 16;
+        tilt_floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        const int i = i0 + li, j = j0 + li;
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int k = k0 + lk;
+            const float a = (i < M && k < K) ? A[(size_t)i * lda + k] : 0.f;
+            float b = 0.f;
+            if (k < K && j < N) b = BT ? Bm[(size_t)j * ldb + k] : Bm[(size_t)k * ldb + j];
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
         }
 #pragma unroll
-        for (int a = 0; a < 4; ++a) *reinterpret_cast<float4*>(B + (4 * i4 + a) * ld + 4 * c) = acc[a];
+        for (int r = 0; r < 4; ++r) {
+            const int oi = i0 + 4 * lk + r;
+            if (oi < M && j < N) C[(size_t)oi * ldc + j] = acc[r];
+        }
+    }
+}
+
+typedef short tilt_short4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest even (finite inputs).
+__device__ inline short to_bf16(float f) {
+    unsigned int u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+// C = A B with A and B rounded to bfloat16 and FP32 accumulation on the
+// matrix cores (v_mfma_f32_16x16x16bf16_1k: lane l supplies
+// A[i0 + l % 16][k0 + 4 (l / 16) + u] and B[k0 + 4 (l / 16) + u][j0 + l % 16],
+// u = 0..3; output layout as in mfma_gemm).  Same operand conventions and
+// bounds as mfma_gemm<false>.
+__device__ void mfma_gemm_bf16(const float* A, int lda, int M, const float* Bm, int ldb, int N, int K, float* C,
+                               int ldc) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ti = (M + 15) >> 4, tj = (N + 15) >> 4;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int t = wv; t < ti * tj; t += NWAVE) {
+        const int tr = t / tj;
+        const int i0 = tr * 16, j0 = (t - tr * tj) * 16;
+        tilt_floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        const int i = i0 + li, j = j0 + li;
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            tilt_short4 av, bv;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + 4 * lk + u;
+                av[u] = (i < M && k < K) ? to_bf16(A[(size_t)i * lda + k]) : (short)0;
+                bv[u] = (k < K && j < N) ? to_bf16(Bm[(size_t)k * ldb + j]) : (short)0;
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int oi = i0 + 4 * lk + r;
+            if (oi < M && j < N) C[(size_t)oi * ldc + j] = acc[r];
+        }
     }
 }
 
@@ -1469,66 +1518,13 @@ __device__ void warm_start_rows(const float* Rl, int ld, const float* X, int ldg
 // G = R R^T goes to Gs (LDS, stride ld), T = G R to the device plane T
 // (stride ldg).
 __device__ void newton_schulz_rows(float* Rl, int ld, int nc, float* Gs, float* T, int ldg) {
-    const int n4 = (nc + 3) >> 2;
-    for (int t = threadIdx.x; t < n4 * n4; t += NT) {
-        const int i4 = t / n4, j4 = t - i4 * n4;
-        float acc[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
-        for (int k4 = 0; k4 < n4; ++k4) {
-            float4 ra[4], rb[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                ra[a] = *reinterpret_cast<const float4*>(Rl + (4 * i4 + a) * ld + 4 * k4);
-                rb[a] = *reinterpret_cast<const float4*>(Rl + (4 * j4 + a) * ld + 4 * k4);
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = dot4(ra[a], rb[b], acc[a][b]);
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-            *reinterpret_cast<float4*>(Gs + (4 * i4 + a) * ld + 4 * j4) =
-                make_float4(acc[a][0], acc[a][1], acc[a][2], acc[a][3]);
-    }
+    mfma_gemm<true>(Rl, ld, nc, Rl, ld, nc, nc, Gs, ld);
     __syncthreads();
-    for (int t = threadIdx.x; t < n4 * n4; t += NT) {
-        const int i4 = t / n4, c = t - i4 * n4;
-        float4 acc[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) acc[a] = f4(0.f);
-        for (int k = 0; k < nc; ++k) {
-            const float4 x = *reinterpret_cast<const float4*>(Rl + k * ld + 4 * c);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const float g = Gs[(4 * i4 + a) * ld + k];
-                acc[a].x = fmaf(g, x.x, acc[a].x);
-                acc[a].y = fmaf(g, x.y, acc[a].y);
-                acc[a].z = fmaf(g, x.z, acc[a].z);
-                acc[a].w = fmaf(g, x.w, acc[a].w);
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int row = 4 * i4 + a;
-            if (row < nc) *reinterpret_cast<float4*>(T + (size_t)row * ldg + 4 * c) = acc[a];
-        }
-    }
+    mfma_gemm<false>(Gs, ld, nc, Rl, ld, nc, nc, T, ldg);
     __syncthreads();
-    for (int e = threadIdx.x; e < nc * n4; e += NT) {
-        const int i = e / n4, c = e - i * n4;
-        float4* pr = reinterpret_cast<float4*>(Rl + i * ld + 4 * c);
-        const float4 r = *pr;
-        const float4 tt = *reinterpret_cast<const float4*>(T + (size_t)i * ldg + 4 * c);
-        float4 o;
-        o.x = fmaf(-0.5f, tt.x, 1.5f * r.x);
-        o.y = fmaf(-0.5f, tt.y, 1.5f * r.y);
-        o.z = fmaf(-0.5f, tt.z, 1.5f * r.z);
-        o.w = fmaf(-0.5f, tt.w, 1.5f * r.w);
-        *pr = o;
+    for (int e = threadIdx.x; e < nc * nc; e += NT) {
+        const int i = e / nc, j = e - i * nc;
+        Rl[i * ld + j] = fmaf(-0.5f, T[(size_t)i * ldg + j], 1.5f * Rl[i * ld + j]);
     }
     __syncthreads();
 }
@@ -1603,10 +1599,26 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
         load_rotation(Rl, ld, nc, V, ldg, saved);
         if (saved && prm.ns_every > 0 && st->warm_count % prm.ns_every == 0)
             newton_schulz_rows(Rl, ld, nc, L.B, d.ws + (PL_Q + 6) * np, ldg);
-        warm_start_rows(Rl, ld, M, ldg, L.B, nc, nr4);
+        // B = R M (nc4 x ldg; rows of R beyond nc are zero).  warm = 1: FP32
+        // products.  warm = 2, 3: the start is formed from bfloat16 operands
+        // (FP32 accumulation); 2 then refines: B = R' M again in FP32 with
+        // the accumulated rotation R' and the Jacobi continues from there,
+        // so the result has FP32 accuracy; 3 keeps the bfloat16 start
+        // (precision study).
+        const int nc4 = (nc + 3) & ~3;
+        if (d.warm == 1)
+            mfma_gemm<false>(Rl, ld, nc4, M, ldg, ldg, nc, L.B, ld);
+        else
+            mfma_gemm_bf16(Rl, ld, nc4, M, ldg, ldg, nc, L.B, ld);
         clear_lds_padding(L.B, nc, ldg, ld);
         __syncthreads();
         jacobi_dispatch_warm(d.svt_cfg, L.B, Rl, nc, ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
+        if (d.warm == 2) {
+            mfma_gemm<false>(Rl, ld, nc4, M, ldg, ldg, nc, L.B, ld);
+            clear_lds_padding(L.B, nc, ldg, ld);
+            __syncthreads();
+            jacobi_dispatch_warm(d.svt_cfg, L.B, Rl, nc, ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
+        }
         save_rotation(Rl, ld, nc, V, ldg);
         if (threadIdx.x == 0) {
             st->warm_ok = 1;
