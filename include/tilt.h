@@ -266,6 +266,24 @@ int tilt_warp_jacobian(tilt_ctx* ctx, const tilt_problem* probs, const double* t
 int tilt_inner_batch(tilt_ctx* ctx, const float* I, const float* J, int count, int m, int n, int p,
                      const tilt_params* prm, float* A, float* E, tilt_result* results, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Jacobi layout tuning.  The layout of the LDS-resident Jacobi (rows per
+ * block, lanes per row pair; the float4 chunks per lane follow from the row
+ * length) is chosen by a cost model unless a measured entry applies: a
+ * window whose min(m,n) and max(m,n) are both within a factor 1.5 of a
+ * tuned shape uses the layout measured for the nearest one (if valid for
+ * its row length).  The table is process-wide; calls are thread-safe and
+ * affect problems planned afterwards.
+ * ---------------------------------------------------------------------- */
+
+/* Valid layouts for an m x n window: writes up to max_count (rows per block,
+ * lanes per pair) pairs and returns how many exist (0 for tiled shapes). */
+int tilt_svt_layouts(int m, int n, int* bs, int* lpp, int max_count);
+/* Record the measured best layout for an m x n window. */
+int tilt_tune_set(int m, int n, int bs, int lpp);
+/* Forget all measured layouts (back to the cost model). */
+int tilt_tune_clear(void);
+
 /* Pyramid levels 1..levels-1 of one image (DEVICE pointers), as used when
  * pyramid_levels = levels: level l (ceil(H/2^l) x ceil(W/2^l), row-major,
  * contiguous) follows level l-1 in `out`.  levels in 2..4. */

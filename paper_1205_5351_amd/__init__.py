@@ -22,4 +22,16 @@ from .tilt import (  # noqa: F401
     workspace_bytes,
     EXPORTS,
     LIB_PATH,
+    load_tuning,
+    svt_layouts,
+    tune_clear,
+    tune_set,
 )
+
+import os as _os
+
+# Measured Jacobi layouts for this GPU (written by autotune.py); set
+# TILT_NO_TUNING=1 to use the built-in cost model only.
+TUNING_TABLE = _os.path.join(_os.path.dirname(_os.path.abspath(__file__)), "tuning", "mi355x_svt_layouts.json")
+if _os.path.exists(TUNING_TABLE) and not _os.environ.get("TILT_NO_TUNING"):
+    load_tuning(TUNING_TABLE)

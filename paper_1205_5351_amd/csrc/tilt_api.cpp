@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -121,6 +122,41 @@ size_t lds_bytes_tiled(int sb, int ncp, int ld, int ldg, int tb) {
 // largest super-blocks whose staged pair fits (fewest block loads, most
 // lane groups busy per round; the pairs examined per sweep, about ncp^2,
 // do not depend on the block size).
+// Measured layouts (autotuner): (nc, nr) -> (rows per block, lanes per
+// pair).  A query uses the entry nearest in log(nc), log(nr) within a factor
+// of 1.5 per axis, with the chunk count recomputed for its own row length;
+// otherwise, or when that layout is not valid there, the cost model.
+struct TuneEntry {
+    int nc, nr, bs, lpp;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+int tuned_cfg(int nc, int nr4) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const TuneEntry* best = nullptr;
+    double bd = 1e300;
+    const double lc = std::log((double)nc), lr = std::log(4.0 * nr4);
+    for (const auto& e : g_tune) {
+        const double dc = std::log((double)e.nc) - lc, dr = std::log((double)e.nr) - lr;
+        if (std::fabs(dc) > std::log(1.5) || std::fabs(dr) > std::log(1.5)) continue;
+        const double d = dc * dc + dr * dr;
+        if (d < bd) {
+            bd = d;
+            best = &e;
+        }
+    }
+    if (!best) return -1;
+    const int nch = (nr4 + best->lpp - 1) / best->lpp;
+    if (nch > (best->bs == 1 ? SVT_MAX_NCH : 4)) return -1;
+    return svt_make_cfg(best->bs, best->lpp, nch);
+}
+
+int choose_svt_cfg(int nc, int nr4) {
+    const int t = tuned_cfg(nc, nr4);
+    return t >= 0 ? t : pick_svt_cfg(nc, nr4);
+}
+
 int shape_config(int m, int n, ShapeCfg* out) {
     ShapeCfg c;
     c.colmajor = m >= n ? 1 : 0;
@@ -133,7 +169,7 @@ int shape_config(int m, int n, ShapeCfg* out) {
     const int nc4 = (c.nc + 3) & ~3;
     const size_t budget = (size_t)LDS_LIMIT - kStaticLdsMargin;
     if (nc4 <= SVT_MAX_ROWS) {
-        c.cfg = pick_svt_cfg(c.nc, c.ldg / 4);
+        c.cfg = choose_svt_cfg(c.nc, c.ldg / 4);
         if (c.cfg >= 0) {
             c.ld = pick_ld(c.cfg);
             for (int tb = 32; tb >= 16; tb -= 16) {
@@ -995,6 +1031,49 @@ int tilt_inner_batch(tilt_ctx* ctx, const float* I, const float* J, int count, i
         worst = worse(worst, r.status);
     }
     return worst;
+}
+
+int tilt_svt_layouts(int m, int n, int* bs, int* lpp, int max_count) {
+    if (m < 1 || n < 1 || !bs || !lpp || max_count < 0) return TILT_ERR_ARG;
+    const int nc = std::min(m, n), nr4 = (std::max(m, n) + 3) / 4;
+    ShapeCfg sc{};
+    if (shape_config(m, n, &sc) != TILT_OK || sc.sb > 0) return 0;  // tiled: not tunable here
+    const size_t budget = (size_t)LDS_LIMIT - kStaticLdsMargin;
+    int k = 0;
+    const int lpps[3] = {4, 8, 16};
+    for (int b = 1; b <= 2; ++b)
+        for (int li = 0; li < 3; ++li) {
+            const int nch = (nr4 + lpps[li] - 1) / lpps[li];
+            if (nch > (b == 1 ? SVT_MAX_NCH : 4)) continue;
+            const int ld = pick_ld(svt_make_cfg(b, lpps[li], nch));
+            if (lds_bytes(nc, ld, 16) > budget) continue;
+            if (k < max_count) {
+                bs[k] = b;
+                lpp[k] = lpps[li];
+            }
+            ++k;
+        }
+    return k;
+}
+
+int tilt_tune_set(int m, int n, int bs, int lpp) {
+    if (m < 1 || n < 1 || (bs != 1 && bs != 2) || (lpp != 4 && lpp != 8 && lpp != 16)) return TILT_ERR_ARG;
+    const int nc = std::min(m, n), nr = std::max(m, n);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (auto& e : g_tune)
+        if (e.nc == nc && e.nr == nr) {
+            e.bs = bs;
+            e.lpp = lpp;
+            return TILT_OK;
+        }
+    g_tune.push_back(TuneEntry{nc, nr, bs, lpp});
+    return TILT_OK;
+}
+
+int tilt_tune_clear(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
+    return TILT_OK;
 }
 
 }  // extern "C"

@@ -167,18 +167,53 @@ _lib.tilt_pyramid.restype = C.c_int
 _lib.tilt_inner_batch.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
                                   C.POINTER(Params), C.c_void_p, C.c_void_p, C.POINTER(Result), C.c_void_p]
 _lib.tilt_inner_batch.restype = C.c_int
+_lib.tilt_svt_layouts.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int]
+_lib.tilt_svt_layouts.restype = C.c_int
+_lib.tilt_tune_set.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+_lib.tilt_tune_set.restype = C.c_int
+_lib.tilt_tune_clear.argtypes = []
+_lib.tilt_tune_clear.restype = C.c_int
 
 EXPORTS = [
     "tilt_default_params", "tilt_status_string", "tilt_version", "tilt_tau_from_quad", "tilt_solve",
     "tilt_ctx_create", "tilt_ctx_destroy", "tilt_workspace_bytes", "tilt_solve_batch",
     "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_warp_jacobian", "tilt_last_error",
     "tilt_ctx_last_kernel_ms", "tilt_submit", "tilt_poll", "tilt_serve_stop", "tilt_pyramid",
-    "tilt_inner_batch",
+    "tilt_inner_batch", "tilt_svt_layouts", "tilt_tune_set", "tilt_tune_clear",
 ]
 
 
 def library():
     return _lib
+
+
+def svt_layouts(m: int, n: int):
+    """Valid (rows per block, lanes per pair) layouts of the LDS Jacobi for m x n."""
+    bs = (C.c_int * 8)()
+    lpp = (C.c_int * 8)()
+    k = _lib.tilt_svt_layouts(int(m), int(n), bs, lpp, 8)
+    return [(bs[i], lpp[i]) for i in range(min(k, 8))]
+
+
+def tune_set(m: int, n: int, bs: int, lpp: int):
+    rc = _lib.tilt_tune_set(int(m), int(n), int(bs), int(lpp))
+    if rc != TILT_OK:
+        raise TiltError(rc, "tilt_tune_set")
+
+
+def tune_clear():
+    _lib.tilt_tune_clear()
+
+
+def load_tuning(path: str) -> int:
+    """Apply a table written by autotune.py; returns the number of entries."""
+    import json
+
+    with open(path) as f:
+        table = json.load(f)
+    for e in table["entries"]:
+        tune_set(e["m"], e["n"], e["bs"], e["lpp"])
+    return len(table["entries"])
 
 
 def status_string(code: int) -> str:

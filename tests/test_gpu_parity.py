@@ -422,3 +422,32 @@ def test_bf16_full_solve_tolerances(tilt, ctx, device, mode, tau_tol, obj_tol):
     assert r["status"] >= 0
     assert O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n) <= tau_tol
     assert abs(r["objective"] - ref.objective) <= obj_tol * ref.objective
+
+
+@pytest.mark.parametrize("m,n", [(100, 100), (40, 130), (64, 200), (33, 17)])
+def test_svt_every_layout_matches_oracle(tilt, ctx, device, m, n):
+    """Each Jacobi layout the tuner may choose gives the oracle's SVT."""
+    import torch
+
+    rng = np.random.default_rng(77 * m + n)
+    L = rng.standard_normal((m, 3)) @ rng.standard_normal((3, n))
+    M = (L / np.linalg.norm(L) + 0.05 * rng.standard_normal((m, n)) / math.sqrt(m * n)).astype(np.float32)
+    Mb = np.stack([M, M])
+    dM = to_device(Mb, device)
+    eps = np.array([0.01, 0.02], np.float32)
+    layouts = tilt.svt_layouts(m, n)
+    assert len(layouts) >= 2
+    try:
+        for bs, lpp in layouts:
+            tilt.tune_set(m, n, bs, lpp)
+            dA = torch.zeros_like(dM)
+            ctx.svt_batch(dM.data_ptr(), dA.data_ptr(), 0, 2, m, n, eps)
+            A = dA.cpu().numpy()
+            for i in range(2):
+                Aref, _ = O.svt(M.astype(np.float64), float(eps[i]))
+                assert np.linalg.norm(A[i] - Aref) <= 1e-5 * np.linalg.norm(Aref), (bs, lpp, i)
+    finally:
+        tilt.tune_clear()
+        import os
+        if os.path.exists(tilt.TUNING_TABLE):
+            tilt.load_tuning(tilt.TUNING_TABLE)
