@@ -543,12 +543,14 @@ def components_main(args):
             ts_.append(1000 * (time.perf_counter() - t0))
         out[name + "_ms"] = round(min(ts_), 3)
         log(f"{name}: {min(ts_):.3f} ms per call ({len(ps)} windows)")
-    prm = T.default_params(lam=ps[0].lam, fixed_iters=1, max_outer=2, max_inner=50)
-    t0 = time.perf_counter()
-    ctx.solve_batch_plain(probs[:1], prm)
-    torch.cuda.synchronize()
-    out["plain_2x50_ms"] = round(1000 * (time.perf_counter() - t0), 1)
-    log(f"plain path, one patch, 2 x 50 iterations: {out['plain_2x50_ms']} ms")
+    for g in (0, 16):
+        prm = T.default_params(lam=ps[0].lam, fixed_iters=1, max_outer=2, max_inner=50, graph_inner=g)
+        t0 = time.perf_counter()
+        ctx.solve_batch_plain(probs[:1], prm)
+        torch.cuda.synchronize()
+        key = "plain_2x50_ms" if g == 0 else f"plain_2x50_graph{g}_ms"
+        out[key] = round(1000 * (time.perf_counter() - t0), 1)
+        log(f"plain path, one patch, 2 x 50 iterations, graph_inner={g}: {out[key]} ms")
     print(json.dumps({"components": out}), flush=True)
     ctx.close()
 

@@ -96,6 +96,10 @@ typedef struct {
                            l times, a ceil(m/2^l) x ceil(n/2^l) window, and
                            starts cold from the coarser level's transform
                            conjugated by diag(2, 2, 1).  Not in the paper.     */
+    int graph_inner;    /* plain path only: 0 (default) launches the inner
+                           iterations one by one; K in 1..256 runs them as
+                           replays of a HIP graph of K captured iterations
+                           (one stop-flag read per replay).  Same results.   */
 } tilt_params;
 
 /* One window of one image. */

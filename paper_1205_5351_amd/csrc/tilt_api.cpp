@@ -266,6 +266,7 @@ int validate_params(const tilt_params* p) {
     if (!(p->jacobi_tol > 0.f) || !(p->jacobi_tol < 1.f)) return TILT_ERR_ARG;
     if (p->svt_mode < 0 || p->svt_mode > 3) return TILT_ERR_ARG;
     if (p->pyramid_levels < 0 || p->pyramid_levels > MAX_LEVELS) return TILT_ERR_ARG;
+    if (p->graph_inner < 0 || p->graph_inner > 256) return TILT_ERR_ARG;
     if (!std::isfinite(p->lambda) || !std::isfinite(p->mu0)) return TILT_ERR_ARG;
     return TILT_OK;
 }
@@ -478,9 +479,45 @@ int upload(tilt_ctx* ctx, const Prepared& P, const std::vector<int>& live, std::
     return TILT_OK;
 }
 
+// Captured inner iterations: graph_k x (SVT, update) of one level.
+struct InnerGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    ~InnerGraph() {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
+int capture_inner(InnerGraph* G, const PatchDesc* d, PatchState* ds, const SolverParams& sp, size_t lds, int graph_k,
+                  hipStream_t stream) {
+    // One eager iteration first: it configures the kernel's LDS attribute
+    // outside the capture and is an ordinary inner iteration.
+    HIP_TRY(launch_svt(d, ds, sp, lds, stream));
+    HIP_TRY(launch_update(d, ds, sp, stream));
+    HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < graph_k; ++i) {
+        hipError_t e = launch_svt(d, ds, sp, lds, stream, false);
+        if (e == hipSuccess) e = launch_update(d, ds, sp, stream);
+        if (e != hipSuccess) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(stream, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            return record_hip_error(e, "capture of inner iterations", __LINE__);
+        }
+    }
+    HIP_TRY(hipStreamEndCapture(stream, &G->g));
+    HIP_TRY(hipGraphInstantiate(&G->ge, G->g, nullptr, nullptr, 0));
+    return TILT_OK;
+}
+
 // Host-driven loop over the step kernels for request k (mirrors
-// solve_request on the device: pyramid, then levels coarse to fine).
-int run_plain_request(tilt_ctx* ctx, size_t lds, const SolverParams& sp, int L, int k, hipStream_t stream) {
+// solve_request on the device: pyramid, then levels coarse to fine).  With
+// graph_k > 0 the inner iterations run as replays of a captured graph of
+// graph_k iterations (one stop-flag read per replay); the first inner
+// iteration of each inner loop is launched eagerly.
+int run_plain_request(tilt_ctx* ctx, size_t lds, const SolverParams& sp, int L, int k, hipStream_t stream,
+                      int graph_k) {
     const PatchDesc* dl = reinterpret_cast<const PatchDesc*>(ctx->descs.p) + (size_t)k * L;
     PatchState* ds = reinterpret_cast<PatchState*>(ctx->states.p) + k;
     PatchState hs;
@@ -500,15 +537,24 @@ int run_plain_request(tilt_ctx* ctx, size_t lds, const SolverParams& sp, int L, 
             if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
             if (hs.status < 0) break;
         }
+        InnerGraph graph;
         for (;;) {
             HIP_TRY(launch_setup(d, ds, sp, lds, stream));
             if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
             if (hs.status < 0) break;
-            for (;;) {
-                HIP_TRY(launch_svt(d, ds, sp, lds, stream));
-                HIP_TRY(launch_update(d, ds, sp, stream));
+            if (graph_k > 0 && !graph.ge) {
+                const int c = capture_inner(&graph, d, ds, sp, lds, graph_k, stream);
+                if (c != TILT_OK) return c;
                 if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
-                if (hs.done_inner) break;
+            }
+            while (!hs.done_inner) {
+                if (graph.ge) {
+                    HIP_TRY(hipGraphLaunch(graph.ge, stream));
+                } else {
+                    HIP_TRY(launch_svt(d, ds, sp, lds, stream));
+                    HIP_TRY(launch_update(d, ds, sp, stream));
+                }
+                if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
             }
             if (hs.status < 0) break;
             HIP_TRY(launch_dtau(d, ds, sp, stream));
@@ -547,10 +593,24 @@ int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const 
         const int nlive = (int)live.size();
         const int L = P.levels;
         if (plain) {
-            for (int k = 0; k < nlive; ++k) {
-                int r = run_plain_request(ctx, max_lds, sp, L, k, stream);
-                if (r != TILT_OK) return r;
+            hipStream_t ps = stream;
+            hipStream_t own = nullptr;
+            if (prm->graph_inner > 0) {
+                // capture needs a stream of our own (not the legacy default stream)
+                HIP_TRY(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+                HIP_TRY(hipEventRecord(ctx->ev0, stream));
+                HIP_TRY(hipStreamWaitEvent(own, ctx->ev0, 0));
+                ps = own;
             }
+            int r = TILT_OK;
+            for (int k = 0; k < nlive && r == TILT_OK; ++k) r = run_plain_request(ctx, max_lds, sp, L, k, ps, prm->graph_inner);
+            if (own) {
+                (void)hipEventRecord(ctx->ev1, own);
+                (void)hipStreamWaitEvent(stream, ctx->ev1, 0);
+                (void)hipStreamSynchronize(own);
+                (void)hipStreamDestroy(own);
+            }
+            if (r != TILT_OK) return r;
         } else {
             if (ctx->queue.reserve(256) != hipSuccess) return TILT_ERR_NOMEM;
             if (ctx->order.reserve(sizeof(int) * nlive) != hipSuccess) return TILT_ERR_NOMEM;

@@ -189,7 +189,8 @@ hipError_t launch_level_begin(const PatchDesc* d, PatchState* st, int first, hip
 hipError_t launch_pyramid_jobs(const float* image, int H, int W, long long stride, float* out, int levels,
                                hipStream_t s);
 hipError_t launch_setup(const PatchDesc* d, PatchState* st, const SolverParams& prm, size_t lds, hipStream_t s);
-hipError_t launch_svt(const PatchDesc* d, PatchState* st, const SolverParams& prm, size_t lds, hipStream_t s);
+hipError_t launch_svt(const PatchDesc* d, PatchState* st, const SolverParams& prm, size_t lds, hipStream_t s,
+                      bool configure = true);
 hipError_t launch_update(const PatchDesc* d, PatchState* st, const SolverParams& prm, hipStream_t s);
 hipError_t launch_dtau(const PatchDesc* d, PatchState* st, const SolverParams& prm, hipStream_t s);
 hipError_t launch_finalize(const PatchDesc* d, PatchState* st, int last, hipStream_t s);

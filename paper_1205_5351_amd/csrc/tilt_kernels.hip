@@ -2124,13 +2124,18 @@ __global__ void __launch_bounds__(NT) k_setup(const PatchDesc* dp, PatchState* s
     dev_setup(d, st, prm, lds);
 }
 
+// The inner-iteration kernels do nothing once the inner loop has stopped,
+// so a captured sequence of several iterations can be replayed past the
+// stopping point without changing the result.
 __global__ void __launch_bounds__(NT) k_svt(const PatchDesc* dp, PatchState* st, SolverParams prm) {
+    if (st->done_inner) return;
     float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
     const PatchDesc d = desc_at_level(dp, st);
     dev_svt(d, st, prm, lds);
 }
 
 __global__ void __launch_bounds__(NT) k_update(const PatchDesc* dp, PatchState* st, SolverParams prm) {
+    if (st->done_inner) return;
     const PatchDesc d = desc_at_level(dp, st);
     dev_update(d, st, prm);
 }
@@ -2353,9 +2358,12 @@ hipError_t launch_setup(const PatchDesc* d, PatchState* st, const SolverParams& 
     return hipGetLastError();
 }
 
-hipError_t launch_svt(const PatchDesc* d, PatchState* st, const SolverParams& prm, size_t lds, hipStream_t s) {
-    hipError_t e = set_lds((const void*)k_svt, lds);
-    if (e != hipSuccess) return e;
+hipError_t launch_svt(const PatchDesc* d, PatchState* st, const SolverParams& prm, size_t lds, hipStream_t s,
+                      bool configure) {
+    if (configure) {
+        hipError_t e = set_lds((const void*)k_svt, lds);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_svt, dim3(1), dim3(NT), lds, s, d, st, prm);
     return hipGetLastError();
 }

@@ -74,6 +74,7 @@ class Params(C.Structure):
         ("jacobi_tol", C.c_float),
         ("max_sweeps", C.c_int),
         ("pyramid_levels", C.c_int),
+        ("graph_inner", C.c_int),
     ]
 
 

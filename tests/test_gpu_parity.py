@@ -451,3 +451,23 @@ def test_svt_every_layout_matches_oracle(tilt, ctx, device, m, n):
         import os
         if os.path.exists(tilt.TUNING_TABLE):
             tilt.load_tuning(tilt.TUNING_TABLE)
+
+
+def test_plain_path_graph_replays_equal_eager(tilt, ctx, device):
+    """Inner iterations replayed from a captured HIP graph (many replays per
+    solve, with eager set-up and Delta-tau kernels and host reads between
+    them) give the same bits as eager launches and as the fused kernel."""
+    ps = ts.make_batch(1, [0, 1])
+    tp = tilt.default_params(lam=ps[0].lam, max_outer=6)
+    tg = tilt.default_params(lam=ps[0].lam, max_outer=6, graph_inner=8)
+    _, eager = solve_on_device(tilt, ctx, ps, device, tp, plain=True)
+    _, graph = solve_on_device(tilt, ctx, ps, device, tg, plain=True)
+    _, fused = solve_on_device(tilt, ctx, ps, device, tg)
+    for a, b, c in zip(eager, graph, fused):
+        assert a["inner_iters_total"] > 8 * 6
+        assert _same(a, b) and _same(b, c)
+    pyr = ts.make_batch(4, [23])
+    tq = tilt.default_params(pyramid_levels=3, max_outer=4, graph_inner=5)
+    _, g2 = solve_on_device(tilt, ctx, pyr, device, tq, plain=True)
+    _, f2 = solve_on_device(tilt, ctx, pyr, device, tq)
+    assert _same(g2[0], f2[0])
