@@ -8,3 +8,4 @@ it computes and which passages of the paper each step follows.
 from .tilt_oracle import *  # noqa: F401,F403
 from . import tilt_oracle  # noqa: F401
 from . import pyramid  # noqa: F401
+from . import svdws  # noqa: F401
