@@ -144,6 +144,8 @@ def main():
                     help="arrival window per rate in serving mode")
     ap.add_argument("--serve-max-outer", type=int, default=20,
                     help="outer iterations per pyramid level in serving mode")
+    ap.add_argument("--serve-max-inner", type=int, default=200,
+                    help="inner iterations per outer iteration in serving mode (a latency bound)")
     ap.add_argument("--convergence", action="store_true",
                     help="range-of-convergence sweep (checkerboard, 11 x 21 affine deformations, one batch)")
     ap.add_argument("--components", action="store_true",
@@ -661,7 +663,8 @@ def serve_main(args):
     outA = [torch.zeros((p.m, p.n), dtype=torch.float32, device=dev) for p in patches]
     outE = [torch.zeros((p.m, p.n), dtype=torch.float32, device=dev) for p in patches]
     levels = args.pyramid if args.pyramid > 1 else 3
-    prm = T.default_params(svt_mode=args.svt_mode, pyramid_levels=levels, max_outer=args.serve_max_outer)
+    prm = T.default_params(svt_mode=args.svt_mode, pyramid_levels=levels, max_outer=args.serve_max_outer,
+                           max_inner=args.serve_max_inner)
     ctx = T.Context(0)
     torch.cuda.synchronize()
 
@@ -729,6 +732,7 @@ def serve_main(args):
         "data": "synthetic",
         "config": {"workload": names[wl], "requests": n, "pyramid_levels": levels,
                    "max_outer_per_level": args.serve_max_outer,
+                   "max_inner_per_outer": args.serve_max_inner,
                    "svt": "cold" if args.svt_mode == 0 else "warm",
                    "value_is": "saturation throughput (all requests in flight)"},
         "latency_ms": {"p50_at_0.75": headline["latency_p50_ms"], "p99_at_0.75": headline["latency_p99_ms"],

@@ -182,7 +182,7 @@ struct ServeCtl {
 hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, int levels,
                         const int* order, int* queue, int grid, size_t lds, hipStream_t s);
 hipError_t launch_serve(ServeCtl* ctl, ServeSlot* slots, PatchDesc* ddesc, PatchState* dstates,
-                        unsigned long long* head, int ring, long long idle_ticks, int grid, size_t lds,
+                        unsigned long long* ctr, int ring, long long idle_ticks, int grid, size_t lds,
                         hipStream_t s);
 hipError_t launch_pyramid_build(const PatchDesc* d, int levels, hipStream_t s);
 hipError_t launch_level_begin(const PatchDesc* d, PatchState* st, int first, hipStream_t s);

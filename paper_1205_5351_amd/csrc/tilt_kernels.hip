@@ -2035,10 +2035,15 @@ __global__ void __launch_bounds__(NT) k_fused(const PatchDesc* __restrict__ desc
 // published requests, claims the next one with a compare-and-swap on the
 // device counter `head`, copies its descriptors and initial state to device
 // memory, solves it and writes the final state back to the slot before
-// raising the slot's `done`.  A workgroup exits when the host sets `stop`
-// or after `idle_ticks` of the device wall clock without work, so every
-// wave reaches an exit; the host relaunches the kernel when requests are
-// outstanding and it has ended.
+// raising the slot's `done`.  The workgroups leave together: `ctr` holds
+// the claim counter, the number of requests being solved, a closing latch
+// and the device wall-clock time of the last finished request.  A
+// workgroup that finds nothing to claim sets the latch when no request is
+// in flight and neither it nor any other workgroup has worked for
+// `idle_ticks`; every workgroup exits once the latch or the host's `stop`
+// is set, so every wave reaches an exit and none leaves while others still
+// solve.  The host clears the latch before each launch and relaunches the
+// kernel when requests are outstanding and it has ended.
 //
 // Workspaces are recycled between requests that may run on different
 // XCDs: an agent-scope fence at the start of a request drops stale cached
@@ -2047,27 +2052,52 @@ __global__ void __launch_bounds__(NT) k_fused(const PatchDesc* __restrict__ desc
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(NT) k_serve(ServeCtl* ctl, ServeSlot* slots, PatchDesc* ddesc, PatchState* dstates,
-                                               unsigned long long* head, int ring, long long idle_ticks) {
+                                               unsigned long long* ctr, int ring, long long idle_ticks) {
     __shared__ long long sh_seq;
     float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
     const int tid = threadIdx.x;
     long long idle_since = (long long)wall_clock64();
     for (;;) {
         if (tid == 0) {
+            unsigned long long* head = ctr;
+            unsigned long long* busy = ctr + 1;
+            unsigned long long* closing = ctr + 2;
+            unsigned long long* last_done = ctr + 3;
             long long seq = -1;
-            const unsigned long long tail =
-                __hip_atomic_load(&ctl->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-            unsigned long long h = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            while (h < tail) {
-                if (__hip_atomic_compare_exchange_strong(head, &h, h + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT)) {
-                    seq = (long long)h;
-                    break;
+            const bool closed = __hip_atomic_load(closing, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0ull;
+            if (!closed) {
+                const unsigned long long tail =
+                    __hip_atomic_load(&ctl->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                unsigned long long h = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (h < tail) {
+                    // counted as busy before the claim, so that no workgroup
+                    // closes the kernel between this claim and its solve
+                    __hip_atomic_fetch_add(busy, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                    while (h < tail) {
+                        if (__hip_atomic_compare_exchange_strong(head, &h, h + 1, __ATOMIC_ACQ_REL,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                            seq = (long long)h;
+                            break;
+                        }
+                    }
+                    if (seq < 0) __hip_atomic_fetch_add(busy, ~0ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
             if (seq < 0) {
                 const int stop = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                if (stop || (long long)wall_clock64() - idle_since > idle_ticks) seq = -2;
+                if (stop || closed) {
+                    seq = -2;
+                } else {
+                    const long long now = (long long)wall_clock64();
+                    const long long last =
+                        (long long)__hip_atomic_load(last_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const long long since = last > idle_since ? last : idle_since;
+                    if (now - since > idle_ticks &&
+                        __hip_atomic_load(busy, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0ull) {
+                        __hip_atomic_store(closing, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                        seq = -2;
+                    }
+                }
             }
             sh_seq = seq;
         }
@@ -2110,9 +2140,12 @@ __global__ void __launch_bounds__(NT) k_serve(ServeCtl* ctl, ServeSlot* slots, P
         }
         __threadfence_system();
         __syncthreads();
-        if (tid == 0) __hip_atomic_store(&sl->done, (unsigned long long)seq + 1ull, __ATOMIC_RELEASE,
-                                         __HIP_MEMORY_SCOPE_SYSTEM);
         idle_since = (long long)wall_clock64();
+        if (tid == 0) {
+            __hip_atomic_store(&sl->done, (unsigned long long)seq + 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_fetch_max(ctr + 3, (unsigned long long)idle_since, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(ctr + 1, ~0ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -2343,11 +2376,11 @@ hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& 
 }
 
 hipError_t launch_serve(ServeCtl* ctl, ServeSlot* slots, PatchDesc* ddesc, PatchState* dstates,
-                        unsigned long long* head, int ring, long long idle_ticks, int grid, size_t lds,
+                        unsigned long long* ctr, int ring, long long idle_ticks, int grid, size_t lds,
                         hipStream_t s) {
     hipError_t e = set_lds((const void*)k_serve, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_serve, dim3(grid), dim3(NT), lds, s, ctl, slots, ddesc, dstates, head, ring, idle_ticks);
+    hipLaunchKernelGGL(k_serve, dim3(grid), dim3(NT), lds, s, ctl, slots, ddesc, dstates, ctr, ring, idle_ticks);
     return hipGetLastError();
 }
 

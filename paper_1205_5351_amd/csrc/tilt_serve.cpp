@@ -176,6 +176,10 @@ int ensure_kernel(tilt_ctx* ctx, ServeState* S) {
     if (st != TILT_OK) return st;
     if (running) return TILT_OK;
     __atomic_store_n(&S->ctl->stop, 0, __ATOMIC_RELEASE);
+    // counters: claim index, requests in flight, closing latch, time of the
+    // last finished request; a new launch starts with the latch open
+    HIP_TRY(hipMemsetAsync(reinterpret_cast<unsigned long long*>(S->head.p) + 1, 0, 2 * sizeof(unsigned long long),
+                           S->stream));
     const long long idle_ticks = (long long)(kIdleMs * ctx->wall_rate_khz);
     HIP_TRY(launch_serve(S->ctl, S->slots, reinterpret_cast<PatchDesc*>(S->ddesc.p),
                          reinterpret_cast<PatchState*>(S->dstates.p),
