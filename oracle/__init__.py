@@ -9,3 +9,4 @@ from .tilt_oracle import *  # noqa: F401,F403
 from . import tilt_oracle  # noqa: F401
 from . import pyramid  # noqa: F401
 from . import svdws  # noqa: F401
+from . import rasl  # noqa: F401

@@ -18,4 +18,6 @@ from .textures import (  # noqa: F401
     inner_problem,
     checkerboard_patch,
     convergence_grid,
+    RaslSet,
+    rasl_set,
 )

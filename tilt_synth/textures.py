@@ -301,3 +301,81 @@ def convergence_grid():
     """(theta, t) of the range-of-convergence sweep: theta in [0, pi/6] in
     steps of pi/60, t in [0, 1] in steps of 0.05 (11 x 21 cases)."""
     return [(k * math.pi / 60.0, j * 0.05) for k in range(11) for j in range(21)]
+
+
+# ---------------------------------------------------------------------------
+# RASL sets: several images of one scene, each moved by its own small
+# planted transform; the data matrix holds one window per column.
+# ---------------------------------------------------------------------------
+
+RASL_SEED_OFFSET = 1000
+
+
+@dataclasses.dataclass
+class RaslSet:
+    """N images of one texture, image k = T(G_k^{-1}(x)) plus corruption."""
+
+    images: np.ndarray        # (N, H, W) float32
+    m: int
+    n: int
+    model: int
+    tau0: np.ndarray          # (N, 3, 3): centred grid px -> image px (all the same window)
+    lam: float
+    G_px: np.ndarray          # (N, 3, 3): planted transform, texture px -> image px
+    corruption: float
+
+    @property
+    def count(self) -> int:
+        return int(self.images.shape[0])
+
+    @property
+    def height(self) -> int:
+        return int(self.images.shape[1])
+
+    @property
+    def width(self) -> int:
+        return int(self.images.shape[2])
+
+
+def rasl_set(index: int, count: int = 16, m: int = 20, n: int = 24, height: int = 48, width: int = 56,
+             rank: int = 2, model: int = AFFINE, corruption: float = 0.05, shift_px: float = 1.5,
+             theta_deg: float = 2.0, scale_rng=(0.98, 1.02), lam: Optional[float] = None) -> RaslSet:
+    """Draw one RASL set.  The texture is the separable low-rank model above
+    (its parameters drawn for an m x n window); image k is that texture seen
+    through G_k = translation by U(-shift_px, shift_px) per axis after a
+    rotation U(-theta_deg, theta_deg) and a scale U(scale_rng), all about the
+    image centre.  tau0 is the axis-aligned window at the image centre for
+    every image; lambda defaults to 1/sqrt(max(m n, N))."""
+    rng = patch_rng(RASL_SEED_OFFSET + int(index), 0)
+    s = max(m, n) / 2.0
+    cx, cy = (width - 1) / 2.0, (height - 1) / 2.0
+    params = _texture_params(rng, rank, m, n)
+    jj, ii = np.meshgrid(np.arange(n), np.arange(m))
+    tmax = float(np.max(_texture(jj - (n - 1) / 2.0, ii - (m - 1) / 2.0, m, n, params)))
+    xs, ys = np.meshgrid(np.arange(width, dtype=np.float64), np.arange(height, dtype=np.float64))
+    imgs = np.zeros((count, height, width), np.float32)
+    G_all = np.zeros((count, 3, 3))
+    for k in range(count):
+        th = math.radians(rng.uniform(-theta_deg, theta_deg))
+        g = rng.uniform(*scale_rng)
+        dx, dy = rng.uniform(-shift_px, shift_px, size=2)
+        G = np.array([[g * math.cos(th), -g * math.sin(th), cx + dx],
+                      [g * math.sin(th), g * math.cos(th), cy + dy],
+                      [0.0, 0.0, 1.0]])
+        Gi = np.linalg.inv(G)
+        u = Gi[0, 0] * xs + Gi[0, 1] * ys + Gi[0, 2]
+        v = Gi[1, 0] * xs + Gi[1, 1] * ys + Gi[1, 2]
+        img = _texture(u, v, m, n, params) / tmax
+        npx = height * width
+        c = int(round(corruption * npx))
+        if c > 0:
+            idx = rng.choice(npx, size=c, replace=False)
+            flat = img.reshape(-1)
+            flat[idx] = rng.uniform(0.0, 1.0, size=c)
+        imgs[k] = img
+        G_all[k] = G
+    tau0 = np.tile(np.array([[1.0, 0.0, cx], [0.0, 1.0, cy], [0.0, 0.0, 1.0]]), (count, 1, 1))
+    if lam is None:
+        lam = 1.0 / math.sqrt(max(m * n, count))
+    return RaslSet(images=imgs, m=int(m), n=int(n), model=int(model), tau0=tau0, lam=float(lam),
+                   G_px=G_all, corruption=float(corruption))
