@@ -294,6 +294,52 @@ int tilt_tune_clear(void);
 int tilt_pyramid(tilt_ctx* ctx, const float* image, int height, int width, long long row_stride, float* out,
                  int levels, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * RASL variant.  The paper (Sec. 1, on RASL) notes that TILT and RASL share
+ * one model and differ only in the data matrix: for RASL it holds several
+ * images, one per column.  Here column k is the m x n window of image k
+ * warped by its own transform tau_k and normalised to unit norm; its
+ * Jacobian depends on tau_k alone, so J_perp acts on every column
+ * separately, and Alg. 1 runs unchanged otherwise (Sec. 4.2 inner loop,
+ * Delta tau_k = (J_k^T J_k)^{-1} J_k^T (a_k + e_k - d_k)).  No extra
+ * constraints are put on the transforms; lambda <= 0 selects
+ * 1/sqrt(max(m n, count)); the outer loop stops when the norm of all
+ * Delta tau_k together is below eps_outer.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const float* images;     /* DEVICE: `count` images, image k at images + k * image_stride */
+    long long image_stride;  /* floats from one image to the next                          */
+    int height, width;       /* size of every image (>= 2 x 2)                             */
+    long long row_stride;    /* floats from one image row to the next (>= width)           */
+    int count;               /* images = columns of the data matrix, 2 <= count < m n      */
+    int m, n;                /* common rectified window, m n <= 512                        */
+    int model;               /* TILT_AFFINE or TILT_PROJECTIVE                             */
+    const double* tau0;      /* HOST: count row-major 3x3 homographies, centred window
+                                pixel (u, v, 1) -> image pixel (x, y, 1)                    */
+} tilt_rasl_problem;
+
+typedef struct {
+    double* tau;             /* HOST, caller-allocated count x 9: the final transforms     */
+    float* A;                /* DEVICE, caller-allocated count x m x n (window k row-major
+                                at k m n), or NULL                                         */
+    float* E;                /* same layout, or NULL                                       */
+    double objective;        /* ||A||_* + lambda ||E||_1 of the last inner loop            */
+    int outer_iters, inner_iters_total;
+    int svt_rank;            /* singular values of the last SVT argument above 1/mu        */
+    int status;              /* TILT_OK, TILT_WARN_MAXITER or an error                     */
+    double solve_ms;         /* device wall-clock time of this solve                       */
+} tilt_rasl_result;
+
+/* Solve `count` independent RASL problems in one fused kernel (one
+ * workgroup per problem, work queue).  Inputs and A/E are device memory;
+ * tau0 and tau are host memory.  `prm->svt_mode` must be 0 and
+ * `prm->pyramid_levels` 1.  TILT_ERR_ARG for invalid shapes or transforms,
+ * TILT_ERR_TOO_LARGE when m n exceeds 512 or the count x m n matrix does not
+ * fit the SVT; per-problem failures are in res[k].status and the call
+ * returns the worst status.  The stream is synchronised before returning. */
+int tilt_rasl_solve_batch(tilt_ctx* ctx, const tilt_rasl_problem* probs, int count, const tilt_params* prm,
+                          tilt_rasl_result* res, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

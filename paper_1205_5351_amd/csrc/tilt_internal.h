@@ -134,6 +134,23 @@ __host__ __device__ inline void to_finer_h(double* H) {
     H[7] *= 0.5;
 }
 
+// RASL problem: the data matrix holds one window per image.  In the X
+// layout of `d` the images are the rows (nc = count, nr = m n, colmajor =
+// 0), so the one-sided Jacobi orthogonalises whole windows and the
+// per-image projections run along contiguous rows.  d.image, d.stride, d.H
+// and d.W describe image 0; image k starts img_stride floats further.
+// d.s is the common scale; every image has its own window centre in geo and
+// transform in tau, both in the workspace after the planes.
+struct RaslDesc {
+    PatchDesc d;
+    long long img_stride;
+    double* tau;   // count x MAXP scaled transforms (updated in place)
+    double* geo;   // count x 2 window centres (cx, cy)
+    double* Rf;    // count x MAXP x MAXP: J_k = Q_k R_k, R_k upper triangular
+    int count;
+    int pad[3];
+};
+
 // Launch shape of the SVT for one matrix shape.
 struct SvtShape {
     int cfg, ld, tb;
@@ -181,6 +198,8 @@ struct ServeCtl {
 // Kernel launchers (tilt_kernels.hip).
 hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, int levels,
                         const int* order, int* queue, int grid, size_t lds, hipStream_t s);
+hipError_t launch_rasl(const RaslDesc* d, PatchState* st, const SolverParams& prm, int count, int* queue, int grid,
+                       size_t lds, hipStream_t s);
 hipError_t launch_serve(ServeCtl* ctl, ServeSlot* slots, PatchDesc* ddesc, PatchState* dstates,
                         unsigned long long* ctr, int ring, long long idle_ticks, int grid, size_t lds,
                         hipStream_t s);

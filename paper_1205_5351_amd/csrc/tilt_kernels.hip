@@ -1658,6 +1658,35 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
 // E-, Y- and mu-updates with the two J~perp products of Sec. 4.2
 // ---------------------------------------------------------------------------
 
+// Cond1, Cond2 (Eqs. Cond1, Cond2), the penalty update (Eqs. mu, rho) and
+// the inner stop, from ||J~perp(A + E - I)||^2 and ||E_{k+1} - E_k||^2
+// (||A_{k+1} - A_k||^2 is in the state).  One thread.
+__device__ void finish_inner_iteration(PatchState* st, const SolverParams& prm, double r2, double dE2) {
+    const double mu = st->mu;
+    const double c = st->c;
+    const double dA = sqrt(st->dA2), dE = sqrt(dE2);
+    const double cond1 = sqrt(r2) / c;
+    const double cond2 = mu * fmax(dA, dE) / c;
+    st->cond1 = cond1;
+    st->cond2 = cond2;
+    st->inner += 1;
+    st->inner_total += 1;
+    int stop = 0;
+    if (!isfinite(cond1) || !isfinite(cond2)) {
+        st->status = -5;
+        st->done_outer = 1;
+        stop = 1;
+    } else {
+        if (!prm.fixed_iters && cond1 < prm.eps1 && cond2 < prm.eps2) stop = 1;
+        if (!stop && cond2 < prm.eps2) st->mu = fmin(prm.mu_max, prm.rho0 * mu);
+        if (!stop && st->inner >= prm.max_inner) {
+            stop = 1;
+            if (!prm.fixed_iters) st->warn = 1;
+        }
+    }
+    st->done_inner = stop;
+}
+
 __device__ void dev_update(const PatchDesc& d, PatchState* st, const SolverParams& prm) {
     const int tid = threadIdx.x;
     const int pp = d.pp;
@@ -1765,36 +1794,27 @@ __device__ void dev_update(const PatchDesc& d, PatchState* st, const SolverParam
     }
     block_sum_f<1>(r2);
 
-    if (tid == 0) {
-        const double c = st->c;
-        const double dA = sqrt(st->dA2), dE = sqrt((double)t2[MAXPP]);
-        const double cond1 = sqrt((double)r2[0]) / c;
-        const double cond2 = mu * fmax(dA, dE) / c;
-        st->cond1 = cond1;
-        st->cond2 = cond2;
-        st->inner += 1;
-        st->inner_total += 1;
-        int stop = 0;
-        if (!isfinite(cond1) || !isfinite(cond2)) {
-            st->status = -5;
-            st->done_outer = 1;
-            stop = 1;
-        } else {
-            if (!prm.fixed_iters && cond1 < prm.eps1 && cond2 < prm.eps2) stop = 1;
-            if (!stop && cond2 < prm.eps2) st->mu = fmin(prm.mu_max, prm.rho0 * mu);
-            if (!stop && st->inner >= prm.max_inner) {
-                stop = 1;
-                if (!prm.fixed_iters) st->warn = 1;
-            }
-        }
-        st->done_inner = stop;
-    }
+    if (tid == 0) finish_inner_iteration(st, prm, (double)r2[0], (double)t2[MAXPP]);
     __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // Steps 3 and 4: Delta tau and the transform update
 // ---------------------------------------------------------------------------
+
+// Outer stop from ||Delta tau||^2 (one thread).
+__device__ void finish_outer_iteration(PatchState* st, const SolverParams& prm, double nrm2, bool finite) {
+    st->dtau_norm = sqrt(nrm2);
+    st->outer += 1;
+    int stop = 0;
+    if (!finite) {
+        st->status = -5;
+        stop = 1;
+    }
+    if (!prm.fixed_iters && st->dtau_norm < prm.eps_outer) stop = 1;
+    if (st->outer >= prm.max_outer) stop = 1;
+    st->done_outer = stop;
+}
 
 __device__ void dev_dtau(const PatchDesc& d, PatchState* st, const SolverParams& prm) {
     const int tid = threadIdx.x;
@@ -1832,16 +1852,7 @@ __device__ void dev_dtau(const PatchDesc& d, PatchState* st, const SolverParams&
             nrm2 += dk * dk;
             finite = finite && isfinite(st->tau[k]);
         }
-        st->dtau_norm = sqrt(nrm2);
-        st->outer += 1;
-        int stop = 0;
-        if (!finite) {
-            st->status = -5;
-            stop = 1;
-        }
-        if (!prm.fixed_iters && st->dtau_norm < prm.eps_outer) stop = 1;
-        if (st->outer >= prm.max_outer) stop = 1;
-        st->done_outer = stop;
+        finish_outer_iteration(st, prm, nrm2, finite);
     }
     __syncthreads();
 }
@@ -2352,6 +2363,8 @@ __global__ void __launch_bounds__(NT) k_svt_jobs(const SvtJob* jobs, SvtShape sh
         c[3] = k;
     }
 }
+
+#include "tilt_rasl.inc"
 
 // ---------------------------------------------------------------------------
 // Launchers

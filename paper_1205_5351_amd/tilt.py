@@ -123,6 +123,35 @@ class Result(C.Structure):
     ]
 
 
+class RaslProblem(C.Structure):
+    _fields_ = [
+        ("images", C.c_void_p),
+        ("image_stride", C.c_longlong),
+        ("height", C.c_int),
+        ("width", C.c_int),
+        ("row_stride", C.c_longlong),
+        ("count", C.c_int),
+        ("m", C.c_int),
+        ("n", C.c_int),
+        ("model", C.c_int),
+        ("tau0", C.POINTER(C.c_double)),
+    ]
+
+
+class RaslResult(C.Structure):
+    _fields_ = [
+        ("tau", C.POINTER(C.c_double)),
+        ("A", C.c_void_p),
+        ("E", C.c_void_p),
+        ("objective", C.c_double),
+        ("outer_iters", C.c_int),
+        ("inner_iters_total", C.c_int),
+        ("svt_rank", C.c_int),
+        ("status", C.c_int),
+        ("solve_ms", C.c_double),
+    ]
+
+
 _lib.tilt_default_params.argtypes = [C.POINTER(Params)]
 _lib.tilt_default_params.restype = None
 _lib.tilt_status_string.argtypes = [C.c_int]
@@ -174,13 +203,16 @@ _lib.tilt_tune_set.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
 _lib.tilt_tune_set.restype = C.c_int
 _lib.tilt_tune_clear.argtypes = []
 _lib.tilt_tune_clear.restype = C.c_int
+_lib.tilt_rasl_solve_batch.argtypes = [C.c_void_p, C.POINTER(RaslProblem), C.c_int, C.POINTER(Params),
+                                       C.POINTER(RaslResult), C.c_void_p]
+_lib.tilt_rasl_solve_batch.restype = C.c_int
 
 EXPORTS = [
     "tilt_default_params", "tilt_status_string", "tilt_version", "tilt_tau_from_quad", "tilt_solve",
     "tilt_ctx_create", "tilt_ctx_destroy", "tilt_workspace_bytes", "tilt_solve_batch",
     "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_warp_jacobian", "tilt_last_error",
     "tilt_ctx_last_kernel_ms", "tilt_submit", "tilt_poll", "tilt_serve_stop", "tilt_pyramid",
-    "tilt_inner_batch", "tilt_svt_layouts", "tilt_tune_set", "tilt_tune_clear",
+    "tilt_inner_batch", "tilt_svt_layouts", "tilt_tune_set", "tilt_tune_clear", "tilt_rasl_solve_batch",
 ]
 
 
@@ -440,6 +472,44 @@ class Context:
                                C.c_void_p(int(out_ptr)), int(levels), C.c_void_p(_stream_ptr(stream)))
         if rc != TILT_OK:
             raise TiltError(rc, "tilt_pyramid")
+
+    def rasl_solve_batch(self, sets, params=None, outs_A=None, outs_E=None, stream=None):
+        """RASL problems: `sets` is a list of dicts with the device pointer
+        `images` (count images, image_stride floats apart), height, width,
+        row_stride, count, m, n, model and tau0 (count x 3 x 3, host).
+        Returns (worst status, per-problem dicts with tau (count x 3 x 3),
+        objective, outer_iters, inner_iters_total, svt_rank, status,
+        solve_ms)."""
+        n = len(sets)
+        prm = params if params is not None else default_params()
+        parr = (RaslProblem * n)()
+        rarr = (RaslResult * n)()
+        keep = []
+        for i, st in enumerate(sets):
+            N = int(st["count"])
+            t0 = np.ascontiguousarray(np.asarray(st["tau0"], np.float64).reshape(N * 9))
+            tb = (C.c_double * (N * 9))(*t0.tolist())
+            tout = (C.c_double * (N * 9))()
+            keep += [tb, tout]
+            parr[i] = RaslProblem(C.c_void_p(int(st["images"])), int(st["image_stride"]), int(st["height"]),
+                                  int(st["width"]), int(st["row_stride"]), N, int(st["m"]), int(st["n"]),
+                                  int(st["model"]), C.cast(tb, C.POINTER(C.c_double)))
+            rarr[i].tau = C.cast(tout, C.POINTER(C.c_double))
+            rarr[i].A = C.c_void_p(int(outs_A[i])) if outs_A is not None and outs_A[i] else None
+            rarr[i].E = C.c_void_p(int(outs_E[i])) if outs_E is not None and outs_E[i] else None
+        rc = _lib.tilt_rasl_solve_batch(self._h, parr, n, C.byref(prm), rarr, C.c_void_p(_stream_ptr(stream)))
+        if rc < 0 and rc not in (TILT_ERR_SINGULAR, TILT_ERR_NONFINITE, TILT_ERR_TOO_LARGE, TILT_ERR_ARG):
+            raise TiltError(rc, "tilt_rasl_solve_batch")
+        out = []
+        for i, st in enumerate(sets):
+            N = int(st["count"])
+            r = rarr[i]
+            out.append(dict(tau=np.array([r.tau[k] for k in range(9 * N)]).reshape(N, 3, 3),
+                            objective=r.objective, outer_iters=r.outer_iters,
+                            inner_iters_total=r.inner_iters_total, svt_rank=r.svt_rank, status=r.status,
+                            solve_ms=r.solve_ms))
+        del keep
+        return rc, out
 
     def warp_jacobian(self, problems: List[Problem], taus, I_ptr: int, J_ptr: int, stream=None):
         n = len(problems)

@@ -1,0 +1,153 @@
+"""RASL variant on the GPU (tilt_rasl_solve_batch) against the FP64 oracle
+(oracle/rasl.py) on the same seeded image sets.
+
+* fixed iteration counts (both sides run exactly the same iterations):
+  tau within 1e-5 (relative, scaled coordinates, every image), A and E
+  within 1e-4 of ||A|| -- the FP32 arithmetic of a few iterations;
+* the same with the count x m n matrix too large for LDS (tiled SVT);
+* converged inner loops over several outer iterations: tau within 1e-4,
+  objective within 1e-4 (relative), the same numerical rank;
+* planted misalignments are undone on the device as by the oracle;
+* problems solved together equal the same problems solved alone, bit for
+  bit (the same device functions run for each, whatever the mix);
+* invalid shapes and modes are rejected before any launch.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import tilt_synth as ts
+from gpu_util import oracle_params, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _descs(sets, device):
+    keep, descs = [], []
+    for r in sets:
+        imgs = to_device(r.images, device)
+        keep.append(imgs)
+        descs.append(dict(images=imgs.data_ptr(), image_stride=r.height * r.width, height=r.height, width=r.width,
+                          row_stride=r.width, count=r.count, m=r.m, n=r.n, model=r.model, tau0=r.tau0))
+    return descs, keep
+
+
+def _run(ctx, device, sets, tp):
+    import torch
+
+    descs, keep = _descs(sets, device)
+    As = [torch.zeros((r.count, r.m, r.n), dtype=torch.float32, device=device) for r in sets]
+    Es = [torch.zeros((r.count, r.m, r.n), dtype=torch.float32, device=device) for r in sets]
+    rc, res = ctx.rasl_solve_batch(descs, tp, [a.data_ptr() for a in As], [e.data_ptr() for e in Es])
+    torch.cuda.synchronize()
+    for out, a, e, r in zip(res, As, Es, sets):
+        out["A"] = a.cpu().numpy().reshape(r.count, -1).T.astype(np.float64)   # L x N, as the oracle
+        out["E"] = e.cpu().numpy().reshape(r.count, -1).T.astype(np.float64)
+    del keep
+    return rc, res
+
+
+def _tau_err(H_gpu, H_ref, m, n):
+    return max(O.tau_rel_err(H_gpu[k], H_ref[k], m, n) for k in range(len(H_ref)))
+
+
+def _print(name, **kw):
+    print(name, " ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+@pytest.mark.parametrize("model", [O.AFFINE, O.PROJECTIVE])
+def test_rasl_fixed_iterations_match_oracle(tilt, ctx, device, model):
+    r = ts.rasl_set(2, count=8, m=12, n=14, height=32, width=36, model=model)
+    tp = tilt.default_params(fixed_iters=1, max_outer=2, max_inner=8, lambda_=r.lam)
+    rc, res = _run(ctx, device, [r], tp)
+    g = res[0]
+    ref = O.rasl.rasl_solve(r.images, r.tau0, r.m, r.n, r.model, oracle_params(O, tp), lam=r.lam)
+    e_tau = _tau_err(g["tau"], ref.tau_px, r.m, r.n)
+    e_A = np.linalg.norm(g["A"] - ref.A) / np.linalg.norm(ref.A)
+    e_E = np.linalg.norm(g["E"] - ref.E) / np.linalg.norm(ref.A)
+    _print("rasl fixed", model=model, tau=e_tau, A=e_A, E=e_E)
+    assert g["status"] == 0 and rc == 0
+    assert g["outer_iters"] == 2 and g["inner_iters_total"] == 16
+    assert e_tau <= 1e-5
+    assert e_A <= 1e-4 and e_E <= 1e-4
+
+
+def test_rasl_tiled_svt_fixed_iterations_match_oracle(tilt, ctx, device):
+    """160 windows of 16 x 24: the 160 x 384 matrix exceeds LDS, so the SVT
+    runs tiled through the device working plane."""
+    r = ts.rasl_set(5, count=160, m=16, n=24, height=40, width=48)
+    tp = tilt.default_params(fixed_iters=1, max_outer=1, max_inner=4, lambda_=r.lam)
+    rc, res = _run(ctx, device, [r], tp)
+    g = res[0]
+    ref = O.rasl.rasl_solve(r.images, r.tau0, r.m, r.n, r.model, oracle_params(O, tp), lam=r.lam)
+    e_tau = _tau_err(g["tau"], ref.tau_px, r.m, r.n)
+    e_A = np.linalg.norm(g["A"] - ref.A) / np.linalg.norm(ref.A)
+    _print("rasl tiled", tau=e_tau, A=e_A)
+    assert g["status"] == 0
+    assert e_tau <= 1e-5 and e_A <= 1e-4
+
+
+def test_rasl_converged_matches_oracle(tilt, ctx, device):
+    r = ts.rasl_set(3, count=10, m=12, n=14, height=32, width=36)
+    tp = tilt.default_params(max_outer=5, lambda_=r.lam)
+    rc, res = _run(ctx, device, [r], tp)
+    g = res[0]
+    ref = O.rasl.rasl_solve(r.images, r.tau0, r.m, r.n, r.model, oracle_params(O, tp), lam=r.lam)
+    e_tau = _tau_err(g["tau"], ref.tau_px, r.m, r.n)
+    e_obj = abs(g["objective"] - ref.objective) / ref.objective
+    _print("rasl converged", tau=e_tau, obj=e_obj, inner_gpu=g["inner_iters_total"],
+           inner_ref=sum(ref.inner_iters), rank_gpu=O.numerical_rank(g["A"]), rank_ref=O.numerical_rank(ref.A))
+    assert g["status"] >= 0
+    assert e_tau <= 1e-4
+    assert e_obj <= 1e-4
+    assert O.numerical_rank(g["A"]) == O.numerical_rank(ref.A)
+
+
+def test_rasl_undoes_planted_misalignment(tilt, ctx, device):
+    r = ts.rasl_set(4, count=32, m=16, n=24, height=48, width=56)
+    tp = tilt.default_params(max_outer=15, lambda_=r.lam)
+    rc, res = _run(ctx, device, [r], tp)
+    taus = res[0]["tau"]
+    Ms = [np.linalg.inv(r.G_px[k]) @ taus[k] for k in range(r.count)]
+    M0 = np.mean(Ms, axis=0)
+    a, b = (r.n - 1) / 2.0, (r.m - 1) / 2.0
+    corners = np.array([[-a, -b, 1], [a, -b, 1], [a, b, 1], [-a, b, 1]]).T
+    ref = M0 @ corners
+    ref = ref[:2] / ref[2]
+    worst = 0.0
+    for M in Ms:
+        c = M @ corners
+        worst = max(worst, float(np.max(np.linalg.norm(c[:2] / c[2] - ref, axis=0))))
+    _print("rasl recovery", spread_px=worst, outer=res[0]["outer_iters"])
+    assert res[0]["status"] >= 0
+    assert worst < 0.15
+
+
+def test_rasl_batch_mix_equals_alone(tilt, device):
+    sets = [ts.rasl_set(6, count=8, m=12, n=14, height=32, width=36),
+            ts.rasl_set(7, count=20, m=16, n=24, height=40, width=48, model=O.PROJECTIVE),
+            ts.rasl_set(8, count=6, m=10, n=10, height=24, width=28)]
+    tp = tilt.default_params(max_outer=3)
+    with tilt.Context(0) as c:
+        _, together = _run(c, device, sets, tp)
+        alone = [_run(c, device, [s], tp)[1][0] for s in sets]
+    for a, b in zip(together, alone):
+        assert np.array_equal(a["tau"], b["tau"])
+        assert np.array_equal(a["A"], b["A"]) and np.array_equal(a["E"], b["E"])
+        assert a["inner_iters_total"] == b["inner_iters_total"]
+
+
+def test_rasl_rejects_invalid_problems(tilt, ctx, device):
+    r = ts.rasl_set(9, count=8, m=12, n=14, height=32, width=36)
+    descs, keep = _descs([r], device)
+    tp = tilt.default_params()
+    rc, _ = ctx.rasl_solve_batch([dict(descs[0], count=8, m=2, n=4)], tp)       # count >= m n
+    assert rc == tilt.tilt.TILT_ERR_ARG
+    big = ts.rasl_set(9, count=4, m=24, n=24, height=40, width=40)
+    d2, k2 = _descs([big], device)
+    rc, _ = ctx.rasl_solve_batch(d2, tp)                                        # m n > 512
+    assert rc == tilt.tilt.TILT_ERR_TOO_LARGE
+    rc, _ = ctx.rasl_solve_batch(descs, tilt.default_params(svt_mode=1))        # warm SVT not offered
+    assert rc == tilt.tilt.TILT_ERR_ARG
+    del keep, k2

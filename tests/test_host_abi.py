@@ -104,6 +104,9 @@ def test_argument_validation_without_device(tilt):
     bad = tilt.default_params(eps1=0.0)
     assert lib.tilt_solve(C.byref(pr), C.byref(bad), C.byref(res)) == tilt.tilt.TILT_ERR_ARG
     assert lib.tilt_ctx_destroy(None) == tilt.tilt.TILT_ERR_ARG
+    rp = (tilt.tilt.RaslProblem * 1)()
+    rr = (tilt.tilt.RaslResult * 1)()
+    assert lib.tilt_rasl_solve_batch(None, rp, 1, C.byref(prm), rr, None) == tilt.tilt.TILT_ERR_ARG
 
 
 def test_missing_library_fails_loudly():
