@@ -73,24 +73,29 @@ def solve_flops(res, p, warm=False):
     return f
 
 
-def profiled_traffic(workload: str):
-    """HBM bytes per launch of the fused kernel from the committed rocprofv3
-    summary of this workload, or None when the kernel source has changed
-    since the counters were taken (or no summary exists)."""
+def kernel_source_sha(sources=("tilt_kernels.hip",)) -> str:
     import hashlib
 
-    prof = os.path.join(ROOT, "profiles", f"k_fused_{workload.replace('batch-256x100x100-projective', 'batch256x100x100')}.md")
-    src = os.path.join(ROOT, "paper_1205_5351_amd", "csrc", "tilt_kernels.hip")
-    if not (os.path.exists(prof) and os.path.exists(src)):
+    h = hashlib.sha256()
+    for name in sources:
+        h.update(open(os.path.join(ROOT, "paper_1205_5351_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(profile: str, sources=("tilt_kernels.hip",)):
+    """HBM bytes per launch of a kernel from its committed rocprofv3 summary
+    (profiles/<profile>), or None when the kernel source has changed since
+    the counters were taken (or no summary exists)."""
+    prof = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(prof):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     fields = {}
     for line in open(prof):
         line = line.strip().lstrip("- ")
         if ":" in line:
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    if fields.get("kernel_source_sha256_16") != sha or "traffic_bytes" not in fields:
+    if fields.get("kernel_source_sha256_16") != kernel_source_sha(sources) or "traffic_bytes" not in fields:
         return None
     return int(fields["traffic_bytes"])
 
@@ -157,6 +162,11 @@ def main():
                          "refinement, warm bfloat16; tau and objective errors against the FP64 oracle")
     ap.add_argument("--inner", action="store_true",
                     help="inner-loop-only mode (random I and J, the setting of Table 1)")
+    ap.add_argument("--rasl", action="store_true",
+                    help="RASL variant: a batch of image sets (one window per image as the columns of the data "
+                         "matrix), one fused launch; sets/s, images/s, latency, roofline, CPU oracle on a sample")
+    ap.add_argument("--rasl-sets", type=int, default=256)
+    ap.add_argument("--rasl-max-outer", type=int, default=10)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the solve, copy a buffer of this many MiB on the device (a plain copy of "
                          "known size, used to calibrate HBM byte counters in profiles)")
@@ -178,6 +188,8 @@ def main():
         return serve_main(args)
     if args.inner:
         return inner_main(args)
+    if args.rasl:
+        return rasl_main(args)
     if args.precision:
         return precision_main(args)
     if args.components:
@@ -322,7 +334,9 @@ def main():
             "peak": PEAK_FP32_VECTOR_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-            "traffic": profiled_traffic(names[args.workload]),
+            "traffic": (profiled_traffic("k_fused_batch256x100x100.md")
+                        if names[args.workload] == "batch-256x100x100-projective" and args.svt_mode == 0
+                        and args.pyramid == 1 and args.patches in (None, 256) else None),
             "kernel_ms": round(k_ms, 2),
             "flops_per_launch": flops,
         },
@@ -636,6 +650,143 @@ def inner_main(args):
         "sizes": rows,
         "roofline": None,
         "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+RASL_SHAPE = dict(count=32, m=16, n=24, height=48, width=56)
+
+
+def _rasl_oracle_worker(args):
+    idx, prm_kw = args
+    import oracle as O
+    import tilt_synth as ts
+
+    r = ts.rasl_set(idx, **RASL_SHAPE)
+    t0 = time.perf_counter()
+    res = O.rasl.rasl_solve(r.images, r.tau0, r.m, r.n, r.model, O.Params(**prm_kw), lam=r.lam)
+    return time.perf_counter() - t0, res.tau_px
+
+
+def rasl_main(args):
+    """RASL variant: `--rasl-sets` independent image sets, each 32 images of
+    48 x 56 with a 16 x 24 window (the data matrix is 384 x 32), affine,
+    5 % corruption, planted shifts of up to 1.5 px; one fused launch
+    (k_rasl, one workgroup per set).  Reports sets/s and images/s over the
+    kernel time, per-set latency, the alignment error against the planted
+    transforms, the roofline of k_rasl from its work counters, and the FP64
+    oracle on a sample of sets (its tau compared with the device's)."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    import paper_1205_5351_amd as T
+    import tilt_synth as ts
+
+    dev = torch.device("cuda:0")
+    ctx = T.Context(0)
+    nsets = args.rasl_sets
+    t_gen = time.perf_counter()
+    sets = [ts.rasl_set(i, **RASL_SHAPE) for i in range(nsets)]
+    log(f"generated {nsets} RASL sets in {time.perf_counter() - t_gen:.1f}s")
+    imgs = [torch.from_numpy(r.images).to(dev) for r in sets]
+    descs = [dict(images=im.data_ptr(), image_stride=r.height * r.width, height=r.height, width=r.width,
+                  row_stride=r.width, count=r.count, m=r.m, n=r.n, model=r.model, tau0=r.tau0)
+             for im, r in zip(imgs, sets)]
+    As = [torch.zeros((r.count, r.m, r.n), dtype=torch.float32, device=dev) for r in sets]
+    Es = [torch.zeros_like(a) for a in As]
+    lam = sets[0].lam
+    prm = T.default_params(lam=lam, max_outer=args.rasl_max_outer)
+    if args.copy_probe_mib > 0:
+        nel = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
+    for w in range(args.warmup):
+        ctx.rasl_solve_batch(descs[:min(8, nsets)], prm)
+    torch.cuda.synchronize()
+    kms, walls, res = [], [], None
+    for step in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, res = ctx.rasl_solve_batch(descs, prm, [a.data_ptr() for a in As], [e.data_ptr() for e in Es])
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        kms.append(ctx.last_kernel_ms())
+        log(f"step {step}: kernel {kms[-1]:.1f} ms, wall {1000 * walls[-1]:.1f} ms, status {rc}")
+    kernel_ms = float(np.mean(kms))
+    lat = np.array([r["solve_ms"] for r in res])
+    # alignment: corner spread of G_k^-1 tau_k around its mean, per set
+    spreads = []
+    for r, out in zip(sets, res):
+        Ms = [np.linalg.inv(r.G_px[k]) @ out["tau"][k] for k in range(r.count)]
+        M0 = np.mean(Ms, axis=0)
+        a, b = (r.n - 1) / 2.0, (r.m - 1) / 2.0
+        cn = np.array([[-a, -b, 1], [a, -b, 1], [a, b, 1], [-a, b, 1]]).T
+        ref = M0 @ cn
+        ref = ref[:2] / ref[2]
+        spreads.append(max(float(np.max(np.linalg.norm((M @ cn)[:2] / (M @ cn)[2] - ref, axis=0))) for M in Ms))
+    nr, nc = RASL_SHAPE["m"] * RASL_SHAPE["n"], RASL_SHAPE["count"]
+    flops = 0.0
+    for out in res:
+        c = out["counters"]
+        flops += (2.0 * nr * c["jacobi_pairs"] + 6.0 * nr * c["jacobi_rotations"] + 4.0 * nc * nr * c["recon_rows"]
+                  + (20.0 + 8.0 * sets[0].model) * nc * nr * c["inner_iters"])
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    roofline = {"kernel": "k_rasl (whole RASL solves, one workgroup per set)", "bound": "alu",
+                "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+                "traffic": (profiled_traffic("k_rasl_rasl256x32x16x24.md", ("tilt_kernels.hip", "tilt_rasl.inc"))
+                            if nsets == 256 and args.rasl_max_outer == 10 else None),
+                "kernel_ms": round(kernel_ms, 2), "flops_per_launch": flops}
+    cpu = None
+    if not args.no_cpu:
+        import multiprocessing as mp
+
+        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            os.environ[k] = "1"
+        sample = list(range(min(args.cpu_sample, nsets)))
+        log(f"cpu baseline: FP64 oracle on {len(sample)} sets, one process and one BLAS thread each")
+        prm_kw = dict(lam=lam, eps1=prm.eps1, eps2=prm.eps2, eps_outer=prm.eps_outer, mu0=prm.mu0, rho0=prm.rho0,
+                      mu_max=prm.mu_max, max_inner=prm.max_inner, max_outer=prm.max_outer)
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(len(sample)) as pool:
+            outs = pool.map(_rasl_oracle_worker, [(i, prm_kw) for i in sample])
+        wall = time.perf_counter() - t0
+        cpu_s = sum(o[0] for o in outs)
+        tau_err = max(O.tau_rel_err(res[i]["tau"][k], outs[j][1][k], RASL_SHAPE["m"], RASL_SHAPE["n"])
+                      for j, i in enumerate(sample) for k in range(RASL_SHAPE["count"]))
+        cpu = {"value": round(len(sample) / wall, 4), "unit": "sets/s", "cores": len(sample), "kind": "oracle",
+               "sample": f"{len(sample)} of the {nsets} sets (indices {sample}), FP64 NumPy oracle with the same "
+                         f"parameters, one process per set; {cpu_s:.1f} CPU-s in {wall:.1f} s wall",
+               "max_tau_rel_err_vs_gpu": tau_err}
+    out = {
+        "metric": "RASL image sets aligned/s",
+        "value": round(nsets / (kernel_ms * 1e-3), 3),
+        "unit": "sets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(kernel_ms, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (one low-rank texture per set seen through planted per-image transforms, 5 % corruption)",
+        "config": {"workload": f"rasl-{nsets}x{RASL_SHAPE['count']}x{RASL_SHAPE['m']}x{RASL_SHAPE['n']}-affine",
+                   "sets": nsets, **RASL_SHAPE, "model": "affine", "max_outer": prm.max_outer,
+                   "lambda": lam, "images_per_s": round(nsets * RASL_SHAPE["count"] / (kernel_ms * 1e-3), 1)},
+        "latency_ms": {"set_solve_p50": round(float(np.percentile(lat, 50)), 2),
+                       "set_solve_p99": round(float(np.percentile(lat, 99)), 2)},
+        "alignment_px": {"p50": round(float(np.median(spreads)), 4), "max": round(float(np.max(spreads)), 4)},
+        "work": {"inner_mean": float(np.mean([r["inner_iters_total"] for r in res])),
+                 "status_ok": int(sum(1 for r in res if r["status"] >= 0))},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -328,6 +328,7 @@ typedef struct {
     int svt_rank;            /* singular values of the last SVT argument above 1/mu        */
     int status;              /* TILT_OK, TILT_WARN_MAXITER or an error                     */
     double solve_ms;         /* device wall-clock time of this solve                       */
+    tilt_counters counters;  /* work counters of this solve                                */
 } tilt_rasl_result;
 
 /* Solve `count` independent RASL problems in one fused kernel (one

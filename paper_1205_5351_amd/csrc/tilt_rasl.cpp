@@ -186,6 +186,12 @@ extern "C" int tilt_rasl_solve_batch(tilt_ctx* ctx, const tilt_rasl_problem* pro
         r.svt_rank = s.svt_rank;
         r.status = s.status < 0 ? s.status : (s.warn ? TILT_WARN_MAXITER : TILT_OK);
         r.solve_ms = (double)(s.t_end - s.t_begin) / ctx->wall_rate_khz;
+        r.counters.inner_iters = s.inner_total;
+        r.counters.svt_calls = s.svt_calls;
+        r.counters.jacobi_sweeps = s.sweeps;
+        r.counters.jacobi_pairs = s.pairs;
+        r.counters.jacobi_rotations = s.rotations;
+        r.counters.recon_rows = s.recon_rows;
         worst = worse(worst, r.status);
     }
     return worst;

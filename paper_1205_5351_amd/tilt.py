@@ -149,6 +149,7 @@ class RaslResult(C.Structure):
         ("svt_rank", C.c_int),
         ("status", C.c_int),
         ("solve_ms", C.c_double),
+        ("counters", Counters),
     ]
 
 
@@ -504,10 +505,14 @@ class Context:
         for i, st in enumerate(sets):
             N = int(st["count"])
             r = rarr[i]
+            c = r.counters
             out.append(dict(tau=np.array([r.tau[k] for k in range(9 * N)]).reshape(N, 3, 3),
                             objective=r.objective, outer_iters=r.outer_iters,
                             inner_iters_total=r.inner_iters_total, svt_rank=r.svt_rank, status=r.status,
-                            solve_ms=r.solve_ms))
+                            solve_ms=r.solve_ms,
+                            counters=dict(inner_iters=c.inner_iters, svt_calls=c.svt_calls,
+                                          jacobi_sweeps=c.jacobi_sweeps, jacobi_pairs=c.jacobi_pairs,
+                                          jacobi_rotations=c.jacobi_rotations, recon_rows=c.recon_rows)))
         del keep
         return rc, out
 
