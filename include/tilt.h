@@ -266,7 +266,10 @@ int tilt_warp_jacobian(tilt_ctx* ctx, const tilt_problem* probs, const double* t
  * with mu_0 from params (<= 0: 1.25/||I||_2).  A, E (count x m x n,
  * DEVICE) may be NULL.  Fills inner_iters_total, objective, mu, cond1,
  * cond2, svt_rank, status, solve_ms and the counters of results[i]; tau is
- * zero.  max(m, n) <= 512; pyramid_levels must be 1. */
+ * zero.  max(m, n) <= 2048, min(m, n) <= 1024; pyramid_levels must be 1.
+ * When the SVT does not fit LDS and count <= (compute units) / 8, each
+ * Jacobi round of a problem runs on many workgroups (one per super-block
+ * pair, one launch per round) instead of one workgroup per problem. */
 int tilt_inner_batch(tilt_ctx* ctx, const float* I, const float* J, int count, int m, int n, int p,
                      const tilt_params* prm, float* A, float* E, tilt_result* results, void* hip_stream);
 
@@ -312,7 +315,7 @@ typedef struct {
     int height, width;       /* size of every image (>= 2 x 2)                             */
     long long row_stride;    /* floats from one image row to the next (>= width)           */
     int count;               /* images = columns of the data matrix, 2 <= count < m n      */
-    int m, n;                /* common rectified window, m n <= 512                        */
+    int m, n;                /* common rectified window, m n <= 2048                       */
     int model;               /* TILT_AFFINE or TILT_PROJECTIVE                             */
     const double* tau0;      /* HOST: count row-major 3x3 homographies, centred window
                                 pixel (u, v, 1) -> image pixel (x, y, 1)                    */
@@ -335,7 +338,7 @@ typedef struct {
  * workgroup per problem, work queue).  Inputs and A/E are device memory;
  * tau0 and tau are host memory.  `prm->svt_mode` must be 0 and
  * `prm->pyramid_levels` 1.  TILT_ERR_ARG for invalid shapes or transforms,
- * TILT_ERR_TOO_LARGE when m n exceeds 512 or the count x m n matrix does not
+ * TILT_ERR_TOO_LARGE when m n exceeds 2048 or the count x m n matrix does not
  * fit the SVT; per-problem failures are in res[k].status and the call
  * returns the worst status.  The stream is synchronised before returning. */
 int tilt_rasl_solve_batch(tilt_ctx* ctx, const tilt_rasl_problem* probs, int count, const tilt_params* prm,

@@ -54,9 +54,13 @@ int pick_svt_cfg(int nc, int nr4) {
     const int nc4 = (nc + 3) & ~3;
     int best = -1;
     double best_cost = 1e300;
-    const int lpps[3] = {4, 8, 16};
+    // Rows longer than 512 floats need groups of 32 or 64 lanes (the device
+    // instantiates those layouts for exactly these chunk counts).
+    const bool long_rows = nr4 > 16 * SVT_MAX_NCH;
+    const int lpps[5] = {4, 8, 16, 32, 64};
     for (int bs = 1; bs <= 2; ++bs) {
-        for (int li = 0; li < 3; ++li) {
+        for (int li = long_rows ? 3 : 0; li < (long_rows ? 5 : 3); ++li) {
+            if (long_rows && lpps[li] == 32 && bs == 2) continue;
             const int lpp = lpps[li];
             const int nch = (nr4 + lpp - 1) / lpp;
             if (nch > (bs == 1 ? SVT_MAX_NCH : 4)) continue;
@@ -179,7 +183,7 @@ int shape_config(int m, int n, ShapeCfg* out) {
                     c.ws_floats = (size_t)NPLANES * c.nc * c.ldg;
                     // warm start: the rotation rows share the layout of the
                     // Jacobi rows and need their own nc4 x ld LDS area
-                    if (svt_nch(c.cfg) <= 4) {
+                    if (svt_nch(c.cfg) <= 4 && svt_lpp(c.cfg) <= 16) {
                         for (int wtb = 32; wtb >= 16; wtb -= 16) {
                             const size_t front = std::max((size_t)nc4 * c.ld, (size_t)wtb * c.ld + (size_t)nc4 * wtb);
                             const size_t wl = sizeof(float) * ((size_t)nc4 * c.ld + front + 3 * (size_t)nc4);
@@ -201,7 +205,7 @@ int shape_config(int m, int n, ShapeCfg* out) {
         const int sb = (((nc4 + nsb - 1) / nsb) + 3) & ~3;
         if (2 * sb > SVT_MAX_ROWS) continue;
         const int ncp = nsb * sb;
-        if (ncp > SVT_MAX_TILED_ROWS) break;
+        if (ncp > SVT_MAX_TILED_ROWS) continue;  // rounding sb up to 4 rows: ncp is not monotonic in nsb
         const int cfg = pick_svt_cfg(2 * sb, c.ldg / 4);
         if (cfg < 0) return TILT_ERR_TOO_LARGE;
         const int ld = pick_ld(cfg);
@@ -656,6 +660,194 @@ int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const 
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Wide inner-loop path: a few large problems (tiled SVT shapes) run their
+// Jacobi rounds on many workgroups, one launch per round, host-driven.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct WideTiling {
+    int sb = 0, nsb = 0, ncp = 0, cfg = -1, ld = 0, tb = 0;
+    size_t lds_round = 0, lds_finish = 0;
+};
+
+// Largest super-blocks whose staged pair is swept in one pass of the lane
+// groups per round (block pairs <= groups) and whose LDS needs fit; the
+// rounds then take about the same time whatever the size, so larger blocks
+// mean fewer launches and fewer staged rows.
+bool wide_tiling(int nc, int ldg, WideTiling* out) {
+    const int nc4 = (nc + 3) & ~3;
+    const size_t budget = (size_t)LDS_LIMIT - kStaticLdsMargin;
+    for (int sb = std::min(128, ((nc4 / 2) + 3) & ~3); sb >= 4; sb -= 4) {
+        const int cfg = pick_svt_cfg(2 * sb, ldg / 4);
+        if (cfg < 0) continue;
+        if (sb / svt_bs(cfg) > NT / svt_lpp(cfg)) continue;
+        int nsb = (nc4 + sb - 1) / sb;
+        nsb += nsb & 1;
+        if (nsb < 2 || nsb * sb > SVT_MAX_TILED_ROWS) continue;
+        const int ld = pick_ld(cfg);
+        const size_t lr = sizeof(float) * 2 * (size_t)sb * ld;
+        if (lr > budget) continue;
+        for (int tb = 32; tb >= 16; tb -= 16) {
+            const size_t lf = lds_bytes_tiled(sb, nsb * sb, ld, ldg, tb);
+            if (lf <= budget) {
+                out->sb = sb;
+                out->nsb = nsb;
+                out->ncp = nsb * sb;
+                out->cfg = cfg;
+                out->ld = ld;
+                out->tb = tb;
+                out->lds_round = lr;
+                out->lds_finish = lf;
+                return true;
+            }
+        }
+    }
+    return false;
+}
+
+int inner_wide(tilt_ctx* ctx, const float* I, const float* J, int count, int m, int n, int p, const tilt_params* prm,
+               float* A, float* E, tilt_result* results, hipStream_t stream, const ShapeCfg& sc,
+               const WideTiling& wt) {
+    const size_t per = (((size_t)NPLANES * sc.nc * sc.ldg + (size_t)wt.ncp * sc.ldg) + 63) & ~(size_t)63;
+    if (per * count * sizeof(float) > ctx->budget) return TILT_ERR_NOMEM;
+    if (ctx->ws.reserve(per * count * sizeof(float)) != hipSuccess ||
+        ctx->descs.reserve(sizeof(PatchDesc) * count) != hipSuccess ||
+        ctx->states.reserve(sizeof(PatchState) * count) != hipSuccess ||
+        ctx->scratch.reserve(sizeof(int) * 4 * (size_t)count) != hipSuccess)
+        return TILT_ERR_NOMEM;
+    int* d_active = reinterpret_cast<int*>(ctx->scratch.p);
+    int* d_cur = d_active + count;
+    int* d_flags = d_cur + count;
+    int* d_sweeps = d_flags + count;
+    const size_t mn = (size_t)m * n;
+    std::vector<PatchDesc> descs(count);
+    std::vector<PatchState> hs(count);
+    for (int i = 0; i < count; ++i) {
+        PatchDesc& d = descs[i];
+        std::memset(&d, 0, sizeof(d));
+        d.m = m;
+        d.n = n;
+        d.model = p + 3;
+        d.pp = p;
+        d.nc = sc.nc;
+        d.nr = sc.nr;
+        d.ldg = sc.ldg;
+        d.colmajor = sc.colmajor;
+        d.ld = wt.ld;
+        d.svt_cfg = wt.cfg;
+        d.tb = wt.tb;
+        d.sb = wt.sb;
+        d.nsb = wt.nsb;
+        d.ncp = wt.ncp;
+        d.s = 1.0;
+        d.lam = prm->lambda > 0 ? prm->lambda : 1.0 / std::sqrt((double)std::max(m, n));
+        d.ws = reinterpret_cast<float*>(ctx->ws.p) + per * i;
+        d.A_out = A ? A + mn * i : nullptr;
+        d.E_out = E ? E + mn * i : nullptr;
+        std::memset(&hs[i], 0, sizeof(PatchState));
+        hs[i].geo[2] = 1.0;
+    }
+    const PatchDesc* dd = reinterpret_cast<const PatchDesc*>(ctx->descs.p);
+    PatchState* ds = reinterpret_cast<PatchState*>(ctx->states.p);
+    HIP_TRY(hipMemcpyAsync(ctx->descs.p, descs.data(), sizeof(PatchDesc) * count, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(ctx->states.p, hs.data(), sizeof(PatchState) * count, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemsetAsync(ctx->scratch.p, 0, sizeof(int) * 4 * (size_t)count, stream));
+    const SolverParams sp = to_solver(prm);
+    SolverParams sp_setup = sp;
+    if (!(sp_setup.mu0 > 0.0)) sp_setup.mu0 = 1.0;  // set below from the wide SVD of I
+    HIP_TRY(hipEventRecord(ctx->ev0, stream));
+    HIP_TRY(launch_wide_setup(dd, ds, sp_setup, I, J, count, 0, stream));
+    auto read_states = [&]() -> int {
+        HIP_TRY(hipMemcpyAsync(hs.data(), ctx->states.p, sizeof(PatchState) * count, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        return TILT_OK;
+    };
+    int st = read_states();
+    if (st != TILT_OK) return st;
+    std::vector<int> active;
+    for (int i = 0; i < count; ++i)
+        if (hs[i].status >= 0) active.push_back(i);
+    std::vector<int> sweeps(count, 0), flags(count, 0);
+    bool configured = false;
+    // Stage, then sweep until a sweep rotates nothing (per problem), then
+    // upload the sweep counts.
+    auto wide_svd = [&](const std::vector<int>& act, int form_m) -> int {
+        HIP_TRY(hipMemcpyAsync(d_active, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, stream));
+        HIP_TRY(launch_wide_stage(dd, ds, d_active, (int)act.size(), form_m, d_flags, stream));
+        for (int i : act) sweeps[i] = 0;
+        std::vector<int> cur = act;
+        for (int sw = 0; sw < prm->max_sweeps && !cur.empty(); ++sw) {
+            HIP_TRY(hipMemcpyAsync(d_cur, cur.data(), sizeof(int) * cur.size(), hipMemcpyHostToDevice, stream));
+            for (int r = 0; r < wt.nsb - 1; ++r) {
+                HIP_TRY(launch_wide_round(dd, ds, d_cur, (int)cur.size(), wt.nsb / 2, r, sp.jacobi_tol, d_flags,
+                                          wt.lds_round, !configured, stream));
+                configured = true;
+            }
+            HIP_TRY(hipMemcpyAsync(flags.data(), d_flags, sizeof(int) * count, hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            HIP_TRY(hipMemsetAsync(d_flags, 0, sizeof(int) * count, stream));
+            std::vector<int> next;
+            for (int i : cur) {
+                sweeps[i] += 1;
+                if (flags[i]) next.push_back(i);
+            }
+            cur.swap(next);
+        }
+        HIP_TRY(hipMemcpyAsync(d_sweeps, sweeps.data(), sizeof(int) * count, hipMemcpyHostToDevice, stream));
+        return TILT_OK;
+    };
+    if (!active.empty() && !(sp.mu0 > 0.0)) {
+        st = wide_svd(active, 0);
+        if (st != TILT_OK) return st;
+        HIP_TRY(launch_wide_finish(dd, ds, d_active, (int)active.size(), sp, d_sweeps, 1, wt.lds_finish, stream));
+        st = read_states();
+        if (st != TILT_OK) return st;
+        std::vector<int> ok;
+        for (int i : active)
+            if (hs[i].status >= 0) ok.push_back(i);
+        active.swap(ok);
+    }
+    // Every pass raises each active problem's inner count by one, and
+    // dev_update stops a problem at max_inner, so the loop ends.
+    while (!active.empty()) {
+        st = wide_svd(active, 1);
+        if (st != TILT_OK) return st;
+        HIP_TRY(launch_wide_finish(dd, ds, d_active, (int)active.size(), sp, d_sweeps, 0, wt.lds_finish, stream));
+        HIP_TRY(launch_wide_update(dd, ds, d_active, (int)active.size(), sp, stream));
+        st = read_states();
+        if (st != TILT_OK) return st;
+        std::vector<int> next;
+        for (int i : active)
+            if (!hs[i].done_inner && hs[i].status >= 0) next.push_back(i);
+        active.swap(next);
+    }
+    HIP_TRY(launch_wide_end(dd, ds, count, stream));
+    HIP_TRY(hipEventRecord(ctx->ev1, stream));
+    st = read_states();
+    if (st != TILT_OK) return st;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->last_kernel_ms = ms;
+    int worst = TILT_OK;
+    long long t0 = hs[0].t_begin;
+    for (int i = 1; i < count; ++i) t0 = std::min(t0, hs[i].t_begin);
+    for (int i = 0; i < count; ++i) {
+        tilt_result& r = results[i];
+        float* hA = r.A;
+        float* hE = r.E;
+        fill_result(descs[i], hs[i], &r, ctx->wall_rate_khz, t0);
+        for (int k = 0; k < 9; ++k) r.tau[k] = 0.0;
+        r.A = hA;
+        r.E = hE;
+        worst = worse(worst, r.status);
+    }
+    return worst;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C interface
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -1031,6 +1223,11 @@ int tilt_inner_batch(tilt_ctx* ctx, const float* I, const float* J, int count, i
     const size_t lds = warm ? sc.warm_lds : sc.lds;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    // Few problems whose SVT does not fit LDS: spread each Jacobi round over
+    // workgroups instead of one workgroup per problem.
+    WideTiling wt;
+    if (sc.sb > 0 && !warm && count * 8 <= ctx->num_cus && wide_tiling(sc.nc, sc.ldg, &wt))
+        return inner_wide(ctx, I, J, count, m, n, p, prm, A, E, results, stream, sc, wt);
     const size_t per = (sc.ws_floats + 63) & ~(size_t)63;
     if (per * count * sizeof(float) > ctx->budget) return TILT_ERR_NOMEM;
     if (ctx->ws.reserve(per * count * sizeof(float)) != hipSuccess ||

@@ -21,16 +21,16 @@ constexpr int MAX_LEVELS = 4;    // pyramid levels per request
 // (nc x nc in the first nc columns); it persists across inner iterations.
 enum Plane { PL_I = 0, PL_A = 1, PL_E = 2, PL_Y = 3, PL_R = 4, PL_M = 5, PL_Q = 6, PL_V = 6 + MAXP };
 
-// Jacobi variants: cfg = (BS - 1) * 64 + (log2(LPP) - 2) * 16 + (NCH - 1)
-// with BS rows per block (1 or 2), LPP lanes per block pair (4, 8 or 16)
-// and NCH float4 chunks of each row held per lane (1..8 for BS = 1, 1..4
-// for BS = 2: at most 64 floats of rows per lane).
+// Jacobi variants: BS rows per block (1 or 2), LPP lanes per block pair
+// (4, 8, 16; 32 and 64 for rows longer than 512) and NCH float4 chunks of
+// each row held per lane (1..8 for BS = 1, 1..4 for BS = 2: at most 64
+// floats of rows per lane); encoded by svt_make_cfg.
 constexpr int SVT_MAX_NCH = 8;
 constexpr int SVT_MAX_ROWS = 256;  // rows of the Jacobi matrix held in LDS at once
 // Tiled SVT (matrices larger than LDS): the rows live in a device plane and
 // are processed in pairs of super-blocks of sb rows staged through LDS.
-constexpr int SVT_MAX_TILED_ROWS = 768;  // rows of the working plane (min(m, n) rounded up to whole super-blocks)
-constexpr int SVT_MAX_COLS = 512;        // max(m, n): 16 lanes x 8 chunks x 4 floats
+constexpr int SVT_MAX_TILED_ROWS = 1024;  // rows of the working plane (min(m, n) rounded up to whole super-blocks)
+constexpr int SVT_MAX_COLS = 2048;       // max(m, n): 64 lanes x 8 chunks x 4 floats
 
 struct PatchDesc {
     const float* image;
@@ -168,12 +168,13 @@ struct SvtJob {
 };
 
 // LDS layout helpers (host and device).
-__host__ __device__ inline int svt_bs(int cfg) { return (cfg >> 6) + 1; }
-__host__ __device__ inline int svt_lpp(int cfg) { return 4 << ((cfg >> 4) & 3); }
-__host__ __device__ inline int svt_nch(int cfg) { return (cfg & 15) + 1; }
-__host__ __device__ inline int svt_make_cfg(int bs, int lpp, int nch) {
-    return (bs - 1) * 64 + (lpp == 4 ? 0 : (lpp == 8 ? 1 : 2)) * 16 + (nch - 1);
+// cfg = (BS - 1) * 128 + log2(LPP / 4) * 16 + (NCH - 1)
+__host__ __device__ constexpr int svt_make_cfg(int bs, int lpp, int nch) {
+    return (bs - 1) * 128 + (lpp == 4 ? 0 : lpp == 8 ? 1 : lpp == 16 ? 2 : lpp == 32 ? 3 : 4) * 16 + (nch - 1);
 }
+__host__ __device__ inline int svt_bs(int cfg) { return (cfg >> 7) + 1; }
+__host__ __device__ inline int svt_lpp(int cfg) { return 4 << ((cfg >> 4) & 7); }
+__host__ __device__ inline int svt_nch(int cfg) { return (cfg & 15) + 1; }
 
 // Serving ring: request slots and the control word live in pinned
 // (coherent) host memory; the host publishes requests by raising `tail`,
@@ -198,6 +199,17 @@ struct ServeCtl {
 // Kernel launchers (tilt_kernels.hip).
 hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, int levels,
                         const int* order, int* queue, int grid, size_t lds, hipStream_t s);
+hipError_t launch_wide_setup(const PatchDesc* d, PatchState* st, const SolverParams& prm, const float* I,
+                             const float* J, int count, size_t lds, hipStream_t s);
+hipError_t launch_wide_stage(const PatchDesc* d, PatchState* st, const int* active, int nactive, int form_m,
+                             int* flags, hipStream_t s);
+hipError_t launch_wide_round(const PatchDesc* d, PatchState* st, const int* active, int nactive, int pairs, int r,
+                             float tol, int* flags, size_t lds, bool configure, hipStream_t s);
+hipError_t launch_wide_finish(const PatchDesc* d, PatchState* st, const int* active, int nactive,
+                              const SolverParams& prm, const int* sweeps, int mode, size_t lds, hipStream_t s);
+hipError_t launch_wide_update(const PatchDesc* d, PatchState* st, const int* active, int nactive,
+                              const SolverParams& prm, hipStream_t s);
+hipError_t launch_wide_end(const PatchDesc* d, PatchState* st, int count, hipStream_t s);
 hipError_t launch_rasl(const RaslDesc* d, PatchState* st, const SolverParams& prm, int count, int* queue, int grid,
                        size_t lds, hipStream_t s);
 hipError_t launch_serve(ServeCtl* ctl, ServeSlot* slots, PatchDesc* ddesc, PatchState* dstates,

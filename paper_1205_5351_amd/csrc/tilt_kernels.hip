@@ -129,14 +129,17 @@ __device__ inline float dpp_mirror(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
 }
 
-// Sum over the LPP (4, 8 or 16) lanes of a group; all lanes get identical
-// bits (each step adds two equal partial sums in either order).
+// Sum over the LPP (4, 8, 16, 32 or 64) lanes of a group; all lanes get
+// identical bits (each step adds two equal partial sums in either order).
+// Groups wider than a 16-lane row exchange halves through lane shuffles.
 template <int LPP>
 __device__ inline float group_sum(float v) {
     v += dpp_xor1(v);
     v += dpp_xor2(v);
     if (LPP >= 8) v += dpp_half_mirror(v);
     if (LPP >= 16) v += dpp_mirror(v);
+    if (LPP >= 32) v += __shfl_xor(v, 16, 64);
+    if (LPP >= 64) v += __shfl_xor(v, 32, 64);
     return v;
 }
 
@@ -494,9 +497,9 @@ __device__ void jacobi_svd_rows(float* B, float* Rm, int nc, int ld, float tol, 
     row_norms<LPP, NCH>(B, nc, ld, s2);
 }
 
-// cfg = (BS - 1) * 64 + (log2(LPP) - 2) * 16 + (NCH - 1)
+// Layout codes from svt_make_cfg(BS, LPP, NCH).
 #define TILT_SVT_CASE(S, L, C)                                                            \
-    case ((S - 1) * 64 + (L == 4 ? 0 : (L == 8 ? 1 : 2)) * 16 + (C - 1)):                  \
+    case svt_make_cfg(S, L, C):                  \
         jacobi_svd_rows<S, L, C, false>(B, nullptr, nc, ld, tol, max_sweeps, js, s2);       \
         break;
 #define TILT_SVT_CASES8(S, L)                                                              \
@@ -510,6 +513,10 @@ __device__ void jacobi_dispatch(int cfg, float* B, int nc, int ld, float tol, in
     switch (cfg) {
         TILT_SVT_CASES8(1, 4) TILT_SVT_CASES8(1, 8) TILT_SVT_CASES8(1, 16)
         TILT_SVT_CASES4(2, 4) TILT_SVT_CASES4(2, 8) TILT_SVT_CASES4(2, 16)
+        // rows longer than 512: the layouts the cost model may choose there
+        TILT_SVT_CASE(1, 32, 5) TILT_SVT_CASE(1, 32, 6) TILT_SVT_CASE(1, 32, 7) TILT_SVT_CASE(1, 32, 8)
+        TILT_SVT_CASE(1, 64, 3) TILT_SVT_CASE(1, 64, 4) TILT_SVT_CASE(1, 64, 5) TILT_SVT_CASE(1, 64, 6)
+        TILT_SVT_CASE(1, 64, 7) TILT_SVT_CASE(1, 64, 8) TILT_SVT_CASE(2, 64, 3) TILT_SVT_CASE(2, 64, 4)
         default:
             break;
     }
@@ -518,7 +525,7 @@ __device__ void jacobi_dispatch(int cfg, float* B, int nc, int ld, float tol, in
 // Warm variants (rotation rows Rm in LDS, same layout as B): chunks per
 // lane up to 4.
 #define TILT_WARM_CASE(S, L, C)                                                           \
-    case ((S - 1) * 64 + (L == 4 ? 0 : (L == 8 ? 1 : 2)) * 16 + (C - 1)):                  \
+    case svt_make_cfg(S, L, C):                  \
         jacobi_svd_rows<S, L, C, true>(B, Rm, nc, ld, tol, max_sweeps, js, s2);             \
         break;
 #define TILT_WARM_CASES4(S, L) \
@@ -541,7 +548,7 @@ __device__ void jacobi_dispatch_warm(int cfg, float* B, float* Rm, int nc, int l
 
 // One sweep over all pairs of the nrows rows of B (LDS); 1 if any rotated.
 #define TILT_SWEEP_CASE(S, L, C)                                                          \
-    case ((S - 1) * 64 + (L == 4 ? 0 : (L == 8 ? 1 : 2)) * 16 + (C - 1)):                  \
+    case svt_make_cfg(S, L, C):                  \
         return jacobi_rows<S, L, C, false>(B, nullptr, nrows, ld, tol, 1, js);
 #define TILT_SWEEP_CASES8(S, L)                                                                    \
     TILT_SWEEP_CASE(S, L, 1) TILT_SWEEP_CASE(S, L, 2) TILT_SWEEP_CASE(S, L, 3) TILT_SWEEP_CASE(S, L, 4) \
@@ -553,6 +560,9 @@ __device__ int jacobi_sweep_dispatch(int cfg, float* B, int nrows, int ld, float
     switch (cfg) {
         TILT_SWEEP_CASES8(1, 4) TILT_SWEEP_CASES8(1, 8) TILT_SWEEP_CASES8(1, 16)
         TILT_SWEEP_CASES4(2, 4) TILT_SWEEP_CASES4(2, 8) TILT_SWEEP_CASES4(2, 16)
+        TILT_SWEEP_CASE(1, 32, 5) TILT_SWEEP_CASE(1, 32, 6) TILT_SWEEP_CASE(1, 32, 7) TILT_SWEEP_CASE(1, 32, 8)
+        TILT_SWEEP_CASE(1, 64, 3) TILT_SWEEP_CASE(1, 64, 4) TILT_SWEEP_CASE(1, 64, 5) TILT_SWEEP_CASE(1, 64, 6)
+        TILT_SWEEP_CASE(1, 64, 7) TILT_SWEEP_CASE(1, 64, 8) TILT_SWEEP_CASE(2, 64, 3) TILT_SWEEP_CASE(2, 64, 4)
         default:
             break;
     }
@@ -1560,25 +1570,18 @@ __device__ void save_rotation(const float* Rl, int ld, int nc, float* V, int ldg
 // A-update: M = A - R - Y/mu, A <- S_{1/mu}(M)
 // ---------------------------------------------------------------------------
 
-__device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& prm, float* lds) {
-    const int tid = threadIdx.x;
+// M_k = A_k - J~perp(A_k + E_k - I) - Y_k/mu_k (R = J~perp(A_k + E_k - I)),
+// into the M plane and, when Bl is given, into the LDS Jacobi matrix.
+__device__ void svt_form_m(const PatchDesc& d, const PatchState* st, float* Bl) {
     const int nc = d.nc, ldg = d.ldg, ld = d.ld;
     const int nr4 = ldg >> 2;
     const size_t np = (size_t)nc * ldg;
-    float* A = d.ws + PL_A * np;
+    const float* A = d.ws + PL_A * np;
     const float* R = d.ws + PL_R * np;
     const float* Y = d.ws + PL_Y * np;
     float* M = d.ws + PL_M * np;
-    const double mu = st->mu;
-    const float inv_mu = (float)(1.0 / mu);
-    const bool tiled = d.sb > 0;
-    const bool warm = d.warm != 0;
-    float* Bg = d.ws + NPLANES * np;
-    float* Rl = nullptr;
-    const SvtLds L = warm ? carve_lds_warm(lds, nc, ld, d.tb, &Rl) : carve_for(d, lds);
-
-    // M_k = A_k - J~perp(A_k + E_k - I) - Y_k/mu_k, with R = J~perp(A_k + E_k - I).
-    for (int idx = tid; idx < nc * nr4; idx += NT) {
+    const float inv_mu = (float)(1.0 / st->mu);
+    for (int idx = threadIdx.x; idx < nc * nr4; idx += NT) {
         const int row = idx / nr4, c = idx - row * nr4;
         const size_t o = (size_t)row * ldg + 4 * c;
         const float4 a = *reinterpret_cast<const float4*>(A + o);
@@ -1590,8 +1593,55 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
         mm.z = fmaf(-y.z, inv_mu, a.z - r.z);
         mm.w = fmaf(-y.w, inv_mu, a.w - r.w);
         *reinterpret_cast<float4*>(M + o) = mm;
-        if (!tiled && !warm) *reinterpret_cast<float4*>(L.B + row * ld + 4 * c) = mm;
+        if (Bl) *reinterpret_cast<float4*>(Bl + row * ld + 4 * c) = mm;
     }
+}
+
+// Shrinkage and reconstruction from the orthogonalised rows (LDS rows L.B,
+// or the working plane when tiled) whose squared norms are in L.s2; A and
+// the SVT statistics of the state are updated.
+__device__ void svt_finish(const PatchDesc& d, PatchState* st, const SvtLds& L, const JacobiStats& js) {
+    const int tid = threadIdx.x;
+    const int nc = d.nc, ldg = d.ldg, ld = d.ld;
+    const int nr4 = ldg >> 2;
+    const size_t np = (size_t)nc * ldg;
+    float* A = d.ws + PL_A * np;
+    const float* M = d.ws + PL_M * np;
+    const float* Bg = d.ws + NPLANES * np;
+    const double mu = st->mu;
+    const float eps = (float)(1.0 / mu);
+    int k;
+    double nuc;
+    shrink_weights(L.s2, nc, eps, L.w, L.act, &k, &nuc);
+    float dA[1];
+    dA[0] = d.sb > 0 && !d.warm
+                ? reconstruct(Bg, ldg, M, A, nc, nr4, ldg, L.w, L.act, k, d.tb, L.xblk, L.cwt, true)
+                : reconstruct(L.B, ld, M, A, nc, nr4, ldg, L.w, L.act, k, d.tb, L.xblk, L.cwt, true);
+    block_sum_f<1>(dA);
+    if (tid == 0) {
+        st->dA2 = (double)dA[0];
+        st->nuc = nuc;
+        st->svt_rank = k;
+        st->svt_calls += 1;
+        st->sweeps += js.sweeps;
+        st->pairs += js.pairs;
+        st->rotations += js.rotations;
+        st->recon_rows += k;
+    }
+    __syncthreads();
+}
+
+__device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& prm, float* lds) {
+    const int nc = d.nc, ldg = d.ldg, ld = d.ld;
+    const size_t np = (size_t)nc * ldg;
+    float* M = d.ws + PL_M * np;
+    const bool tiled = d.sb > 0;
+    const bool warm = d.warm != 0;
+    float* Bg = d.ws + NPLANES * np;
+    float* Rl = nullptr;
+    const SvtLds L = warm ? carve_lds_warm(lds, nc, ld, d.tb, &Rl) : carve_for(d, lds);
+
+    svt_form_m(d, st, (!tiled && !warm) ? L.B : nullptr);
     JacobiStats js{0, 0, 0};
     if (warm) {
         float* V = d.ws + PL_V * np;
@@ -1632,26 +1682,7 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
         __syncthreads();
         jacobi_dispatch(d.svt_cfg, L.B, nc, ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
     }
-
-    const float eps = (float)(1.0 / mu);
-    int k;
-    double nuc;
-    shrink_weights(L.s2, nc, eps, L.w, L.act, &k, &nuc);
-    float dA[1];
-    dA[0] = tiled ? reconstruct(Bg, ldg, M, A, nc, nr4, ldg, L.w, L.act, k, d.tb, L.xblk, L.cwt, true)
-                  : reconstruct(L.B, ld, M, A, nc, nr4, ldg, L.w, L.act, k, d.tb, L.xblk, L.cwt, true);
-    block_sum_f<1>(dA);
-    if (tid == 0) {
-        st->dA2 = (double)dA[0];
-        st->nuc = nuc;
-        st->svt_rank = k;
-        st->svt_calls += 1;
-        st->sweeps += js.sweeps;
-        st->pairs += js.pairs;
-        st->rotations += js.rotations;
-        st->recon_rows += k;
-    }
-    __syncthreads();
+    svt_finish(d, st, L, js);
 }
 
 // ---------------------------------------------------------------------------
@@ -2221,6 +2252,139 @@ __global__ void __launch_bounds__(NT) k_inner(const PatchDesc* descs, PatchState
     if (threadIdx.x == 0) st->t_end = (long long)wall_clock64();
 }
 
+// ---------------------------------------------------------------------------
+// Wide SVT for a few large problems of the inner-loop entry.  The
+// super-block pairs of one round of the tiled Jacobi touch disjoint rows, so
+// each runs on its own workgroup (one launch per round); the host ends a
+// sweep by reading the per-problem rotation flags.  Every pair of a round
+// sees the same rows in whatever order the workgroups run, so the result is
+// the one the single-workgroup tiled Jacobi gives with the same super-blocks.
+// ---------------------------------------------------------------------------
+
+// Set-up of problem blockIdx.x (as the first part of k_inner).
+__global__ void __launch_bounds__(NT) k_wide_setup(const PatchDesc* descs, PatchState* states, SolverParams prm,
+                                                    const float* Iall, const float* Jall) {
+    float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
+    const int idx = blockIdx.x;
+    PatchState* st = states + idx;
+    const PatchDesc d = desc_at_level(descs + idx, st);
+    const size_t mn = (size_t)d.m * d.n;
+    if (threadIdx.x == 0) st->t_begin = (long long)wall_clock64();
+    dev_setup_given(d, st, prm, lds, Iall + idx * mn, Jall + (size_t)idx * d.pp * mn);
+}
+
+// Stage the Jacobi rows of problem active[blockIdx.x] into its working
+// plane (rows beyond nc zero): M_k, formed first, when form_m; else the
+// normalised image I (whose largest singular value sets mu_0).  Clears the
+// problem's rotation flag.
+__global__ void __launch_bounds__(NT) k_wide_stage(const PatchDesc* descs, PatchState* states, const int* active,
+                                                    int form_m, int* flags) {
+    const int idx = active[blockIdx.x];
+    PatchState* st = states + idx;
+    const PatchDesc d = desc_at_level(descs + idx, st);
+    const size_t np = (size_t)d.nc * d.ldg;
+    if (form_m) {
+        svt_form_m(d, st, nullptr);
+        __syncthreads();
+    }
+    const float* X = d.ws + (form_m ? PL_M : PL_I) * np;
+    float* Bg = d.ws + NPLANES * np;
+    const int nr4 = d.ldg >> 2;
+    for (int e = threadIdx.x; e < d.ncp * nr4; e += NT) {
+        const int row = e / nr4, c = e - row * nr4;
+        float4 v = f4(0.f);
+        if (row < d.nc) v = reinterpret_cast<const float4*>(X + (size_t)row * d.ldg)[c];
+        reinterpret_cast<float4*>(Bg + (size_t)row * d.ldg)[c] = v;
+    }
+    if (threadIdx.x == 0) flags[idx] = 0;
+}
+
+// One super-block pair of round r of the circle ordering over super-blocks:
+// workgroup g takes problem active[g / pairs], pair g % pairs.
+__global__ void __launch_bounds__(NT) k_wide_round(const PatchDesc* descs, PatchState* states, const int* active,
+                                                    int pairs, int r, float tol, int* flags) {
+    float* mini = reinterpret_cast<float*>(tilt_dyn_lds);
+    const int slot = blockIdx.x / pairs, k = blockIdx.x - slot * pairs;
+    const int idx = active[slot];
+    PatchState* st = states + idx;
+    const PatchDesc& d = descs[idx];
+    const int Nb = d.nsb - 1, sb = d.sb;
+    int I, J;
+    if (k == 0) {
+        I = Nb;
+        J = r;
+    } else {
+        I = r + k;
+        if (I >= Nb) I -= Nb;
+        J = r - k;
+        if (J < 0) J += Nb;
+    }
+    float* Bg = d.ws + NPLANES * (size_t)d.nc * d.ldg;
+    load_block(Bg, I * sb, sb, d.ldg, mini, 0, d.ld);
+    load_block(Bg, J * sb, sb, d.ldg, mini, sb, d.ld);
+    clear_lds_padding(mini, 2 * sb, d.ldg, d.ld);
+    __syncthreads();
+    JacobiStats js{0, 0, 0};
+    const int rot = jacobi_sweep_dispatch(d.svt_cfg, mini, 2 * sb, d.ld, tol, js);
+    if (rot) {
+        store_block(Bg, I * sb, sb, d.ldg, mini, 0, d.ld);
+        store_block(Bg, J * sb, sb, d.ldg, mini, sb, d.ld);
+    }
+    if (threadIdx.x == 0) {
+        if (rot) atomicOr(flags + idx, 1);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&st->pairs), (unsigned long long)js.pairs);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&st->rotations), (unsigned long long)js.rotations);
+    }
+}
+
+// After the sweeps of problem active[blockIdx.x]: row norms of the working
+// plane, then (mode 0) shrinkage and reconstruction of A, or (mode 1)
+// mu_0 = 1.25 / sigma_max(I) unless mu_0 is given.
+__global__ void __launch_bounds__(NT) k_wide_finish(const PatchDesc* descs, PatchState* states, const int* active,
+                                                     SolverParams prm, const int* sweeps, int mode) {
+    float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
+    const int idx = active[blockIdx.x];
+    PatchState* st = states + idx;
+    const PatchDesc d = desc_at_level(descs + idx, st);
+    const SvtLds L = carve_for(d, lds);
+    const float* Bg = d.ws + NPLANES * (size_t)d.nc * d.ldg;
+    row_norms_global(Bg, d.nc, d.ldg, L.s2);
+    if (mode == 0) {
+        const JacobiStats js{sweeps[idx], 0, 0};
+        svt_finish(d, st, L, js);
+        return;
+    }
+    if (threadIdx.x == 0) {
+        float mx = 0.f;
+        for (int j = 0; j < d.nc; ++j) mx = fmaxf(mx, L.s2[j]);
+        const double mu0 = prm.mu0 > 0.0 ? prm.mu0 : 1.25 / (double)sqrtf(mx);
+        st->mu = mu0;
+        st->svt_calls += 1;
+        st->sweeps += sweeps[idx];
+        if (!isfinite(mu0)) {
+            st->status = -5;
+            st->done_outer = 1;
+            st->done_inner = 1;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_wide_update(const PatchDesc* descs, PatchState* states, const int* active,
+                                                     SolverParams prm) {
+    const int idx = active[blockIdx.x];
+    PatchState* st = states + idx;
+    const PatchDesc d = desc_at_level(descs + idx, st);
+    dev_update(d, st, prm);
+}
+
+__global__ void __launch_bounds__(NT) k_wide_end(const PatchDesc* descs, PatchState* states) {
+    const int idx = blockIdx.x;
+    PatchState* st = states + idx;
+    const PatchDesc d = desc_at_level(descs + idx, st);
+    dev_finalize(d, st);
+    if (threadIdx.x == 0) st->t_end = (long long)wall_clock64();
+}
+
 __global__ void __launch_bounds__(NT) k_mark_end(PatchState* st) {
     if (threadIdx.x == 0) st->t_end = (long long)wall_clock64();
 }
@@ -2434,6 +2598,49 @@ hipError_t launch_inner(const PatchDesc* d, PatchState* st, const SolverParams& 
     hipError_t e = set_lds((const void*)k_inner, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_inner, dim3(count), dim3(NT), lds, s, d, st, prm, I, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_setup(const PatchDesc* d, PatchState* st, const SolverParams& prm, const float* I,
+                             const float* J, int count, size_t lds, hipStream_t s) {
+    hipError_t e = set_lds((const void*)k_wide_setup, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wide_setup, dim3(count), dim3(NT), lds, s, d, st, prm, I, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_stage(const PatchDesc* d, PatchState* st, const int* active, int nactive, int form_m,
+                             int* flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_wide_stage, dim3(nactive), dim3(NT), 0, s, d, st, active, form_m, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_round(const PatchDesc* d, PatchState* st, const int* active, int nactive, int pairs, int r,
+                             float tol, int* flags, size_t lds, bool configure, hipStream_t s) {
+    if (configure) {
+        hipError_t e = set_lds((const void*)k_wide_round, lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_wide_round, dim3(nactive * pairs), dim3(NT), lds, s, d, st, active, pairs, r, tol, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_finish(const PatchDesc* d, PatchState* st, const int* active, int nactive,
+                              const SolverParams& prm, const int* sweeps, int mode, size_t lds, hipStream_t s) {
+    hipError_t e = set_lds((const void*)k_wide_finish, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wide_finish, dim3(nactive), dim3(NT), lds, s, d, st, active, prm, sweeps, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_update(const PatchDesc* d, PatchState* st, const int* active, int nactive,
+                              const SolverParams& prm, hipStream_t s) {
+    hipLaunchKernelGGL(k_wide_update, dim3(nactive), dim3(NT), 0, s, d, st, active, prm);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_end(const PatchDesc* d, PatchState* st, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_wide_end, dim3(count), dim3(NT), 0, s, d, st);
     return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ SVT_SHAPES = [(8, 8), (17, 33), (33, 17), (50, 50), (64, 64), (100, 100), (101, 
 # Matrices beyond LDS (tiled Jacobi over super-blocks of rows), ragged and
 # maximum sizes, plus a long-row shape that still fits in LDS.
 SVT_SHAPES_LARGE = [(180, 180), (200, 200), (256, 256), (300, 200), (131, 257), (400, 400), (512, 512),
-                    (40, 400)]
+                    (40, 400), (24, 1000), (600, 90)]
 
 
 @pytest.mark.parametrize("m,n", SVT_SHAPES + SVT_SHAPES_LARGE)
@@ -247,15 +247,15 @@ def test_error_statuses(tilt, ctx, device):
     rc, res = solve_on_device(tilt, ctx, [flat, nan], device, tp)
     assert res[0]["status"] == tilt.tilt.TILT_ERR_SINGULAR
     assert res[1]["status"] == tilt.tilt.TILT_ERR_NONFINITE
-    big = ts.Patch(image=np.zeros((700, 700), np.float32), m=600, n=600, model=6,
-                   tau0=np.array([[1, 0, 349.5], [0, 1, 349.5], [0, 0, 1.0]]), lam=0.05, G_px=np.eye(3),
-                   rank=1, corruption=0.0)
+    big = ts.Patch(image=np.zeros((40, 2200), np.float32), m=20, n=2100, model=6,
+                   tau0=np.array([[1, 0, 1099.5], [0, 1, 19.5], [0, 0, 1.0]]), lam=0.05, G_px=np.eye(3),
+                   rank=1, corruption=0.0)                             # rows longer than 2048
     rc, res = solve_on_device(tilt, ctx, [big], device, tp)
     assert res[0]["status"] == tilt.tilt.TILT_ERR_TOO_LARGE
 
 
 @pytest.mark.parametrize("m,n,model", [(9, 9, 6), (12, 60, 8), (61, 13, 8), (7, 100, 6), (200, 236, 6),
-                                       (257, 181, 8), (400, 400, 8)])
+                                       (257, 181, 8), (400, 400, 8), (40, 560, 6)])
 def test_ragged_shapes_fixed_iters(tilt, ctx, device, m, n, model):
     rng = ts.patch_rng(99, m * 1000 + n)
     p = ts.make_patch(rng, m=m, n=n, height=2 * max(m, n) + 8, width=2 * max(m, n) + 8, rank=2, model=model,
@@ -363,6 +363,34 @@ def test_inner_loop_alone_matches_oracle(tilt, ctx, device, m, n, p, fixed):
             # shifts the schedule.  The solution itself is compared above.
             assert abs(r["inner_iters_total"] - ref.iters) <= max(3, 0.1 * ref.iters), (r["inner_iters_total"],
                                                                                         ref.iters)
+
+
+@pytest.mark.parametrize("m,n,p,count,iters", [(16, 900, 3, 3, 10), (64, 700, 3, 2, 6), (300, 300, 5, 1, 6),
+                                                (1000, 1000, 5, 1, 3)])
+def test_inner_loop_long_rows_and_wide_svt_match_oracle(tilt, ctx, device, m, n, p, count, iters):
+    """Rows longer than 512 (lane groups of 32 or 64) held in LDS (16 x 900)
+    and tiled; a few large problems (tiled shapes, count <= CUs / 8) take
+    the wide path, whose Jacobi rounds run on many workgroups."""
+    import torch
+
+    Is, Js = zip(*[ts.inner_problem(k, m, n, p) for k in range(count)])
+    dI = to_device(np.stack(Is), device)
+    dJ = to_device(np.stack(Js), device)
+    dA = torch.zeros_like(dI)
+    dE = torch.zeros_like(dI)
+    tp = tilt.default_params(fixed_iters=1, max_inner=iters)
+    rc, res = ctx.inner_batch(dI.data_ptr(), dJ.data_ptr(), count, m, n, p, tp, dA.data_ptr(), dE.data_ptr())
+    A = dA.cpu().numpy()
+    lam = 1.0 / math.sqrt(max(m, n))
+    for k in range(count):
+        ref = _inner_ref(Is[k], Js[k], oracle_params(O, tp), lam)
+        r = res[k]
+        errA = np.linalg.norm(A[k] - ref.A) / np.linalg.norm(ref.A)
+        obj = O.objective(ref.A, ref.E, lam)
+        print("inner", m, n, k, "A", errA, "obj", abs(r["objective"] - obj) / obj, "ms", r["solve_ms"], flush=True)
+        assert r["status"] >= 0 and r["inner_iters_total"] == iters
+        assert errA <= 1e-4
+        assert abs(r["objective"] - obj) <= 1e-4 * obj
 
 
 # ---------------------------------------------------------------------------

@@ -73,6 +73,20 @@ def test_rasl_fixed_iterations_match_oracle(tilt, ctx, device, model):
     assert e_A <= 1e-4 and e_E <= 1e-4
 
 
+def test_rasl_long_windows_fixed_iterations_match_oracle(tilt, ctx, device):
+    """24 x 32 windows: rows of 768 floats (lane groups of 32 or 64)."""
+    r = ts.rasl_set(10, count=12, m=24, n=32, height=48, width=56)
+    tp = tilt.default_params(fixed_iters=1, max_outer=2, max_inner=6, lambda_=r.lam)
+    rc, res = _run(ctx, device, [r], tp)
+    g = res[0]
+    ref = O.rasl.rasl_solve(r.images, r.tau0, r.m, r.n, r.model, oracle_params(O, tp), lam=r.lam)
+    e_tau = _tau_err(g["tau"], ref.tau_px, r.m, r.n)
+    e_A = np.linalg.norm(g["A"] - ref.A) / np.linalg.norm(ref.A)
+    _print("rasl long", tau=e_tau, A=e_A)
+    assert g["status"] == 0
+    assert e_tau <= 1e-5 and e_A <= 1e-4
+
+
 def test_rasl_tiled_svt_fixed_iterations_match_oracle(tilt, ctx, device):
     """160 windows of 16 x 24: the 160 x 384 matrix exceeds LDS, so the SVT
     runs tiled through the device working plane."""
@@ -144,9 +158,9 @@ def test_rasl_rejects_invalid_problems(tilt, ctx, device):
     tp = tilt.default_params()
     rc, _ = ctx.rasl_solve_batch([dict(descs[0], count=8, m=2, n=4)], tp)       # count >= m n
     assert rc == tilt.tilt.TILT_ERR_ARG
-    big = ts.rasl_set(9, count=4, m=24, n=24, height=40, width=40)
+    big = ts.rasl_set(9, count=4, m=48, n=48, height=60, width=60)
     d2, k2 = _descs([big], device)
-    rc, _ = ctx.rasl_solve_batch(d2, tp)                                        # m n > 512
+    rc, _ = ctx.rasl_solve_batch(d2, tp)                                        # m n > 2048
     assert rc == tilt.tilt.TILT_ERR_TOO_LARGE
     rc, _ = ctx.rasl_solve_batch(descs, tilt.default_params(svt_mode=1))        # warm SVT not offered
     assert rc == tilt.tilt.TILT_ERR_ARG

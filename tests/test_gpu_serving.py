@@ -165,7 +165,7 @@ def test_serving_tickets_errors_and_restart(tilt, device):
         with pytest.raises(tilt.TiltError) as e:
             c.poll(12345)
         assert e.value.code == tilt.tilt.TILT_ERR_NOT_FOUND
-        big = tilt.make_problem(probs[0].image, 480, 640, 640, 600, 600, 6, p.tau0)
+        big = tilt.make_problem(probs[0].image, 480, 640, 640, 20, 2100, 6, p.tau0)   # rows longer than 2048
         with pytest.raises(tilt.TiltError) as e:
             c.submit(big)
         assert e.value.code == tilt.tilt.TILT_ERR_TOO_LARGE
