@@ -574,14 +574,17 @@ def components_main(args):
 # LADMAP column of Table 1 (MATLAB, one Xeon E5540 core): seconds per
 # solve and iterations; context only (other machine, unstated inputs).
 PAPER_TABLE1_LADMAP = {10: (7.49e-6, 20.4), 50: (0.00054, 21.2), 100: (0.00252, 22.2), 300: (0.10501, 21.9),
-                       500: (0.6574, 22.0)}
+                       500: (0.6574, 22.0), 1000: (25.8139, 23.0)}
 
 
 def inner_main(args):
     """Inner loop alone on random I ~ U(0,1) and J ~ N(0,1) (p = 5) at the
-    sizes of Table 1 that fit (up to 500 x 500): batch throughput, mean
+    sizes of Table 1 (10 x 10 to 1000 x 1000): batch throughput, mean
     per-solve latency and iterations, with the FP64 oracle on one problem
-    per size (same inputs) for the objective and iteration count."""
+    per size (same inputs, up to 500 x 500) for the objective and iteration
+    count.  Batches of 64 or more large problems run one workgroup per
+    problem; a single large problem (the latency rows) takes the wide path,
+    whose Jacobi rounds run on many workgroups."""
     import numpy as np
     import torch
 
@@ -594,7 +597,7 @@ def inner_main(args):
     prm = T.default_params(svt_mode=args.svt_mode)
     rows = []
     p = 5
-    for size, count in ((10, 256), (50, 256), (100, 256), (300, 64), (500, 16)):
+    for size, count in ((10, 256), (50, 256), (100, 256), (300, 64), (300, 1), (500, 16), (500, 1), (1000, 1)):
         Is, Js = zip(*[ts.inner_problem(k, size, size, p) for k in range(count)])
         dI = torch.from_numpy(np.stack(Is)).to(dev)
         dJ = torch.from_numpy(np.stack(Js)).to(dev)
@@ -611,24 +614,27 @@ def inner_main(args):
         iters = np.array([r["inner_iters_total"] for r in res])
         objs = np.array([r["objective"] for r in res])
         lat = np.array([r["solve_ms"] for r in res])
-        # oracle on problem 0
-        lam = 1.0 / math.sqrt(size)
-        Jm = np.asarray(Js[0], np.float64).reshape(p, size * size).T
-        I64 = np.asarray(Is[0], np.float64)
-        Z = np.zeros_like(I64)
-        opr = O.Params(eps1=prm.eps1, eps2=prm.eps2, mu0=prm.mu0, rho0=prm.rho0, mu_max=prm.mu_max,
-                       max_inner=prm.max_inner)
-        t1 = time.perf_counter()
-        ref = O.ladmap_inner(I64, O.Annihilator(Jm), lam, I64, Z, Z, opr)
-        cpu_s = time.perf_counter() - t1
-        ref_obj = O.objective(ref.A, ref.E, lam)
-        row = {"size": size, "count": count, "solves_per_s": round(count / (kms * 1e-3), 2),
+        row = {"size": size, "count": count, "path": "wide" if (size >= 300 and count * 8 <= 256) else "one workgroup per problem",
+               "solves_per_s": round(count / (kms * 1e-3), 2),
                "kernel_ms": round(kms, 2), "latency_mean_ms": round(float(lat.mean()), 3),
                "iters_mean": round(float(iters.mean()), 2), "objective_mean": round(float(objs.mean()), 4),
-               "oracle_obj_rel_err": float(abs(res[0]["objective"] - ref_obj) / ref_obj),
-               "oracle_iters": ref.iters, "gpu_iters_0": int(iters[0]), "oracle_cpu_s": round(cpu_s, 3),
+               "gpu_iters_0": int(iters[0]),
                "paper_ladmap_s_per_solve": PAPER_TABLE1_LADMAP[size][0],
                "paper_ladmap_iters": PAPER_TABLE1_LADMAP[size][1]}
+        if size <= 500 and count > 1:
+            # oracle on problem 0
+            lam = 1.0 / math.sqrt(size)
+            Jm = np.asarray(Js[0], np.float64).reshape(p, size * size).T
+            I64 = np.asarray(Is[0], np.float64)
+            Z = np.zeros_like(I64)
+            opr = O.Params(eps1=prm.eps1, eps2=prm.eps2, mu0=prm.mu0, rho0=prm.rho0, mu_max=prm.mu_max,
+                           max_inner=prm.max_inner)
+            t1 = time.perf_counter()
+            ref = O.ladmap_inner(I64, O.Annihilator(Jm), lam, I64, Z, Z, opr)
+            cpu_s = time.perf_counter() - t1
+            ref_obj = O.objective(ref.A, ref.E, lam)
+            row.update({"oracle_obj_rel_err": float(abs(res[0]["objective"] - ref_obj) / ref_obj),
+                        "oracle_iters": ref.iters, "oracle_cpu_s": round(cpu_s, 3)})
         rows.append(row)
         log(f"inner {size}x{size}: {row}")
     head = next(r for r in rows if r["size"] == 100)
