@@ -1186,13 +1186,15 @@ int tilt_warp_jacobian(tilt_ctx* ctx, const tilt_problem* probs, const double* t
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     if (ctx->descs.reserve(sizeof(PatchDesc) * count) != hipSuccess ||
-        ctx->states.reserve(sizeof(PatchState) * count) != hipSuccess)
+        ctx->states.reserve(sizeof(PatchState) * count) != hipSuccess ||
+        ctx->scratch.reserve(sizeof(double) * (1 + MAXP) * STEP1_SLICES * (size_t)count) != hipSuccess)
         return TILT_ERR_NOMEM;
     HIP_TRY(hipMemcpyAsync(ctx->descs.p, descs.data(), sizeof(PatchDesc) * count, hipMemcpyHostToDevice, stream));
     HIP_TRY(hipMemcpyAsync(ctx->states.p, states.data(), sizeof(PatchState) * count, hipMemcpyHostToDevice,
                            stream));
     HIP_TRY(launch_step1(reinterpret_cast<const PatchDesc*>(ctx->descs.p),
-                         reinterpret_cast<PatchState*>(ctx->states.p), count, I_out, J_out, stream));
+                         reinterpret_cast<PatchState*>(ctx->states.p), count,
+                         reinterpret_cast<double*>(ctx->scratch.p), I_out, J_out, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     return TILT_OK;
 }

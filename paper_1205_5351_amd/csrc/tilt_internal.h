@@ -13,6 +13,7 @@ constexpr int MAXPP = 5;         // free parameters after the 3 constraints
 constexpr int NPLANES = 7 + MAXP;
 constexpr int LDS_LIMIT = 160 * 1024;
 constexpr int MAX_LEVELS = 4;    // pyramid levels per request
+constexpr int STEP1_SLICES = 4;  // workgroups per window in the batched Step-1 component kernels
 
 // Per-patch device planes, each nc * ldg floats in "X layout": the matrix
 // is stored with its shorter side as the outer index, so the vectors the
@@ -228,7 +229,7 @@ hipError_t launch_finalize(const PatchDesc* d, PatchState* st, int last, hipStre
 hipError_t launch_mark_end(PatchState* st, hipStream_t s);
 hipError_t launch_inner(const PatchDesc* d, PatchState* st, const SolverParams& prm, const float* I, const float* J,
                         int count, size_t lds, hipStream_t s);
-hipError_t launch_step1(const PatchDesc* d, PatchState* st, int count, float* I_out, float* J_out,
+hipError_t launch_step1(const PatchDesc* d, PatchState* st, int count, double* partial, float* I_out, float* J_out,
                         hipStream_t s);
 hipError_t launch_svt_jobs(const SvtJob* jobs, int count, const SvtShape& shape, float tol,
                            int max_sweeps, long long* counters, float* scratch, size_t lds, hipStream_t s);

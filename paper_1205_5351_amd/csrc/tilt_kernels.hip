@@ -2427,21 +2427,32 @@ __global__ void __launch_bounds__(NT) k_pyramid_jobs(const float* image, int H, 
 // Component kernel: normalised warp and Jacobian (Alg. 1 Step 1); one
 // workgroup per patch, outputs in row-major m x n (I) and p planes of m x n
 // (J, parameter-major).
-__global__ void __launch_bounds__(NT) k_step1(const PatchDesc* descs, PatchState* states, float* I_out,
-                                              float* J_out) {
-    const PatchDesc d = descs[blockIdx.x];
-    const PatchState* st = states + blockIdx.x;
-    const int tid = threadIdx.x;
-    const int p = d.model;
+// Component kernels: Step 1 (warp, Jacobian of the normalised warp) for a
+// batch of windows, each window split over STEP1_SLICES workgroups so that
+// every SIMD holds several waves.  The first kernel writes each slice's
+// partial sums (||I||^2 and I^T J_raw); the second combines the partials of
+// its window in a fixed order, samples its slice again and writes I and J.
+
+__device__ inline void step1_slice(const PatchDesc& d, int slice, size_t* e0, size_t* e1) {
     const size_t mn = (size_t)d.m * d.n;
-    float* Io = I_out + (size_t)blockIdx.x * mn;
-    float* Jo = J_out + (size_t)blockIdx.x * mn * p;
+    const size_t per = (mn + STEP1_SLICES - 1) / STEP1_SLICES;
+    *e0 = min(mn, per * (size_t)slice);
+    *e1 = min(mn, *e0 + per);
+}
+
+__global__ void __launch_bounds__(NT) k_step1_sums(const PatchDesc* descs, const PatchState* states,
+                                                   double* partial) {
+    const int w = blockIdx.x / STEP1_SLICES, slice = blockIdx.x - w * STEP1_SLICES;
+    const PatchDesc d = descs[w];
+    const int p = d.model;
     double h[8];
-    tau_to_h(st, p, h);
+    tau_to_h(states + w, p, h);
+    size_t e0, e1;
+    step1_slice(d, slice, &e0, &e1);
     double acc[1 + MAXP];
 #pragma unroll
     for (int k = 0; k <= MAXP; ++k) acc[k] = 0.0;
-    for (size_t e = tid; e < mn; e += NT) {
+    for (size_t e = e0 + threadIdx.x; e < e1; e += NT) {
         const int i = (int)(e / d.n), j = (int)(e - (size_t)i * d.n);
         float jr[MAXP];
         const float val = warp_pixel(d, h, i, j, jr);
@@ -2450,9 +2461,31 @@ __global__ void __launch_bounds__(NT) k_step1(const PatchDesc* descs, PatchState
         for (int k = 0; k < MAXP; ++k) if (k < p) acc[1 + k] += (double)val * (double)jr[k];
     }
     block_sum_d<1 + MAXP>(acc);
+    if (threadIdx.x <= MAXP) partial[(size_t)blockIdx.x * (1 + MAXP) + threadIdx.x] = acc[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(NT) k_step1_out(const PatchDesc* descs, const PatchState* states,
+                                                  const double* partial, float* I_out, float* J_out) {
+    const int w = blockIdx.x / STEP1_SLICES, slice = blockIdx.x - w * STEP1_SLICES;
+    const PatchDesc d = descs[w];
+    const int p = d.model;
+    const size_t mn = (size_t)d.m * d.n;
+    float* Io = I_out + (size_t)w * mn;
+    float* Jo = J_out + (size_t)w * mn * p;
+    double h[8];
+    tau_to_h(states + w, p, h);
+    double acc[1 + MAXP];
+#pragma unroll
+    for (int k = 0; k <= MAXP; ++k) {
+        double s = 0.0;
+        for (int q = 0; q < STEP1_SLICES; ++q) s += partial[((size_t)w * STEP1_SLICES + q) * (1 + MAXP) + k];
+        acc[k] = s;
+    }
     const double inv_n = 1.0 / sqrt(acc[0]);
     const double inv_n3 = inv_n * inv_n * inv_n;
-    for (size_t e = tid; e < mn; e += NT) {
+    size_t e0, e1;
+    step1_slice(d, slice, &e0, &e1);
+    for (size_t e = e0 + threadIdx.x; e < e1; e += NT) {
         const int i = (int)(e / d.n), j = (int)(e - (size_t)i * d.n);
         float jr[MAXP];
         const double val = warp_pixel(d, h, i, j, jr);
@@ -2665,9 +2698,12 @@ hipError_t launch_pyramid_jobs(const float* image, int H, int W, long long strid
     return hipGetLastError();
 }
 
-hipError_t launch_step1(const PatchDesc* d, PatchState* st, int count, float* I_out, float* J_out,
+hipError_t launch_step1(const PatchDesc* d, PatchState* st, int count, double* partial, float* I_out, float* J_out,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_step1, dim3(count), dim3(NT), 0, s, d, st, I_out, J_out);
+    hipLaunchKernelGGL(k_step1_sums, dim3(count * STEP1_SLICES), dim3(NT), 0, s, d, st, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_step1_out, dim3(count * STEP1_SLICES), dim3(NT), 0, s, d, st, partial, I_out, J_out);
     return hipGetLastError();
 }
 

@@ -333,7 +333,8 @@ def _inner_ref(I, J, prm, lam):
 
 
 @pytest.mark.parametrize("m,n,p,fixed", [(10, 10, 5, True), (50, 50, 5, True), (37, 81, 3, True),
-                                         (100, 100, 5, False), (50, 50, 5, False), (200, 170, 5, True)])
+                                         (100, 100, 5, False), (50, 50, 5, False), (200, 170, 5, True),
+                                         (200, 170, 5, False)])
 def test_inner_loop_alone_matches_oracle(tilt, ctx, device, m, n, p, fixed):
     import torch
 
