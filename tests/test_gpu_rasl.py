@@ -165,3 +165,20 @@ def test_rasl_rejects_invalid_problems(tilt, ctx, device):
     rc, _ = ctx.rasl_solve_batch(descs, tilt.default_params(svt_mode=1))        # warm SVT not offered
     assert rc == tilt.tilt.TILT_ERR_ARG
     del keep, k2
+
+
+def test_rasl_failed_set_leaves_others_intact(tilt, device):
+    """A set with a flat image (J_k = 0, so J_k^T J_k is singular) fails with
+    TILT_ERR_SINGULAR; the set solved beside it in the same launch equals
+    its solve alone."""
+    good = ts.rasl_set(11, count=8, m=12, n=14, height=32, width=36)
+    flat = ts.rasl_set(12, count=8, m=12, n=14, height=32, width=36)
+    flat.images[3] = 0.5
+    tp = tilt.default_params(max_outer=2)
+    with tilt.Context(0) as c:
+        rc, both = _run(c, device, [flat, good], tp)
+        _, alone = _run(c, device, [good], tp)
+    assert both[0]["status"] == tilt.tilt.TILT_ERR_SINGULAR
+    assert rc == tilt.tilt.TILT_ERR_SINGULAR
+    assert both[1]["status"] >= 0
+    assert np.array_equal(both[1]["tau"], alone[0]["tau"]) and np.array_equal(both[1]["A"], alone[0]["A"])
