@@ -324,27 +324,6 @@ __device__ inline void rotate_two(float4* x1, float4* y1, float& nx1, float& ny1
     ny2 = f2 ? fmaxf(fmaf(t2, g2, ny2), 0.f) : ny2;
 }
 
-// Apply a rotation (s, tau) to two rows held in LDS (the lane's chunks).
-template <int LPP, int NCH>
-__device__ inline void rotate_lds_rows(float* pa, float* pb, float s, float h) {
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        const float4 a = *reinterpret_cast<const float4*>(pa + 4 * LPP * c);
-        const float4 b = *reinterpret_cast<const float4*>(pb + 4 * LPP * c);
-        float4 x, y;
-        x.x = fmaf(-s, fmaf(h, a.x, b.x), a.x);
-        x.y = fmaf(-s, fmaf(h, a.y, b.y), a.y);
-        x.z = fmaf(-s, fmaf(h, a.z, b.z), a.z);
-        x.w = fmaf(-s, fmaf(h, a.w, b.w), a.w);
-        y.x = fmaf(s, fmaf(-h, b.x, a.x), b.x);
-        y.y = fmaf(s, fmaf(-h, b.y, a.y), b.y);
-        y.z = fmaf(s, fmaf(-h, b.z, a.z), b.z);
-        y.w = fmaf(s, fmaf(-h, b.w, a.w), b.w);
-        *reinterpret_cast<float4*>(pa + 4 * LPP * c) = x;
-        *reinterpret_cast<float4*>(pb + 4 * LPP * c) = y;
-    }
-}
-
 // Squared norms of rows 0..nrows-1 of B into s2 (LDS).
 template <int LPP, int NCH>
 __device__ void row_norms(const float* B, int nrows, int ld, float* s2) {
@@ -385,6 +364,9 @@ template <int BS, int LPP, int NCH, bool WARM, bool FIRST>
 __device__ inline void jacobi_round(float* B, float* Rm, float* nrm, int ld, int r, int Nb, int Pb, int g, int q,
                                     float tol, int& any, long long& rots) {
     constexpr int G = NT / LPP;
+    // WARM: the rotation rows of the block pair (same layout as the Jacobi
+    // rows) stay in registers for the round and take the same rotations.
+    constexpr int RN = WARM ? NCH : 1;
     for (int k = g; k < Pb; k += G) {
         int I, J;
         if (k == 0) {
@@ -400,17 +382,28 @@ __device__ inline void jacobi_round(float* B, float* Rm, float* nrm, int ld, int
         float* pb = B + (BS * J) * ld + 4 * q;
         if (BS == 1) {
             float4 a1[NCH], b1[NCH];
+            float4 ra[RN], rb[RN];
             load_row<LPP, NCH>(pa, a1);
             load_row<LPP, NCH>(pb, b1);
+            float* qa = WARM ? Rm + I * ld + 4 * q : nullptr;
+            float* qb = WARM ? Rm + J * ld + 4 * q : nullptr;
+            if (WARM) {
+                load_row<LPP, RN>(qa, ra);
+                load_row<LPP, RN>(qb, rb);
+            }
             float na1 = nrm[I], nb1 = nrm[J];
             float sr, hr;
             const bool f = rotate_rows<LPP, NCH>(a1, b1, na1, nb1, tol, sr, hr);
-            if (WARM && f) rotate_lds_rows<LPP, NCH>(Rm + I * ld + 4 * q, Rm + J * ld + 4 * q, sr, hr);
+            if (WARM && __any(f)) apply_rotation<RN>(ra, rb, sr, hr);
             if (f) {
                 any = 1;
                 rots += 1;
                 store_row<LPP, NCH>(pa, a1);
                 store_row<LPP, NCH>(pb, b1);
+                if (WARM) {
+                    store_row<LPP, RN>(qa, ra);
+                    store_row<LPP, RN>(qb, rb);
+                }
                 if (q == 0) {
                     nrm[I] = na1;
                     nrm[J] = nb1;
@@ -418,34 +411,53 @@ __device__ inline void jacobi_round(float* B, float* Rm, float* nrm, int ld, int
             }
         } else {
             float4 a1[NCH], a2[NCH], b1[NCH], b2[NCH];
+            float4 ra1[RN], ra2[RN], rb1[RN], rb2[RN];
             load_row<LPP, NCH>(pa, a1);
             load_row<LPP, NCH>(pa + ld, a2);
             load_row<LPP, NCH>(pb, b1);
             load_row<LPP, NCH>(pb + ld, b2);
+            float* qa = WARM ? Rm + (BS * I) * ld + 4 * q : nullptr;
+            float* qb = WARM ? Rm + (BS * J) * ld + 4 * q : nullptr;
+            if (WARM) {
+                load_row<LPP, RN>(qa, ra1);
+                load_row<LPP, RN>(qa + ld, ra2);
+                load_row<LPP, RN>(qb, rb1);
+                load_row<LPP, RN>(qb + ld, rb2);
+            }
             float na1 = nrm[2 * I], na2 = nrm[2 * I + 1], nb1 = nrm[2 * J], nb2 = nrm[2 * J + 1];
             bool d0 = false, d1 = false, d2 = false, d3 = false, f, h;
             float s1, h1, s2, h2;
-            float* ra1 = WARM ? Rm + (BS * I) * ld + 4 * q : nullptr;
-            float* rb1 = WARM ? Rm + (BS * J) * ld + 4 * q : nullptr;
             if (FIRST) {
                 rotate_two<LPP, NCH>(a1, a2, na1, na2, f, b1, b2, nb1, nb2, h, tol, s1, h1, s2, h2);
-                if (WARM && f) rotate_lds_rows<LPP, NCH>(ra1, ra1 + ld, s1, h1);
-                if (WARM && h) rotate_lds_rows<LPP, NCH>(rb1, rb1 + ld, s2, h2);
+                if (WARM && __any(f || h)) {
+                    apply_rotation<RN>(ra1, ra2, s1, h1);
+                    apply_rotation<RN>(rb1, rb2, s2, h2);
+                }
                 d0 |= f; d1 |= f; d2 |= h; d3 |= h; rots += f; rots += h;
             }
             rotate_two<LPP, NCH>(a1, b1, na1, nb1, f, a2, b2, na2, nb2, h, tol, s1, h1, s2, h2);
-            if (WARM && f) rotate_lds_rows<LPP, NCH>(ra1, rb1, s1, h1);
-            if (WARM && h) rotate_lds_rows<LPP, NCH>(ra1 + ld, rb1 + ld, s2, h2);
+            if (WARM && __any(f || h)) {
+                apply_rotation<RN>(ra1, rb1, s1, h1);
+                apply_rotation<RN>(ra2, rb2, s2, h2);
+            }
             d0 |= f; d2 |= f; d1 |= h; d3 |= h; rots += f; rots += h;
             rotate_two<LPP, NCH>(a1, b2, na1, nb2, f, a2, b1, na2, nb1, h, tol, s1, h1, s2, h2);
-            if (WARM && f) rotate_lds_rows<LPP, NCH>(ra1, rb1 + ld, s1, h1);
-            if (WARM && h) rotate_lds_rows<LPP, NCH>(ra1 + ld, rb1, s2, h2);
+            if (WARM && __any(f || h)) {
+                apply_rotation<RN>(ra1, rb2, s1, h1);
+                apply_rotation<RN>(ra2, rb1, s2, h2);
+            }
             d0 |= f; d3 |= f; d1 |= h; d2 |= h; rots += f; rots += h;
             if (d0 | d1 | d2 | d3) any = 1;
             if (d0) store_row<LPP, NCH>(pa, a1);
             if (d1) store_row<LPP, NCH>(pa + ld, a2);
             if (d2) store_row<LPP, NCH>(pb, b1);
             if (d3) store_row<LPP, NCH>(pb + ld, b2);
+            if (WARM) {
+                if (d0) store_row<LPP, RN>(qa, ra1);
+                if (d1) store_row<LPP, RN>(qa + ld, ra2);
+                if (d2) store_row<LPP, RN>(qb, rb1);
+                if (d3) store_row<LPP, RN>(qb + ld, rb2);
+            }
             if (q == 0) {
                 nrm[2 * I] = na1;
                 nrm[2 * I + 1] = na2;
