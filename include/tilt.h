@@ -163,8 +163,10 @@ int tilt_tau_from_quad(const double quad[8], int m, int n, int model, double tau
 
 /* Plain single-patch path: host pointers in and out, synchronous, on the
  * current device.  Runs Alg. 1 step by step with one kernel per step and one
- * device-to-host read of the stop flags per inner iteration.  Allocates and
- * frees its own device memory. */
+ * device-to-host read of the stop flags per inner iteration; when the
+ * window's SVT does not fit LDS, each round of the tiled Jacobi runs on many
+ * workgroups (same results as the batched path).  Allocates and frees its
+ * own device memory. */
 int tilt_solve(const tilt_problem* prob, const tilt_params* prm, tilt_result* res);
 
 /* ------------------------------------------------------------------------

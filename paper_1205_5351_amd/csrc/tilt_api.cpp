@@ -520,8 +520,13 @@ int capture_inner(InnerGraph* G, const PatchDesc* d, PatchState* ds, const Solve
 // graph_k > 0 the inner iterations run as replays of a captured graph of
 // graph_k iterations (one stop-flag read per replay); the first inner
 // iteration of each inner loop is launched eagerly.
+// A level whose SVT does not fit LDS runs each Jacobi round's super-block
+// pairs on separate workgroups (the wide kernels, same tiling, same bits as
+// the one-workgroup tiled Jacobi): the host launches one kernel per round
+// and reads the rotation flag after each sweep.  The decomposition of I for
+// mu_0 goes the same way.  Such levels are never captured into graphs.
 int run_plain_request(tilt_ctx* ctx, size_t lds, const SolverParams& sp, int L, int k, hipStream_t stream,
-                      int graph_k) {
+                      int graph_k, const RequestPlan& plan) {
     const PatchDesc* dl = reinterpret_cast<const PatchDesc*>(ctx->descs.p) + (size_t)k * L;
     PatchState* ds = reinterpret_cast<PatchState*>(ctx->states.p) + k;
     PatchState hs;
@@ -530,10 +535,38 @@ int run_plain_request(tilt_ctx* ctx, size_t lds, const SolverParams& sp, int L, 
         HIP_TRY(hipStreamSynchronize(stream));
         return TILT_OK;
     };
+    // [active list {0}, rotation flag, sweep count] for the wide kernels
+    if (ctx->queue.reserve(256) != hipSuccess) return TILT_ERR_NOMEM;
+    int* d_ints = reinterpret_cast<int*>(ctx->queue.p);
+    HIP_TRY(hipMemsetAsync(d_ints, 0, 3 * sizeof(int), stream));
+    bool configured = false;
+    auto wide_svd = [&](const PatchDesc* d, const PatchDesc& hd, int form_m) -> int {
+        HIP_TRY(launch_wide_stage(d, ds, d_ints, 1, form_m, d_ints + 1, stream));
+        const size_t lr = sizeof(float) * 2 * (size_t)hd.sb * hd.ld;
+        int sweeps = 0, flag = 1;
+        for (int sw = 0; sw < sp.max_sweeps && flag; ++sw) {
+            for (int r = 0; r < hd.nsb - 1; ++r) {
+                HIP_TRY(launch_wide_round(d, ds, d_ints, 1, hd.nsb / 2, r, sp.jacobi_tol, d_ints + 1, lr, !configured,
+                                          stream));
+                configured = true;
+            }
+            HIP_TRY(hipMemcpyAsync(&flag, d_ints + 1, sizeof(int), hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            HIP_TRY(hipMemsetAsync(d_ints + 1, 0, sizeof(int), stream));
+            ++sweeps;
+        }
+        HIP_TRY(hipMemcpyAsync(d_ints + 2, &sweeps, sizeof(int), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        return TILT_OK;
+    };
     HIP_TRY(launch_level_begin(dl + L - 1, ds, 1, stream));
     if (L > 1) HIP_TRY(launch_pyramid_build(dl, L, stream));
     for (int l = L - 1; l >= 0; --l) {
         const PatchDesc* d = dl + l;
+        const PatchDesc& hd = plan.d[l];
+        const bool wide = hd.sb > 0 && !hd.warm;
+        SolverParams sp_setup = sp;
+        if (wide && !(sp_setup.mu0 > 0.0)) sp_setup.mu0 = 1.0;  // mu_0 from the wide decomposition of I
         if (l < L - 1) {
             if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
             if (hs.status < 0) break;
@@ -543,16 +576,28 @@ int run_plain_request(tilt_ctx* ctx, size_t lds, const SolverParams& sp, int L, 
         }
         InnerGraph graph;
         for (;;) {
-            HIP_TRY(launch_setup(d, ds, sp, lds, stream));
+            HIP_TRY(launch_setup(d, ds, sp_setup, lds, stream));
             if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
             if (hs.status < 0) break;
-            if (graph_k > 0 && !graph.ge) {
+            if (wide && !(sp.mu0 > 0.0)) {
+                const int w = wide_svd(d, hd, 0);
+                if (w != TILT_OK) return w;
+                HIP_TRY(launch_wide_finish(d, ds, d_ints, 1, sp, d_ints + 2, 1, lds, stream));
+                if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
+                if (hs.status < 0) break;
+            }
+            if (!wide && graph_k > 0 && !graph.ge) {
                 const int c = capture_inner(&graph, d, ds, sp, lds, graph_k, stream);
                 if (c != TILT_OK) return c;
                 if (fetch() != TILT_OK) return TILT_ERR_DEVICE;
             }
             while (!hs.done_inner) {
-                if (graph.ge) {
+                if (wide) {
+                    const int w = wide_svd(d, hd, 1);
+                    if (w != TILT_OK) return w;
+                    HIP_TRY(launch_wide_finish(d, ds, d_ints, 1, sp, d_ints + 2, 0, lds, stream));
+                    HIP_TRY(launch_update(d, ds, sp, stream));
+                } else if (graph.ge) {
                     HIP_TRY(hipGraphLaunch(graph.ge, stream));
                 } else {
                     HIP_TRY(launch_svt(d, ds, sp, lds, stream));
@@ -607,7 +652,8 @@ int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const 
                 ps = own;
             }
             int r = TILT_OK;
-            for (int k = 0; k < nlive && r == TILT_OK; ++k) r = run_plain_request(ctx, max_lds, sp, L, k, ps, prm->graph_inner);
+            for (int k = 0; k < nlive && r == TILT_OK; ++k)
+                r = run_plain_request(ctx, max_lds, sp, L, k, ps, prm->graph_inner, plans[k]);
             if (own) {
                 (void)hipEventRecord(ctx->ev1, own);
                 (void)hipStreamWaitEvent(stream, ctx->ev1, 0);

@@ -270,6 +270,24 @@ def test_ragged_shapes_fixed_iters(tilt, ctx, device, m, n, model):
     assert O.tau_rel_err(r["tau"], ref.tau_px, m, n) <= 1e-5
 
 
+def test_plain_wide_svt_equals_fused_bitwise(tilt, ctx, device):
+    """A window whose SVT does not fit LDS: the plain path runs each Jacobi
+    round's super-block pairs on separate workgroups, the fused kernel runs
+    them one after another in one workgroup; the pairs of a round touch
+    disjoint rows, so tau, A, E and the work counters agree bit for bit."""
+    rng = ts.patch_rng(98, 1)
+    p = ts.make_patch(rng, m=300, n=280, height=620, width=620, rank=2, model=6, corruption=0.05, theta_deg=5,
+                      skew=0.05)
+    tp = tilt.default_params(fixed_iters=1, max_outer=2, max_inner=3, lam=p.lam)
+    _, fused = solve_on_device(tilt, ctx, [p], device, tp)
+    _, plain = solve_on_device(tilt, ctx, [p], device, tp, plain=True)
+    a, b = fused[0], plain[0]
+    assert a["status"] == 0 and b["status"] == 0
+    assert np.array_equal(a["tau"], b["tau"])
+    assert np.array_equal(a["A"], b["A"]) and np.array_equal(a["E"], b["E"])
+    assert a["counters"] == b["counters"]
+
+
 # ---------------------------------------------------------------------------
 # a5 warm: SVT started from the previous iteration's accumulated rotation
 # (svt_mode = 1).  It computes the same shrinkage, so the oracle and the
