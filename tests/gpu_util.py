@@ -7,6 +7,29 @@ from __future__ import annotations
 import numpy as np
 
 
+def same_numerical_rank(O, A_dev, A_ref, rel=1e-3):
+    """Numerical rank #{sigma_i > rel sigma_1} of the device result against
+    the oracle's.  The count jumps at the cut, so it is compared as far as
+    the two matrices determine it: by Weyl's inequality each singular value
+    of A_dev lies within d = ||A_dev - A_ref||_2 of the matching one of
+    A_ref (and the cut rel sigma_1 moves by at most rel d), so the counts
+    may differ only by oracle singular values within (1 + rel) d of the
+    cut, and only while d is below a quarter of the cut (so no singular
+    value further than 25 % from the cut may fall on the other side).
+    Returns (agree, rank_dev, rank_ref)."""
+    a = np.asarray(A_dev, dtype=np.float64)
+    b = np.asarray(A_ref, dtype=np.float64)
+    r_dev, r_ref = O.numerical_rank(a, rel), O.numerical_rank(b, rel)
+    if r_dev == r_ref:
+        return True, r_dev, r_ref
+    d = float(np.linalg.norm(a - b, 2))
+    sv = np.linalg.svd(b, compute_uv=False)
+    cut = rel * sv[0]
+    lo, hi = min(r_dev, r_ref), max(r_dev, r_ref)
+    agree = d <= 0.25 * cut and all(abs(sv[i] - cut) <= (1.0 + rel) * d for i in range(lo, hi))
+    return agree, r_dev, r_ref
+
+
 def to_device(arr, device):
     import torch
 
