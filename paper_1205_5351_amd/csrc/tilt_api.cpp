@@ -42,15 +42,36 @@ void DevBuf::release() {
     bytes = 0;
 }
 
+// Chunks per lane (and single floats after them) for rows of nr4 float4
+// chunks in groups of lpp lanes.  With tails allowed, a two-row-block layout
+// of 8 or 16 lanes whose last chunk would hold at most 2 real floats per lane
+// keeps those as single floats instead (100 floats in 8 lanes: 3 chunks + 1
+// float, 104 floats, instead of 4 chunks, 128).  The device instantiates
+// these layouts for 1-3 chunks.
+void split_row(int nr4, int bs, int lpp, bool tails, int* nch, int* tl) {
+    *nch = (nr4 + lpp - 1) / lpp;
+    *tl = 0;
+    if (!tails || bs != 2 || (lpp != 8 && lpp != 16)) return;
+    const int full = nr4 / lpp;
+    const int rem = 4 * (nr4 - full * lpp);  // floats beyond the full chunks
+    if (full < 1 || full > 3 || rem == 0) return;
+    const int t = (rem + lpp - 1) / lpp;
+    if (t <= 2) {
+        *nch = full;
+        *tl = t;
+    }
+}
+
 // Jacobi layout for a matrix of nc rows of nr4 float4 chunks: rows per
-// block (BS), lanes per block pair (LPP) and chunks per lane (NCH).  The
+// block (BS), lanes per block pair (LPP), chunks per lane (NCH) and single
+// floats per lane (TL, only with tails: the one-workgroup SVT).  The
 // model counts, per sweep, rounds x block pairs per lane group x the
 // instructions of a round (BS^2 rotations of NCH chunks plus a fixed cost
 // for the reduction and rotation parameters that grows with the reduction
 // width, plus the row loads/stores), and divides by the number of
 // concurrent groups' worth of issue slots when fewer groups than slots are
 // busy.  The cheapest layout wins.
-int pick_svt_cfg(int nc, int nr4) {
+int pick_svt_cfg(int nc, int nr4, bool tails) {
     const int nc4 = (nc + 3) & ~3;
     int best = -1;
     double best_cost = 1e300;
@@ -62,15 +83,17 @@ int pick_svt_cfg(int nc, int nr4) {
         for (int li = long_rows ? 3 : 0; li < (long_rows ? 5 : 3); ++li) {
             if (long_rows && lpps[li] == 32 && bs == 2) continue;
             const int lpp = lpps[li];
-            const int nch = (nr4 + lpp - 1) / lpp;
+            int nch, tl;
+            split_row(nr4, bs, lpp, tails, &nch, &tl);
             if (nch > (bs == 1 ? SVT_MAX_NCH : 4)) continue;
+            const int fl = 4 * nch + tl;  // floats per lane and row
             const int groups = NT / lpp;
             const int nb = nc4 / bs;
             const int pairs = nb / 2;
             const int per_group = (pairs + groups - 1) / groups;
             const int active = std::min(pairs, groups);
-            const double rot = 20.0 * nch + 30.0 + 4.0 * li;
-            const double round_instr = per_group * (bs * bs * rot + 4.0 * bs * nch) + 40.0;
+            const double rot = 5.0 * fl + 30.0 + 4.0 * li;
+            const double round_instr = per_group * (bs * bs * rot + 1.0 * bs * fl) + 40.0;
             // waves with work per SIMD: issue-bound when >= 2, latency-bound below
             const double waves = std::max(1.0, active * (double)lpp / 64.0 / 4.0);
             const double round_cycles = round_instr * 4.0 * std::max(waves, 2.0) / (bs == 2 ? 1.5 : 1.0);
@@ -79,19 +102,20 @@ int pick_svt_cfg(int nc, int nr4) {
             const double cost = (nb - 1) * round_cycles * (spills ? 4.0 : 1.0);
             if (cost < best_cost) {
                 best_cost = cost;
-                best = svt_make_cfg(bs, lpp, nch);
+                best = svt_make_cfg(bs, lpp, nch, tl);
             }
         }
     }
     return best;
 }
 
-// LDS row stride: at least 4*LPP*NCH floats (every lane reads NCH chunks)
-// and chosen so that the lane groups served by one 256-byte LDS pass
-// (consecutive groups start BS rows apart) hit disjoint banks.
+// LDS row stride: at least LPP*(4*NCH + TL) floats (every lane reads NCH
+// chunks and TL single floats) and chosen so that the lane groups served by
+// one 256-byte LDS pass (consecutive groups start BS rows apart) hit
+// disjoint banks.
 int pick_ld(int cfg) {
-    const int bs = svt_bs(cfg), lpp = svt_lpp(cfg), nch = svt_nch(cfg);
-    const int min_ld = 4 * lpp * nch;
+    const int bs = svt_bs(cfg), lpp = svt_lpp(cfg);
+    const int min_ld = svt_span(cfg);
     const int group_bytes = 16 * lpp;
     const int per_pass = std::max(1, 256 / group_bytes);
     for (int ld = min_ld; ld < min_ld + 256; ld += 4) {
@@ -136,7 +160,7 @@ struct TuneEntry {
 std::mutex g_tune_mu;
 std::vector<TuneEntry> g_tune;
 
-int tuned_cfg(int nc, int nr4) {
+int tuned_cfg(int nc, int nr4, bool tails) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     const TuneEntry* best = nullptr;
     double bd = 1e300;
@@ -151,14 +175,16 @@ int tuned_cfg(int nc, int nr4) {
         }
     }
     if (!best) return -1;
-    const int nch = (nr4 + best->lpp - 1) / best->lpp;
+    int nch, tl;
+    split_row(nr4, best->bs, best->lpp, tails, &nch, &tl);
     if (nch > (best->bs == 1 ? SVT_MAX_NCH : 4)) return -1;
-    return svt_make_cfg(best->bs, best->lpp, nch);
+    return svt_make_cfg(best->bs, best->lpp, nch, tl);
 }
 
+// Layout of the one-workgroup SVT (single floats allowed).
 int choose_svt_cfg(int nc, int nr4) {
-    const int t = tuned_cfg(nc, nr4);
-    return t >= 0 ? t : pick_svt_cfg(nc, nr4);
+    const int t = tuned_cfg(nc, nr4, true);
+    return t >= 0 ? t : pick_svt_cfg(nc, nr4, true);
 }
 
 int shape_config(int m, int n, ShapeCfg* out) {
@@ -206,7 +232,7 @@ int shape_config(int m, int n, ShapeCfg* out) {
         if (2 * sb > SVT_MAX_ROWS) continue;
         const int ncp = nsb * sb;
         if (ncp > SVT_MAX_TILED_ROWS) continue;  // rounding sb up to 4 rows: ncp is not monotonic in nsb
-        const int cfg = pick_svt_cfg(2 * sb, c.ldg / 4);
+        const int cfg = pick_svt_cfg(2 * sb, c.ldg / 4, false);
         if (cfg < 0) return TILT_ERR_TOO_LARGE;
         const int ld = pick_ld(cfg);
         for (int tb = 32; tb >= 16; tb -= 16) {
@@ -725,7 +751,7 @@ bool wide_tiling(int nc, int ldg, WideTiling* out) {
     const int nc4 = (nc + 3) & ~3;
     const size_t budget = (size_t)LDS_LIMIT - kStaticLdsMargin;
     for (int sb = std::min(128, ((nc4 / 2) + 3) & ~3); sb >= 4; sb -= 4) {
-        const int cfg = pick_svt_cfg(2 * sb, ldg / 4);
+        const int cfg = pick_svt_cfg(2 * sb, ldg / 4, false);
         if (cfg < 0) continue;
         if (sb / svt_bs(cfg) > NT / svt_lpp(cfg)) continue;
         int nsb = (nc4 + sb - 1) / sb;

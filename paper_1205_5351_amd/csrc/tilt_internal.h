@@ -169,13 +169,20 @@ struct SvtJob {
 };
 
 // LDS layout helpers (host and device).
-// cfg = (BS - 1) * 128 + log2(LPP / 4) * 16 + (NCH - 1)
-__host__ __device__ constexpr int svt_make_cfg(int bs, int lpp, int nch) {
-    return (bs - 1) * 128 + (lpp == 4 ? 0 : lpp == 8 ? 1 : lpp == 16 ? 2 : lpp == 32 ? 3 : 4) * 16 + (nch - 1);
+// cfg = TL * 256 + (BS - 1) * 128 + log2(LPP / 4) * 16 + (NCH - 1): blocks of
+// BS rows, LPP lanes per block pair, NCH float4 chunks per lane and row,
+// then TL (0, 1 or 2) single floats per lane, so a lane group covers
+// LPP * (4 NCH + TL) floats of a row.
+__host__ __device__ constexpr int svt_make_cfg(int bs, int lpp, int nch, int tl = 0) {
+    return tl * 256 + (bs - 1) * 128 + (lpp == 4 ? 0 : lpp == 8 ? 1 : lpp == 16 ? 2 : lpp == 32 ? 3 : 4) * 16 +
+           (nch - 1);
 }
-__host__ __device__ inline int svt_bs(int cfg) { return (cfg >> 7) + 1; }
+__host__ __device__ inline int svt_bs(int cfg) { return ((cfg >> 7) & 1) + 1; }
 __host__ __device__ inline int svt_lpp(int cfg) { return 4 << ((cfg >> 4) & 7); }
 __host__ __device__ inline int svt_nch(int cfg) { return (cfg & 15) + 1; }
+__host__ __device__ inline int svt_tl(int cfg) { return (cfg >> 8) & 3; }
+// Floats of a row covered by one lane group.
+__host__ __device__ inline int svt_span(int cfg) { return svt_lpp(cfg) * (4 * svt_nch(cfg) + svt_tl(cfg)); }
 
 // Serving ring: request slots and the control word live in pinned
 // (coherent) host memory; the host publishes requests by raising `tail`,

@@ -150,9 +150,9 @@ __device__ inline float4 f4(float a) { return make_float4(a, a, a, a); }
 // of BS rows (BS = 1: single rows, BS = 2: pairs of rows).
 //
 // Rows 0..nc4-1 (nc rounded up to a multiple of 4 with zero rows) with
-// stride ld; every row is zero-padded to 4*LPP*NCH floats so each of the
-// LPP lanes of a group reads exactly NCH float4 chunks (lane q owns chunks
-// q, q+LPP, ...).  Each round pairs every block with another (circle
+// stride ld; every row is zero-padded to LPP*(4*NCH + TL) floats so each of
+// the LPP lanes of a group reads exactly NCH float4 chunks (lane q owns
+// chunks q, q+LPP, ...) and TL single floats after them.  Each round pairs every block with another (circle
 // method: the last block is fixed, pair k of round r is (r+k, r-k) mod
 // (nb-1)); a group owns one block pair, holds its 2 BS rows in registers
 // and rotates its cross pairs -- for BS = 2 in the order (a1,b1), (a2,b2),
@@ -181,10 +181,15 @@ struct JacobiStats {
 // correction, which keeps the transformation orthogonal to rounding level
 // with no systematic shrink or growth of the rows over the thousands of
 // rotations of a decomposition.  Four transcendental instructions per pair.
-__device__ inline void jacobi_rotation(float al, float be, float ga, float& sn, float& ta, float& tn) {
+// t = 0 gives s = tau = 0 exactly (and leaves the tracked norms unchanged),
+// so a pair that needs no rotation only has its t replaced by 0.
+__device__ inline float rotation_tangent(float al, float be, float ga) {
     const float d = be - al;
     const float dd = __builtin_amdgcn_sqrtf(fmaf(d, d, 4.0f * ga * ga));
-    const float t = copysignf(1.0f, d) * (2.0f * ga) * __builtin_amdgcn_rcpf(fabsf(d) + dd);
+    return copysignf(1.0f, d) * (2.0f * ga) * __builtin_amdgcn_rcpf(fabsf(d) + dd);
+}
+
+__device__ inline void rotation_sin_halftan(float t, float& sn, float& ta) {
     const float q = fmaf(t, t, 1.0f);
     float y = __builtin_amdgcn_rsqf(q);
     y = fmaf(y, fmaf(-0.5f * q * y, y, 0.5f), y);
@@ -194,7 +199,11 @@ __device__ inline void jacobi_rotation(float al, float be, float ga, float& sn, 
     const float h = t * ro;
     sn = t * y;
     ta = fmaf(fmaf(-h, op, t), ro, h);
-    tn = t;
+}
+
+__device__ inline void jacobi_rotation(float al, float be, float ga, float& sn, float& ta, float& tn) {
+    tn = rotation_tangent(al, be, ga);
+    rotation_sin_halftan(tn, sn, ta);
 }
 
 // Rotation test: |a.b| > tol ||a|| ||b||, squared (no square roots).
@@ -210,72 +219,117 @@ __device__ inline float dot4(const float4& a, const float4& b, float acc) {
     return acc;
 }
 
-// a.b summed over the group (two partial sums per lane for shorter chains).
-template <int LPP, int NCH>
-__device__ inline float group_dot(const float4* a, const float4* b) {
-    float s0 = 0.f, s1 = 0.f;
+// A lane's part of one row: NCH float4 chunks (lane q of a group owns chunks
+// q, q + LPP, ...), then TL single floats (lane q owns floats
+// 4 LPP NCH + q TL + t).  The single floats let a row whose length is not a
+// multiple of 4 LPP avoid a last chunk that would be mostly zero padding.
+template <int NCH, int TL>
+struct RowPart {
+    float4 c[NCH];
+    float t[TL > 0 ? TL : 1];
+};
+
+template <int LPP, int NCH, int TL>
+__device__ inline void load_row(const float* row, int q, RowPart<NCH, TL>& x) {
 #pragma unroll
-    for (int c = 0; c < NCH; c += 2) s0 = dot4(a[c], b[c], s0);
-#pragma unroll
-    for (int c = 1; c < NCH; c += 2) s1 = dot4(a[c], b[c], s1);
-    return group_sum<LPP>(s0 + s1);
+    for (int c = 0; c < NCH; ++c) x.c[c] = *reinterpret_cast<const float4*>(row + 4 * q + 4 * LPP * c);
+    if constexpr (TL == 1) x.t[0] = row[4 * LPP * NCH + q];
+    if constexpr (TL == 2) {
+        const float2 v = *reinterpret_cast<const float2*>(row + 4 * LPP * NCH + 2 * q);
+        x.t[0] = v.x;
+        x.t[1] = v.y;
+    }
 }
 
-// Rotate rows x, y (registers of the group) if they are not yet orthogonal
-// to tolerance; updates their squared norms.  The decision is uniform over
-// the group (all lanes hold identical sums).
-template <int LPP, int NCH>
-__device__ inline bool rotate_rows(float4* x, float4* y, float& nx, float& ny, float tol, float& sn, float& ta) {
-    sn = ta = 0.f;
-    const float ga = group_dot<LPP, NCH>(x, y);
-    if (!needs_rotation(ga, nx, ny, tol)) return false;
-    float t;
-    jacobi_rotation(nx, ny, ga, sn, ta, t);
+template <int LPP, int NCH, int TL>
+__device__ inline void store_row(float* row, int q, const RowPart<NCH, TL>& x) {
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        const float4 a = x[c], b = y[c];
-        x[c].x = fmaf(-sn, fmaf(ta, a.x, b.x), a.x);
-        x[c].y = fmaf(-sn, fmaf(ta, a.y, b.y), a.y);
-        x[c].z = fmaf(-sn, fmaf(ta, a.z, b.z), a.z);
-        x[c].w = fmaf(-sn, fmaf(ta, a.w, b.w), a.w);
-        y[c].x = fmaf(sn, fmaf(-ta, b.x, a.x), b.x);
-        y[c].y = fmaf(sn, fmaf(-ta, b.y, a.y), b.y);
-        y[c].z = fmaf(sn, fmaf(-ta, b.z, a.z), b.z);
-        y[c].w = fmaf(sn, fmaf(-ta, b.w, a.w), b.w);
-    }
-    // Tracked norms; clamped at 0 (cancellation can only make a small norm
-    // inaccurate until the exact recomputation at the next sweep start).
-    nx = fmaxf(fmaf(-t, ga, nx), 0.f);
-    ny = fmaxf(fmaf(t, ga, ny), 0.f);
-    return true;
+    for (int c = 0; c < NCH; ++c) *reinterpret_cast<float4*>(row + 4 * q + 4 * LPP * c) = x.c[c];
+    if constexpr (TL == 1) row[4 * LPP * NCH + q] = x.t[0];
+    if constexpr (TL == 2) *reinterpret_cast<float2*>(row + 4 * LPP * NCH + 2 * q) = make_float2(x.t[0], x.t[1]);
+}
+
+// a.b summed over the group (two partial sums per lane for shorter chains:
+// even chunks, then odd chunks and the single floats).
+template <int LPP, int NCH, int TL>
+__device__ inline float group_dot(const RowPart<NCH, TL>& a, const RowPart<NCH, TL>& b) {
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCH; c += 2) s0 = dot4(a.c[c], b.c[c], s0);
+#pragma unroll
+    for (int c = 1; c < NCH; c += 2) s1 = dot4(a.c[c], b.c[c], s1);
+#pragma unroll
+    for (int i = 0; i < TL; ++i) s1 = fmaf(a.t[i], b.t[i], s1);
+    return group_sum<LPP>(s0 + s1);
 }
 
 // Rotate two rows in place by (s, tau): a' = a - s (b + tau a),
 // b' = b + s (a - tau b).  Both temporaries are formed before either row is
 // overwritten, so the update needs no register copies; s = tau = 0 leaves
 // the rows bit-for-bit unchanged.
-template <int NCH>
-__device__ inline void apply_rotation(float4* x, float4* y, float s, float h) {
+__device__ inline void rotate_values(float& a, float& b, float s, float h) {
+    const float u = fmaf(h, a, b);
+    const float v = fmaf(-h, b, a);
+    a = fmaf(-s, u, a);
+    b = fmaf(s, v, b);
+}
+
+template <int NCH, int TL>
+__device__ inline void apply_rotation(RowPart<NCH, TL>& x, RowPart<NCH, TL>& y, float s, float h) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         float4 u, v;
-        u.x = fmaf(h, x[c].x, y[c].x);
-        u.y = fmaf(h, x[c].y, y[c].y);
-        u.z = fmaf(h, x[c].z, y[c].z);
-        u.w = fmaf(h, x[c].w, y[c].w);
-        v.x = fmaf(-h, y[c].x, x[c].x);
-        v.y = fmaf(-h, y[c].y, x[c].y);
-        v.z = fmaf(-h, y[c].z, x[c].z);
-        v.w = fmaf(-h, y[c].w, x[c].w);
-        x[c].x = fmaf(-s, u.x, x[c].x);
-        x[c].y = fmaf(-s, u.y, x[c].y);
-        x[c].z = fmaf(-s, u.z, x[c].z);
-        x[c].w = fmaf(-s, u.w, x[c].w);
-        y[c].x = fmaf(s, v.x, y[c].x);
-        y[c].y = fmaf(s, v.y, y[c].y);
-        y[c].z = fmaf(s, v.z, y[c].z);
-        y[c].w = fmaf(s, v.w, y[c].w);
+        u.x = fmaf(h, x.c[c].x, y.c[c].x);
+        u.y = fmaf(h, x.c[c].y, y.c[c].y);
+        u.z = fmaf(h, x.c[c].z, y.c[c].z);
+        u.w = fmaf(h, x.c[c].w, y.c[c].w);
+        v.x = fmaf(-h, y.c[c].x, x.c[c].x);
+        v.y = fmaf(-h, y.c[c].y, x.c[c].y);
+        v.z = fmaf(-h, y.c[c].z, x.c[c].z);
+        v.w = fmaf(-h, y.c[c].w, x.c[c].w);
+        x.c[c].x = fmaf(-s, u.x, x.c[c].x);
+        x.c[c].y = fmaf(-s, u.y, x.c[c].y);
+        x.c[c].z = fmaf(-s, u.z, x.c[c].z);
+        x.c[c].w = fmaf(-s, u.w, x.c[c].w);
+        y.c[c].x = fmaf(s, v.x, y.c[c].x);
+        y.c[c].y = fmaf(s, v.y, y.c[c].y);
+        y.c[c].z = fmaf(s, v.z, y.c[c].z);
+        y.c[c].w = fmaf(s, v.w, y.c[c].w);
     }
+#pragma unroll
+    for (int i = 0; i < TL; ++i) rotate_values(x.t[i], y.t[i], s, h);
+}
+
+// Rotate rows x, y (registers of the group) if they are not yet orthogonal
+// to tolerance; updates their squared norms.  The decision is uniform over
+// the group (all lanes hold identical sums).
+template <int LPP, int NCH, int TL>
+__device__ inline bool rotate_rows(RowPart<NCH, TL>& x, RowPart<NCH, TL>& y, float& nx, float& ny, float tol,
+                                   float& sn, float& ta) {
+    sn = ta = 0.f;
+    const float ga = group_dot<LPP, NCH, TL>(x, y);
+    if (!needs_rotation(ga, nx, ny, tol)) return false;
+    float t;
+    jacobi_rotation(nx, ny, ga, sn, ta, t);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const float4 a = x.c[c], b = y.c[c];
+        x.c[c].x = fmaf(-sn, fmaf(ta, a.x, b.x), a.x);
+        x.c[c].y = fmaf(-sn, fmaf(ta, a.y, b.y), a.y);
+        x.c[c].z = fmaf(-sn, fmaf(ta, a.z, b.z), a.z);
+        x.c[c].w = fmaf(-sn, fmaf(ta, a.w, b.w), a.w);
+        y.c[c].x = fmaf(sn, fmaf(-ta, b.x, a.x), b.x);
+        y.c[c].y = fmaf(sn, fmaf(-ta, b.y, a.y), b.y);
+        y.c[c].z = fmaf(sn, fmaf(-ta, b.z, a.z), b.z);
+        y.c[c].w = fmaf(sn, fmaf(-ta, b.w, a.w), b.w);
+    }
+#pragma unroll
+    for (int i = 0; i < TL; ++i) rotate_values(x.t[i], y.t[i], sn, ta);
+    // Tracked norms; clamped at 0 (cancellation can only make a small norm
+    // inaccurate until the exact recomputation at the next sweep start).
+    nx = fmaxf(fmaf(-t, ga, nx), 0.f);
+    ny = fmaxf(fmaf(t, ga, ny), 0.f);
+    return true;
 }
 
 // Two independent rotations (disjoint rows) computed side by side so that
@@ -286,56 +340,59 @@ __device__ inline void apply_rotation(float4* x, float4* y, float s, float h) {
 // which leaves its rows and norms bit-for-bit unchanged.  Keeping the
 // updates free of divergent branches lets the rows stay in their
 // registers.
-template <int LPP, int NCH>
-__device__ inline void rotate_two(float4* x1, float4* y1, float& nx1, float& ny1, bool& f1, float4* x2, float4* y2,
-                                  float& nx2, float& ny2, bool& f2, float tol, float& s1, float& h1, float& s2,
-                                  float& h2) {
+template <int LPP, int NCH, int TL>
+__device__ inline void rotate_two(RowPart<NCH, TL>& x1, RowPart<NCH, TL>& y1, float& nx1, float& ny1, bool& f1,
+                                  RowPart<NCH, TL>& x2, RowPart<NCH, TL>& y2, float& nx2, float& ny2, bool& f2,
+                                  float tol, float& s1, float& h1, float& s2, float& h2) {
     s1 = h1 = s2 = h2 = 0.f;
     float p0 = 0.f, p1 = 0.f, q0 = 0.f, q1 = 0.f;
 #pragma unroll
     for (int c = 0; c < NCH; c += 2) {
-        p0 = dot4(x1[c], y1[c], p0);
-        q0 = dot4(x2[c], y2[c], q0);
+        p0 = dot4(x1.c[c], y1.c[c], p0);
+        q0 = dot4(x2.c[c], y2.c[c], q0);
     }
 #pragma unroll
     for (int c = 1; c < NCH; c += 2) {
-        p1 = dot4(x1[c], y1[c], p1);
-        q1 = dot4(x2[c], y2[c], q1);
+        p1 = dot4(x1.c[c], y1.c[c], p1);
+        q1 = dot4(x2.c[c], y2.c[c], q1);
+    }
+#pragma unroll
+    for (int i = 0; i < TL; ++i) {
+        p1 = fmaf(x1.t[i], y1.t[i], p1);
+        q1 = fmaf(x2.t[i], y2.t[i], q1);
     }
     const float g1 = group_sum<LPP>(p0 + p1);
     const float g2 = group_sum<LPP>(q0 + q1);
     f1 = needs_rotation(g1, nx1, ny1, tol);
     f2 = needs_rotation(g2, nx2, ny2, tol);
     if (!__any(f1 || f2)) return;
-    float t1, t2;
-    jacobi_rotation(nx1, ny1, f1 ? g1 : 1.0f, s1, h1, t1);
-    jacobi_rotation(nx2, ny2, f2 ? g2 : 1.0f, s2, h2, t2);
-    s1 = f1 ? s1 : 0.f;
-    h1 = f1 ? h1 : 0.f;
+    // both tangents are computed (a = b = 1 stand in for a pair that stays,
+    // whose own norms may both be 0) and the tangent of a pair that stays is
+    // replaced by 0: s = tau = 0 and its norms keep their values
+    float t1 = rotation_tangent(nx1, ny1, f1 ? g1 : 1.0f);
+    float t2 = rotation_tangent(nx2, ny2, f2 ? g2 : 1.0f);
     t1 = f1 ? t1 : 0.f;
-    s2 = f2 ? s2 : 0.f;
-    h2 = f2 ? h2 : 0.f;
     t2 = f2 ? t2 : 0.f;
-    apply_rotation<NCH>(x1, y1, s1, h1);
-    apply_rotation<NCH>(x2, y2, s2, h2);
-    nx1 = f1 ? fmaxf(fmaf(-t1, g1, nx1), 0.f) : nx1;
-    ny1 = f1 ? fmaxf(fmaf(t1, g1, ny1), 0.f) : ny1;
-    nx2 = f2 ? fmaxf(fmaf(-t2, g2, nx2), 0.f) : nx2;
-    ny2 = f2 ? fmaxf(fmaf(t2, g2, ny2), 0.f) : ny2;
+    rotation_sin_halftan(t1, s1, h1);
+    rotation_sin_halftan(t2, s2, h2);
+    apply_rotation<NCH, TL>(x1, y1, s1, h1);
+    apply_rotation<NCH, TL>(x2, y2, s2, h2);
+    nx1 = fmaxf(fmaf(-t1, g1, nx1), 0.f);
+    ny1 = fmaxf(fmaf(t1, g1, ny1), 0.f);
+    nx2 = fmaxf(fmaf(-t2, g2, nx2), 0.f);
+    ny2 = fmaxf(fmaf(t2, g2, ny2), 0.f);
 }
 
 // Squared norms of rows 0..nrows-1 of B into s2 (LDS).
-template <int LPP, int NCH>
+template <int LPP, int NCH, int TL>
 __device__ void row_norms(const float* B, int nrows, int ld, float* s2) {
     const int tid = threadIdx.x;
     const int g = tid / LPP, q = tid % LPP;
     constexpr int G = NT / LPP;
     for (int j = g; j < nrows; j += G) {
-        const float* pj = B + j * ld + 4 * q;
-        float4 x[NCH];
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) x[c] = *reinterpret_cast<const float4*>(pj + 4 * LPP * c);
-        const float v = group_dot<LPP, NCH>(x, x);
+        RowPart<NCH, TL> x;
+        load_row<LPP, NCH, TL>(B + j * ld, q, x);
+        const float v = group_dot<LPP, NCH, TL>(x, x);
         if (q == 0) s2[j] = v;
     }
     __syncthreads();
@@ -344,29 +401,20 @@ __device__ void row_norms(const float* B, int nrows, int ld, float* s2) {
 // Squared row norms during the sweeps: one LDS array for every variant.
 __shared__ float tilt_jacobi_nrm[SVT_MAX_ROWS];
 
-template <int LPP, int NCH>
-__device__ inline void load_row(const float* p, float4* x) {
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) x[c] = *reinterpret_cast<const float4*>(p + 4 * LPP * c);
-}
-
-template <int LPP, int NCH>
-__device__ inline void store_row(float* p, const float4* x) {
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) *reinterpret_cast<float4*>(p + 4 * LPP * c) = x[c];
-}
-
 // One round of the circle ordering: every lane group takes block pairs
 // k = g, g + G, ... of round r.  FIRST (round 0 of a sweep) also rotates
 // the pairs inside each block of two rows; it is a separate instance so the
 // other rounds carry no conditional stage.
-template <int BS, int LPP, int NCH, bool WARM, bool FIRST>
+template <int BS, int LPP, int NCH, int TL, bool WARM, bool FIRST>
 __device__ inline void jacobi_round(float* B, float* Rm, float* nrm, int ld, int r, int Nb, int Pb, int g, int q,
                                     float tol, int& any, long long& rots) {
     constexpr int G = NT / LPP;
     // WARM: the rotation rows of the block pair (same layout as the Jacobi
     // rows) stay in registers for the round and take the same rotations.
     constexpr int RN = WARM ? NCH : 1;
+    constexpr int RT = WARM ? TL : 0;
+    using Row = RowPart<NCH, TL>;
+    using RRow = RowPart<RN, RT>;
     for (int k = g; k < Pb; k += G) {
         int I, J;
         if (k == 0) {
@@ -378,31 +426,31 @@ __device__ inline void jacobi_round(float* B, float* Rm, float* nrm, int ld, int
             J = r - k;
             if (J < 0) J += Nb;
         }
-        float* pa = B + (BS * I) * ld + 4 * q;
-        float* pb = B + (BS * J) * ld + 4 * q;
+        float* pa = B + (BS * I) * ld;
+        float* pb = B + (BS * J) * ld;
         if (BS == 1) {
-            float4 a1[NCH], b1[NCH];
-            float4 ra[RN], rb[RN];
-            load_row<LPP, NCH>(pa, a1);
-            load_row<LPP, NCH>(pb, b1);
-            float* qa = WARM ? Rm + I * ld + 4 * q : nullptr;
-            float* qb = WARM ? Rm + J * ld + 4 * q : nullptr;
+            Row a1, b1;
+            RRow ra, rb;
+            load_row<LPP, NCH, TL>(pa, q, a1);
+            load_row<LPP, NCH, TL>(pb, q, b1);
+            float* qa = WARM ? Rm + I * ld : nullptr;
+            float* qb = WARM ? Rm + J * ld : nullptr;
             if (WARM) {
-                load_row<LPP, RN>(qa, ra);
-                load_row<LPP, RN>(qb, rb);
+                load_row<LPP, RN, RT>(qa, q, ra);
+                load_row<LPP, RN, RT>(qb, q, rb);
             }
             float na1 = nrm[I], nb1 = nrm[J];
             float sr, hr;
-            const bool f = rotate_rows<LPP, NCH>(a1, b1, na1, nb1, tol, sr, hr);
-            if (WARM && __any(f)) apply_rotation<RN>(ra, rb, sr, hr);
+            const bool f = rotate_rows<LPP, NCH, TL>(a1, b1, na1, nb1, tol, sr, hr);
+            if (WARM && __any(f)) apply_rotation<RN, RT>(ra, rb, sr, hr);
             if (f) {
                 any = 1;
                 rots += 1;
-                store_row<LPP, NCH>(pa, a1);
-                store_row<LPP, NCH>(pb, b1);
+                store_row<LPP, NCH, TL>(pa, q, a1);
+                store_row<LPP, NCH, TL>(pb, q, b1);
                 if (WARM) {
-                    store_row<LPP, RN>(qa, ra);
-                    store_row<LPP, RN>(qb, rb);
+                    store_row<LPP, RN, RT>(qa, q, ra);
+                    store_row<LPP, RN, RT>(qb, q, rb);
                 }
                 if (q == 0) {
                     nrm[I] = na1;
@@ -410,53 +458,53 @@ __device__ inline void jacobi_round(float* B, float* Rm, float* nrm, int ld, int
                 }
             }
         } else {
-            float4 a1[NCH], a2[NCH], b1[NCH], b2[NCH];
-            float4 ra1[RN], ra2[RN], rb1[RN], rb2[RN];
-            load_row<LPP, NCH>(pa, a1);
-            load_row<LPP, NCH>(pa + ld, a2);
-            load_row<LPP, NCH>(pb, b1);
-            load_row<LPP, NCH>(pb + ld, b2);
-            float* qa = WARM ? Rm + (BS * I) * ld + 4 * q : nullptr;
-            float* qb = WARM ? Rm + (BS * J) * ld + 4 * q : nullptr;
+            Row a1, a2, b1, b2;
+            RRow ra1, ra2, rb1, rb2;
+            load_row<LPP, NCH, TL>(pa, q, a1);
+            load_row<LPP, NCH, TL>(pa + ld, q, a2);
+            load_row<LPP, NCH, TL>(pb, q, b1);
+            load_row<LPP, NCH, TL>(pb + ld, q, b2);
+            float* qa = WARM ? Rm + (BS * I) * ld : nullptr;
+            float* qb = WARM ? Rm + (BS * J) * ld : nullptr;
             if (WARM) {
-                load_row<LPP, RN>(qa, ra1);
-                load_row<LPP, RN>(qa + ld, ra2);
-                load_row<LPP, RN>(qb, rb1);
-                load_row<LPP, RN>(qb + ld, rb2);
+                load_row<LPP, RN, RT>(qa, q, ra1);
+                load_row<LPP, RN, RT>(qa + ld, q, ra2);
+                load_row<LPP, RN, RT>(qb, q, rb1);
+                load_row<LPP, RN, RT>(qb + ld, q, rb2);
             }
             float na1 = nrm[2 * I], na2 = nrm[2 * I + 1], nb1 = nrm[2 * J], nb2 = nrm[2 * J + 1];
             bool d0 = false, d1 = false, d2 = false, d3 = false, f, h;
             float s1, h1, s2, h2;
             if (FIRST) {
-                rotate_two<LPP, NCH>(a1, a2, na1, na2, f, b1, b2, nb1, nb2, h, tol, s1, h1, s2, h2);
+                rotate_two<LPP, NCH, TL>(a1, a2, na1, na2, f, b1, b2, nb1, nb2, h, tol, s1, h1, s2, h2);
                 if (WARM && __any(f || h)) {
-                    apply_rotation<RN>(ra1, ra2, s1, h1);
-                    apply_rotation<RN>(rb1, rb2, s2, h2);
+                    apply_rotation<RN, RT>(ra1, ra2, s1, h1);
+                    apply_rotation<RN, RT>(rb1, rb2, s2, h2);
                 }
                 d0 |= f; d1 |= f; d2 |= h; d3 |= h; rots += f; rots += h;
             }
-            rotate_two<LPP, NCH>(a1, b1, na1, nb1, f, a2, b2, na2, nb2, h, tol, s1, h1, s2, h2);
+            rotate_two<LPP, NCH, TL>(a1, b1, na1, nb1, f, a2, b2, na2, nb2, h, tol, s1, h1, s2, h2);
             if (WARM && __any(f || h)) {
-                apply_rotation<RN>(ra1, rb1, s1, h1);
-                apply_rotation<RN>(ra2, rb2, s2, h2);
+                apply_rotation<RN, RT>(ra1, rb1, s1, h1);
+                apply_rotation<RN, RT>(ra2, rb2, s2, h2);
             }
             d0 |= f; d2 |= f; d1 |= h; d3 |= h; rots += f; rots += h;
-            rotate_two<LPP, NCH>(a1, b2, na1, nb2, f, a2, b1, na2, nb1, h, tol, s1, h1, s2, h2);
+            rotate_two<LPP, NCH, TL>(a1, b2, na1, nb2, f, a2, b1, na2, nb1, h, tol, s1, h1, s2, h2);
             if (WARM && __any(f || h)) {
-                apply_rotation<RN>(ra1, rb2, s1, h1);
-                apply_rotation<RN>(ra2, rb1, s2, h2);
+                apply_rotation<RN, RT>(ra1, rb2, s1, h1);
+                apply_rotation<RN, RT>(ra2, rb1, s2, h2);
             }
             d0 |= f; d3 |= f; d1 |= h; d2 |= h; rots += f; rots += h;
             if (d0 | d1 | d2 | d3) any = 1;
-            if (d0) store_row<LPP, NCH>(pa, a1);
-            if (d1) store_row<LPP, NCH>(pa + ld, a2);
-            if (d2) store_row<LPP, NCH>(pb, b1);
-            if (d3) store_row<LPP, NCH>(pb + ld, b2);
+            if (d0) store_row<LPP, NCH, TL>(pa, q, a1);
+            if (d1) store_row<LPP, NCH, TL>(pa + ld, q, a2);
+            if (d2) store_row<LPP, NCH, TL>(pb, q, b1);
+            if (d3) store_row<LPP, NCH, TL>(pb + ld, q, b2);
             if (WARM) {
-                if (d0) store_row<LPP, RN>(qa, ra1);
-                if (d1) store_row<LPP, RN>(qa + ld, ra2);
-                if (d2) store_row<LPP, RN>(qb, rb1);
-                if (d3) store_row<LPP, RN>(qb + ld, rb2);
+                if (d0) store_row<LPP, RN, RT>(qa, q, ra1);
+                if (d1) store_row<LPP, RN, RT>(qa + ld, q, ra2);
+                if (d2) store_row<LPP, RN, RT>(qb, q, rb1);
+                if (d3) store_row<LPP, RN, RT>(qb + ld, q, rb2);
             }
             if (q == 0) {
                 nrm[2 * I] = na1;
@@ -471,7 +519,7 @@ __device__ inline void jacobi_round(float* B, float* Rm, float* nrm, int ld, int
 // Returns 1 (uniform over the workgroup) if any pair was rotated.  WARM:
 // every rotation is also applied to the rows of Rm (same layout), which
 // accumulates the product of the rotations.
-template <int BS, int LPP, int NCH, bool WARM>
+template <int BS, int LPP, int NCH, int TL, bool WARM>
 __device__ int jacobi_rows(float* B, float* Rm, int nc, int ld, float tol, int max_sweeps, JacobiStats& js) {
     float* nrm = tilt_jacobi_nrm;
     const int tid = threadIdx.x;
@@ -482,12 +530,12 @@ __device__ int jacobi_rows(float* B, float* Rm, int nc, int ld, float tol, int m
     long long rots = 0;
     int sweeps = 0, rotated = 0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
-        row_norms<LPP, NCH>(B, nc4, ld, nrm);
+        row_norms<LPP, NCH, TL>(B, nc4, ld, nrm);
         int any = 0;
-        jacobi_round<BS, LPP, NCH, WARM, true>(B, Rm, nrm, ld, 0, Nb, Pb, g, q, tol, any, rots);
+        jacobi_round<BS, LPP, NCH, TL, WARM, true>(B, Rm, nrm, ld, 0, Nb, Pb, g, q, tol, any, rots);
         __syncthreads();
         for (int r = 1; r < Nb; ++r) {
-            jacobi_round<BS, LPP, NCH, WARM, false>(B, Rm, nrm, ld, r, Nb, Pb, g, q, tol, any, rots);
+            jacobi_round<BS, LPP, NCH, TL, WARM, false>(B, Rm, nrm, ld, r, Nb, Pb, g, q, tol, any, rots);
             __syncthreads();
         }
         ++sweeps;
@@ -502,29 +550,36 @@ __device__ int jacobi_rows(float* B, float* Rm, int nc, int ld, float tol, int m
     return rotated;
 }
 
-template <int BS, int LPP, int NCH, bool WARM>
+template <int BS, int LPP, int NCH, int TL, bool WARM>
 __device__ void jacobi_svd_rows(float* B, float* Rm, int nc, int ld, float tol, int max_sweeps, JacobiStats& js,
                                 float* s2) {
-    jacobi_rows<BS, LPP, NCH, WARM>(B, Rm, nc, ld, tol, max_sweeps, js);
-    row_norms<LPP, NCH>(B, nc, ld, s2);
+    jacobi_rows<BS, LPP, NCH, TL, WARM>(B, Rm, nc, ld, tol, max_sweeps, js);
+    row_norms<LPP, NCH, TL>(B, nc, ld, s2);
 }
 
-// Layout codes from svt_make_cfg(BS, LPP, NCH).
-#define TILT_SVT_CASE(S, L, C)                                                            \
-    case svt_make_cfg(S, L, C):                  \
-        jacobi_svd_rows<S, L, C, false>(B, nullptr, nc, ld, tol, max_sweeps, js, s2);       \
+// Layout codes from svt_make_cfg(BS, LPP, NCH, TL).
+#define TILT_SVT_CASE_T(S, L, C, T)                                                       \
+    case svt_make_cfg(S, L, C, T):                                                        \
+        jacobi_svd_rows<S, L, C, T, false>(B, nullptr, nc, ld, tol, max_sweeps, js, s2);  \
         break;
+#define TILT_SVT_CASE(S, L, C) TILT_SVT_CASE_T(S, L, C, 0)
 #define TILT_SVT_CASES8(S, L)                                                              \
     TILT_SVT_CASE(S, L, 1) TILT_SVT_CASE(S, L, 2) TILT_SVT_CASE(S, L, 3) TILT_SVT_CASE(S, L, 4) \
     TILT_SVT_CASE(S, L, 5) TILT_SVT_CASE(S, L, 6) TILT_SVT_CASE(S, L, 7) TILT_SVT_CASE(S, L, 8)
 #define TILT_SVT_CASES4(S, L) \
     TILT_SVT_CASE(S, L, 1) TILT_SVT_CASE(S, L, 2) TILT_SVT_CASE(S, L, 3) TILT_SVT_CASE(S, L, 4)
+// Two-row blocks of 8 or 16 lanes with 1-3 chunks and 1 or 2 single floats
+// per lane (the layouts the host offers for the one-workgroup SVT).
+#define TILT_SVT_TAILS(S, L)                                                                      \
+    TILT_SVT_CASE_T(S, L, 1, 1) TILT_SVT_CASE_T(S, L, 2, 1) TILT_SVT_CASE_T(S, L, 3, 1)           \
+    TILT_SVT_CASE_T(S, L, 1, 2) TILT_SVT_CASE_T(S, L, 2, 2) TILT_SVT_CASE_T(S, L, 3, 2)
 
 __device__ void jacobi_dispatch(int cfg, float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js,
                                 float* s2) {
     switch (cfg) {
         TILT_SVT_CASES8(1, 4) TILT_SVT_CASES8(1, 8) TILT_SVT_CASES8(1, 16)
         TILT_SVT_CASES4(2, 4) TILT_SVT_CASES4(2, 8) TILT_SVT_CASES4(2, 16)
+        TILT_SVT_TAILS(2, 8) TILT_SVT_TAILS(2, 16)
         // rows longer than 512: the layouts the cost model may choose there
         TILT_SVT_CASE(1, 32, 5) TILT_SVT_CASE(1, 32, 6) TILT_SVT_CASE(1, 32, 7) TILT_SVT_CASE(1, 32, 8)
         TILT_SVT_CASE(1, 64, 3) TILT_SVT_CASE(1, 64, 4) TILT_SVT_CASE(1, 64, 5) TILT_SVT_CASE(1, 64, 6)
@@ -536,32 +591,42 @@ __device__ void jacobi_dispatch(int cfg, float* B, int nc, int ld, float tol, in
 
 // Warm variants (rotation rows Rm in LDS, same layout as B): chunks per
 // lane up to 4.
-#define TILT_WARM_CASE(S, L, C)                                                           \
-    case svt_make_cfg(S, L, C):                  \
-        jacobi_svd_rows<S, L, C, true>(B, Rm, nc, ld, tol, max_sweeps, js, s2);             \
+#define TILT_WARM_CASE_T(S, L, C, T)                                                      \
+    case svt_make_cfg(S, L, C, T):                                                        \
+        jacobi_svd_rows<S, L, C, T, true>(B, Rm, nc, ld, tol, max_sweeps, js, s2);        \
         break;
+#define TILT_WARM_CASE(S, L, C) TILT_WARM_CASE_T(S, L, C, 0)
 #define TILT_WARM_CASES4(S, L) \
     TILT_WARM_CASE(S, L, 1) TILT_WARM_CASE(S, L, 2) TILT_WARM_CASE(S, L, 3) TILT_WARM_CASE(S, L, 4)
+#define TILT_WARM_TAILS(S, L)                                                                       \
+    TILT_WARM_CASE_T(S, L, 1, 1) TILT_WARM_CASE_T(S, L, 2, 1) TILT_WARM_CASE_T(S, L, 3, 1)          \
+    TILT_WARM_CASE_T(S, L, 1, 2) TILT_WARM_CASE_T(S, L, 2, 2) TILT_WARM_CASE_T(S, L, 3, 2)
 
 __device__ void jacobi_dispatch_warm(int cfg, float* B, float* Rm, int nc, int ld, float tol, int max_sweeps,
                                      JacobiStats& js, float* s2) {
     switch (cfg) {
         TILT_WARM_CASES4(1, 4) TILT_WARM_CASES4(1, 8) TILT_WARM_CASES4(1, 16)
         TILT_WARM_CASES4(2, 4) TILT_WARM_CASES4(2, 8) TILT_WARM_CASES4(2, 16)
+        TILT_WARM_TAILS(2, 8) TILT_WARM_TAILS(2, 16)
         default:
             break;
     }
 }
+#undef TILT_WARM_TAILS
 #undef TILT_WARM_CASES4
 #undef TILT_WARM_CASE
+#undef TILT_WARM_CASE_T
+#undef TILT_SVT_TAILS
 #undef TILT_SVT_CASES4
 #undef TILT_SVT_CASES8
 #undef TILT_SVT_CASE
+#undef TILT_SVT_CASE_T
 
 // One sweep over all pairs of the nrows rows of B (LDS); 1 if any rotated.
+// The tiled paths use layouts without single floats.
 #define TILT_SWEEP_CASE(S, L, C)                                                          \
     case svt_make_cfg(S, L, C):                  \
-        return jacobi_rows<S, L, C, false>(B, nullptr, nrows, ld, tol, 1, js);
+        return jacobi_rows<S, L, C, 0, false>(B, nullptr, nrows, ld, tol, 1, js);
 #define TILT_SWEEP_CASES8(S, L)                                                                    \
     TILT_SWEEP_CASE(S, L, 1) TILT_SWEEP_CASE(S, L, 2) TILT_SWEEP_CASE(S, L, 3) TILT_SWEEP_CASE(S, L, 4) \
     TILT_SWEEP_CASE(S, L, 5) TILT_SWEEP_CASE(S, L, 6) TILT_SWEEP_CASE(S, L, 7) TILT_SWEEP_CASE(S, L, 8)
