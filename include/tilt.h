@@ -277,8 +277,10 @@ int tilt_inner_batch(tilt_ctx* ctx, const float* I, const float* J, int count, i
 
 /* ------------------------------------------------------------------------
  * Jacobi layout tuning.  The layout of the LDS-resident Jacobi (rows per
- * block, lanes per row pair; the float4 chunks per lane follow from the row
- * length) is chosen by a cost model unless a measured entry applies: a
+ * block, lanes per row pair; the float4 chunks per lane, and for two-row
+ * blocks of 8 or 16 lanes up to 2 single floats per lane that stand in for
+ * a mostly empty last chunk, follow from the row length) is chosen by a
+ * cost model unless a measured entry applies: a
  * window whose min(m,n) and max(m,n) are both within a factor 1.5 of a
  * tuned shape uses the layout measured for the nearest one (if valid for
  * its row length).  The table is process-wide; calls are thread-safe and
@@ -292,6 +294,13 @@ int tilt_svt_layouts(int m, int n, int* bs, int* lpp, int max_count);
 int tilt_tune_set(int m, int n, int bs, int lpp);
 /* Forget all measured layouts (back to the cost model). */
 int tilt_tune_clear(void);
+/* The layout an m x n window's SVT runs with, as planned now (table and
+ * cost model): out[0..4] = rows per block, lanes per pair, float4 chunks
+ * per lane, single floats per lane, and 1 if the matrix is tiled through
+ * device memory (then out[0..3] describe the staged super-block pair).
+ * Host-only, no device work.  TILT_ERR_ARG for a null out or m, n < 1;
+ * TILT_ERR_TOO_LARGE if no SVT plan exists for the shape. */
+int tilt_svt_layout(int m, int n, int* out);
 
 /* Pyramid levels 1..levels-1 of one image (DEVICE pointers), as used when
  * pyramid_levels = levels: level l (ceil(H/2^l) x ceil(W/2^l), row-major,

@@ -1387,6 +1387,19 @@ int tilt_svt_layouts(int m, int n, int* bs, int* lpp, int max_count) {
     return k;
 }
 
+int tilt_svt_layout(int m, int n, int* out) {
+    if (m < 1 || n < 1 || !out) return TILT_ERR_ARG;
+    ShapeCfg sc{};
+    const int rc = shape_config(m, n, &sc);
+    if (rc != TILT_OK) return rc;
+    out[0] = svt_bs(sc.cfg);
+    out[1] = svt_lpp(sc.cfg);
+    out[2] = svt_nch(sc.cfg);
+    out[3] = svt_tl(sc.cfg);
+    out[4] = sc.sb > 0 ? 1 : 0;
+    return TILT_OK;
+}
+
 int tilt_tune_set(int m, int n, int bs, int lpp) {
     if (m < 1 || n < 1 || (bs != 1 && bs != 2) || (lpp != 4 && lpp != 8 && lpp != 16)) return TILT_ERR_ARG;
     const int nc = std::min(m, n), nr = std::max(m, n);

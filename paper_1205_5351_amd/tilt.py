@@ -202,6 +202,8 @@ _lib.tilt_svt_layouts.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTE
 _lib.tilt_svt_layouts.restype = C.c_int
 _lib.tilt_tune_set.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
 _lib.tilt_tune_set.restype = C.c_int
+_lib.tilt_svt_layout.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int)]
+_lib.tilt_svt_layout.restype = C.c_int
 _lib.tilt_tune_clear.argtypes = []
 _lib.tilt_tune_clear.restype = C.c_int
 _lib.tilt_rasl_solve_batch.argtypes = [C.c_void_p, C.POINTER(RaslProblem), C.c_int, C.POINTER(Params),
@@ -213,7 +215,8 @@ EXPORTS = [
     "tilt_ctx_create", "tilt_ctx_destroy", "tilt_workspace_bytes", "tilt_solve_batch",
     "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_warp_jacobian", "tilt_last_error",
     "tilt_ctx_last_kernel_ms", "tilt_submit", "tilt_poll", "tilt_serve_stop", "tilt_pyramid",
-    "tilt_inner_batch", "tilt_svt_layouts", "tilt_tune_set", "tilt_tune_clear", "tilt_rasl_solve_batch",
+    "tilt_inner_batch", "tilt_svt_layouts", "tilt_svt_layout", "tilt_tune_set", "tilt_tune_clear",
+    "tilt_rasl_solve_batch",
 ]
 
 
@@ -227,6 +230,16 @@ def svt_layouts(m: int, n: int):
     lpp = (C.c_int * 8)()
     k = _lib.tilt_svt_layouts(int(m), int(n), bs, lpp, 8)
     return [(bs[i], lpp[i]) for i in range(min(k, 8))]
+
+
+def svt_layout(m: int, n: int):
+    """Layout the SVT of an m x n window runs with now: (rows per block,
+    lanes per pair, float4 chunks per lane, single floats per lane, tiled)."""
+    out = (C.c_int * 5)()
+    rc = _lib.tilt_svt_layout(int(m), int(n), out)
+    if rc != TILT_OK:
+        raise TiltError(rc, "tilt_svt_layout")
+    return tuple(out[i] for i in range(5))
 
 
 def tune_set(m: int, n: int, bs: int, lpp: int):

@@ -21,6 +21,7 @@ import pytest
 import oracle as O
 import tilt_synth as ts
 from gpu_util import device_problems, oracle_params, same_numerical_rank, solve_on_device, to_device
+from svt_layouts import TAIL_LAYOUTS
 
 pytestmark = pytest.mark.gpu
 
@@ -518,3 +519,56 @@ def test_plain_path_graph_replays_equal_eager(tilt, ctx, device):
     _, g2 = solve_on_device(tilt, ctx, pyr, device, tq, plain=True)
     _, f2 = solve_on_device(tilt, ctx, pyr, device, tq)
     assert _same(g2[0], f2[0])
+
+
+@pytest.mark.parametrize("lpp,nch,tl,nr", TAIL_LAYOUTS)
+def test_svt_single_float_tail_layouts_match_oracle(tilt, ctx, device, lpp, nch, tl, nr):
+    """Every layout with single floats per lane (cold SVT) gives the oracle's
+    SVT, on 22 rows (two zero rows pad them to whole blocks)."""
+    import torch
+
+    m = 22
+    rng = np.random.default_rng(1000 * lpp + nr)
+    L = rng.standard_normal((m, 4)) @ rng.standard_normal((4, nr))
+    M = (L / np.linalg.norm(L) + 0.05 * rng.standard_normal((m, nr)) / math.sqrt(m * nr)).astype(np.float32)
+    dM = to_device(np.stack([M, M.copy()]), device)
+    eps = np.array([0.005, 0.02], np.float32)
+    try:
+        tilt.tune_set(m, nr, 2, lpp)
+        assert tilt.svt_layout(m, nr) == (2, lpp, nch, tl, 0)
+        dA = torch.zeros_like(dM)
+        ctx.svt_batch(dM.data_ptr(), dA.data_ptr(), 0, 2, m, nr, eps)
+        A = dA.cpu().numpy()
+    finally:
+        tilt.tune_clear()
+        import os
+        if os.path.exists(tilt.TUNING_TABLE):
+            tilt.load_tuning(tilt.TUNING_TABLE)
+    for i in range(2):
+        Aref, _ = O.svt(M.astype(np.float64), float(eps[i]))
+        assert np.linalg.norm(A[i] - Aref) <= 1e-5 * np.linalg.norm(Aref), (lpp, nch, tl, i)
+
+
+@pytest.mark.parametrize("lpp,nch,tl,nr", TAIL_LAYOUTS)
+def test_warm_svt_single_float_tail_layouts_match_oracle(tilt, ctx, device, lpp, nch, tl, nr):
+    """The warm SVT (rotation rows in the same layout) with single floats
+    per lane: a fixed-iteration solve of a 22 x nr window against the
+    oracle."""
+    m = 22
+    p = ts.make_patch(ts.patch_rng(9, 17 * lpp + nr), m=m, n=nr, height=m + 40, width=nr + 40, rank=3,
+                      model=O.PROJECTIVE, corruption=0.1)
+    tp = tilt.default_params(fixed_iters=1, max_outer=2, max_inner=8, lam=p.lam, svt_mode=1)
+    try:
+        tilt.tune_set(m, nr, 2, lpp)
+        assert tilt.svt_layout(m, nr) == (2, lpp, nch, tl, 0)
+        _, res = solve_on_device(tilt, ctx, [p], device, tp)
+    finally:
+        tilt.tune_clear()
+        import os
+        if os.path.exists(tilt.TUNING_TABLE):
+            tilt.load_tuning(tilt.TUNING_TABLE)
+    r = res[0]
+    assert r["status"] == 0, r
+    ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
+    assert np.linalg.norm(r["A"] - ref.A) <= 1e-4 * np.linalg.norm(ref.A)
+    assert O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n) <= 1e-5

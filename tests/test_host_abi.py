@@ -124,3 +124,39 @@ def test_product_path_never_touches_the_oracle():
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src, f
                 assert "tilt_oracle" not in src, f
+
+
+def _restore_tuning(tilt):
+    tilt.tune_clear()
+    if os.path.exists(tilt.TUNING_TABLE):
+        tilt.load_tuning(tilt.TUNING_TABLE)
+
+
+def test_svt_layout_single_float_tails(tilt):
+    """Two-row blocks of 8 or 16 lanes hold a remainder of at most 2 floats
+    per lane as single floats; other layouts, longer remainders and the
+    tiled path use whole chunks."""
+    from svt_layouts import TAIL_LAYOUTS
+
+    m = 22
+    try:
+        for lpp, nch, tl, nr in TAIL_LAYOUTS:
+            tilt.tune_set(m, nr, 2, lpp)
+            assert tilt.svt_layout(m, nr) == (2, lpp, nch, tl, 0), (lpp, nr)
+            assert tilt.svt_layout(nr, m) == (2, lpp, nch, tl, 0), (lpp, nr)  # rows are min(m, n)
+        tilt.tune_set(m, 128, 2, 8)
+        assert tilt.svt_layout(m, 128) == (2, 8, 4, 0, 0)            # whole chunks: no tail
+        tilt.tune_set(m, 120, 2, 8)
+        assert tilt.svt_layout(m, 120) == (2, 8, 4, 0, 0)            # remainder of 3 floats per lane
+        tilt.tune_set(m, 99, 1, 8)
+        assert tilt.svt_layout(m, 99) == (1, 8, 4, 0, 0)             # one-row blocks: whole chunks
+        tilt.tune_set(m, 35, 2, 4)
+        assert tilt.svt_layout(m, 35) == (2, 4, 3, 0, 0)             # 4-lane groups: whole chunks
+    finally:
+        _restore_tuning(tilt)
+    bs, lpp, nch, tl, tiled = tilt.svt_layout(600, 600)              # beyond LDS: tiled, whole chunks
+    assert tiled == 1 and tl == 0
+    with pytest.raises(tilt.TiltError):
+        tilt.svt_layout(20, 2100)                                   # rows longer than 2048 floats
+    with pytest.raises(tilt.TiltError):
+        tilt.svt_layout(0, 10)
