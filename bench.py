@@ -29,6 +29,13 @@ if ROOT not in sys.path:
 
 METRIC = "rectified patches/s at τ rel err≤1e-4 vs plain GPU path; p50/p99 latency"
 PEAK_FP32_VECTOR_TFLOPS = 157.3
+# MI355X published peaks used for the machine-peak study (256 CUs at 2.4 GHz;
+# LDS 256 bytes per clock per CU)
+NOMINAL_PEAKS = {"hbm_copy": (8000.0, "GB/s"), "lds_read": (157.3, "TB/s"),
+                 "fp32_fma": (157.3, "TFLOP/s"), "fp32_mfma": (157.3, "TFLOP/s")}
+# probe kind, work unit scale, iterations (each probe launch lasts ~10-50 ms)
+PEAK_PROBES = {"hbm_copy": (0, 1e9, 1), "lds_read": (1, 1e12, 20000), "fp32_fma": (2, 1e12, 100000),
+               "fp32_mfma": (3, 1e12, 40000)}
 
 
 def log(msg):
@@ -50,6 +57,46 @@ def tau_rel_err(Ha, Hb, tau0, m, n):
 
     a, b = nrm(np.asarray(Ha)), nrm(np.asarray(Hb))
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def measure_peak(T, torch, name, reps=5, nbytes=1 << 30):
+    """Best rate of `reps` launches of one machine-peak probe kernel
+    (tilt_peak_probe), in the unit of NOMINAL_PEAKS[name]."""
+    kind, scale, iters = PEAK_PROBES[name]
+    dev = torch.device("cuda:0")
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev) if kind == 0 else None
+    dst = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    best = 0.0
+    for _ in range(reps):
+        ms, work = T.peak_probe(kind, src.data_ptr() if src is not None else 0, dst.data_ptr(), nbytes, iters)
+        best = max(best, work / (ms * 1e-3) / scale)
+    del src, dst
+    return best
+
+
+def peaks_main(args):
+    """Machine peaks measured with the solver's compiler flags: HBM stream
+    copy, LDS 16-byte reads consumed by one VALU operation per word, FP32
+    vector FMA (no packed FP32 in this build) and FP32 MFMA 16x16x4; each
+    against MI355X's published figure."""
+    import torch
+
+    import paper_1205_5351_amd as T
+
+    measured = {}
+    for name in PEAK_PROBES:
+        nbytes = (2 << 30) if name == "hbm_copy" else (1 << 30)
+        measured[name] = measure_peak(T, torch, name, nbytes=nbytes)
+        log(f"{name}: {measured[name]:.1f} {NOMINAL_PEAKS[name][1]}")
+    out = {
+        "metric": "machine peaks measured by probe kernels (best of 5 launches)",
+        "value": round(measured["fp32_fma"], 2), "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": 5, "warmup": 0, "higher_is_better": True, "data": "synthetic",
+        "config": {"workload": "peak-probes", "hbm_copy_bytes": 2 << 30, "grid": "8 workgroups of 256 per CU"},
+        "peaks": {k: {"measured": round(v, 2), "nominal": NOMINAL_PEAKS[k][0], "unit": NOMINAL_PEAKS[k][1],
+                      "frac_of_nominal": round(v / NOMINAL_PEAKS[k][0], 4)} for k, v in measured.items()},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def solve_flops(res, p, warm=False):
@@ -170,6 +217,9 @@ def main():
                          "matrix), one fused launch; sets/s, images/s, latency, roofline, CPU oracle on a sample")
     ap.add_argument("--rasl-sets", type=int, default=256)
     ap.add_argument("--rasl-max-outer", type=int, default=10)
+    ap.add_argument("--peaks", action="store_true",
+                    help="machine peaks from probe kernels built like the solver: HBM copy, LDS reads, FP32 FMA, "
+                         "FP32 MFMA, each against MI355X's published figure")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the solve, copy a buffer of this many MiB on the device (a plain copy of "
                          "known size, used to calibrate HBM byte counters in profiles)")
@@ -195,6 +245,8 @@ def main():
         return rasl_main(args)
     if args.precision:
         return precision_main(args)
+    if args.peaks:
+        return peaks_main(args)
     if args.components:
         return components_main(args)
     if args.convergence:
@@ -266,6 +318,9 @@ def main():
     done_ms = np.array([r["done_ms"] for r in res])
 
     flops = sum(solve_flops(r, p, warm=args.svt_mode == 1) for r, p in zip(res, patches))
+    # attainable FP32 vector rate of this build (no packed FP32), measured
+    # after the timed region by a probe kernel of a few ms
+    fma_peak = measure_peak(T, torch, "fp32_fma", reps=3, nbytes=8 << 20)
     k_ms = float(np.mean(kernel_ms))
     achieved = flops / (k_ms * 1e-3) / 1e12
     outer = np.array([r["outer_iters"] for r in res])
@@ -342,6 +397,8 @@ def main():
                         and args.pyramid == 1 and args.patches in (None, 256) else None),
             "kernel_ms": round(k_ms, 2),
             "flops_per_launch": flops,
+            "peak_measured": round(fma_peak, 2),
+            "frac_of_measured": round(achieved / fma_peak, 4),
         },
         "cpu_baseline": cpu,
     }
@@ -746,12 +803,14 @@ def rasl_main(args):
         flops += (2.0 * nr * c["jacobi_pairs"] + 6.0 * nr * c["jacobi_rotations"] + 4.0 * nc * nr * c["recon_rows"]
                   + (20.0 + 8.0 * sets[0].model) * nc * nr * c["inner_iters"])
     achieved = flops / (kernel_ms * 1e-3) / 1e12
+    fma_peak = measure_peak(T, torch, "fp32_fma", reps=3, nbytes=8 << 20)
     roofline = {"kernel": "k_rasl (whole RASL solves, one workgroup per set)", "bound": "alu",
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
                 "traffic": (profiled_traffic("k_rasl_rasl256x32x16x24.md", ("tilt_kernels.hip", "tilt_rasl.inc"))
                             if nsets == 256 and args.rasl_max_outer == 10 else None),
-                "kernel_ms": round(kernel_ms, 2), "flops_per_launch": flops}
+                "kernel_ms": round(kernel_ms, 2), "flops_per_launch": flops,
+                "peak_measured": round(fma_peak, 2), "frac_of_measured": round(achieved / fma_peak, 4)}
     cpu = None
     if not args.no_cpu:
         import multiprocessing as mp

@@ -302,6 +302,27 @@ int tilt_tune_clear(void);
  * TILT_ERR_TOO_LARGE if no SVT plan exists for the shape. */
 int tilt_svt_layout(int m, int n, int* out);
 
+/* ------------------------------------------------------------------------
+ * Machine peaks for the rooflines (not part of the method): one probe
+ * kernel, built with the solver's compiler flags, runs on the stream and
+ * *ms_out receives its duration (HIP events), *work_out the work it did.
+ *   kind 0: HBM stream copy of `bytes` (rounded down to 16) from src to dst
+ *           (DEVICE buffers of at least `bytes` each); work = bytes read +
+ *           written.
+ *   kind 1: LDS 16-byte reads (consecutive lanes, no bank conflicts), iters
+ *           x 8 per thread; work = LDS bytes read.
+ *   kind 2: FP32 vector FMA (8 independent chains per lane, iters steps);
+ *           work = flops.
+ *   kind 3: FP32 matrix-core MFMA 16x16x4 (4 accumulators per wavefront,
+ *           iters steps); work = flops.
+ * Kinds 1-3 run 8 workgroups of 256 threads per compute unit and write one
+ * 4-byte word per thread to dst, which must hold `bytes` >= that many
+ * words; src is unused.  Synchronous.  TILT_ERR_ARG for a bad kind, null
+ * pointers, iters < 1 (kinds 1-3) or a dst too small.
+ * ---------------------------------------------------------------------- */
+int tilt_peak_probe(int kind, const void* src, void* dst, size_t bytes, int iters, double* ms_out,
+                    double* work_out, void* hip_stream);
+
 /* Pyramid levels 1..levels-1 of one image (DEVICE pointers), as used when
  * pyramid_levels = levels: level l (ceil(H/2^l) x ceil(W/2^l), row-major,
  * contiguous) follows level l-1 in `out`.  levels in 2..4. */

@@ -23,6 +23,7 @@ from .tilt import (  # noqa: F401
     EXPORTS,
     LIB_PATH,
     load_tuning,
+    peak_probe,
     svt_layout,
     svt_layouts,
     tune_clear,

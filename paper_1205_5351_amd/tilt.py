@@ -204,6 +204,9 @@ _lib.tilt_tune_set.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
 _lib.tilt_tune_set.restype = C.c_int
 _lib.tilt_svt_layout.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int)]
 _lib.tilt_svt_layout.restype = C.c_int
+_lib.tilt_peak_probe.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double), C.c_void_p]
+_lib.tilt_peak_probe.restype = C.c_int
 _lib.tilt_tune_clear.argtypes = []
 _lib.tilt_tune_clear.restype = C.c_int
 _lib.tilt_rasl_solve_batch.argtypes = [C.c_void_p, C.POINTER(RaslProblem), C.c_int, C.POINTER(Params),
@@ -216,7 +219,7 @@ EXPORTS = [
     "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_warp_jacobian", "tilt_last_error",
     "tilt_ctx_last_kernel_ms", "tilt_submit", "tilt_poll", "tilt_serve_stop", "tilt_pyramid",
     "tilt_inner_batch", "tilt_svt_layouts", "tilt_svt_layout", "tilt_tune_set", "tilt_tune_clear",
-    "tilt_rasl_solve_batch",
+    "tilt_rasl_solve_batch", "tilt_peak_probe",
 ]
 
 
@@ -230,6 +233,21 @@ def svt_layouts(m: int, n: int):
     lpp = (C.c_int * 8)()
     k = _lib.tilt_svt_layouts(int(m), int(n), bs, lpp, 8)
     return [(bs[i], lpp[i]) for i in range(min(k, 8))]
+
+
+PEAK_HBM_COPY, PEAK_LDS_READ, PEAK_FP32_FMA, PEAK_FP32_MFMA = 0, 1, 2, 3
+
+
+def peak_probe(kind: int, src_ptr: int, dst_ptr: int, nbytes: int, iters: int = 1, stream=None):
+    """Run one machine-peak probe kernel; returns (ms, work) with work in
+    bytes (kinds 0, 1) or flops (kinds 2, 3)."""
+    ms = C.c_double()
+    work = C.c_double()
+    rc = _lib.tilt_peak_probe(int(kind), C.c_void_p(src_ptr or None), C.c_void_p(dst_ptr), C.c_size_t(nbytes),
+                              int(iters), C.byref(ms), C.byref(work), C.c_void_p(_stream_ptr(stream)))
+    if rc != TILT_OK:
+        raise TiltError(rc, "tilt_peak_probe")
+    return ms.value, work.value
 
 
 def svt_layout(m: int, n: int):

@@ -160,3 +160,15 @@ def test_svt_layout_single_float_tails(tilt):
         tilt.svt_layout(20, 2100)                                   # rows longer than 2048 floats
     with pytest.raises(tilt.TiltError):
         tilt.svt_layout(0, 10)
+
+
+def test_peak_probe_rejects_bad_arguments(tilt):
+    """Argument checks of the machine-peak probe come before any device call."""
+    with pytest.raises(tilt.TiltError):
+        tilt.peak_probe(7, 0, 1, 1 << 20, 1)          # unknown kind
+    with pytest.raises(tilt.TiltError):
+        tilt.peak_probe(2, 0, 0, 1 << 20, 1)          # no destination
+    with pytest.raises(tilt.TiltError):
+        tilt.peak_probe(0, 0, 1, 1 << 20, 1)          # copy without a source
+    with pytest.raises(tilt.TiltError):
+        tilt.peak_probe(2, 0, 1, 1 << 20, 0)          # no iterations
