@@ -78,13 +78,20 @@ class Patch:
 
 
 def _freqs(rng: np.random.Generator, r: int, L: int) -> np.ndarray:
+    """r frequencies uniform in [1, hi] cycles, pairwise at least 0.5 apart."""
     hi = max(1.0 + 0.5 * r + 0.5, L / 8.0)
     for _ in range(10000):
         f = rng.uniform(1.0, hi, size=r)
         fs = np.sort(f)
         if r == 1 or np.min(np.diff(fs)) >= 0.5:
             return f
-    raise RuntimeError("could not draw separated frequencies")
+    # Where r separated values barely fit (small windows of high rank) the
+    # rejection rarely succeeds; draw from the same law directly: r uniform
+    # points in the interval shortened by the r - 1 gaps, sorted, spread by
+    # 0.5, in random order.
+    span = (hi - 1.0) - 0.5 * (r - 1)
+    f = np.sort(rng.uniform(0.0, span, size=r)) + 1.0 + 0.5 * np.arange(r)
+    return rng.permutation(f)
 
 
 def _texture_params(rng: np.random.Generator, r: int, m: int, n: int):
