@@ -572,3 +572,24 @@ def test_warm_svt_single_float_tail_layouts_match_oracle(tilt, ctx, device, lpp,
     ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
     assert np.linalg.norm(r["A"] - ref.A) <= 1e-4 * np.linalg.norm(ref.A)
     assert O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n) <= 1e-5
+
+
+def test_full_headline_batch_sampled_against_oracle(tilt, ctx, device):
+    """The 256-patch 100x100 projective workload in one fused launch (the
+    launch configuration bench.py times): every patch returns a status >= 0,
+    and sampled patches, solved one by one by the oracle, agree (tau within
+    1e-4, objective within 1e-4, the same numerical rank).  The samples are
+    patches whose solves converge in few iterations, so the oracle leg stays
+    short."""
+    patches = ts.make_config(1)
+    assert len(patches) == 256
+    tp = tilt.default_params(lam=patches[0].lam)
+    _, res = solve_on_device(tilt, ctx, patches, device, tp)
+    assert all(r["status"] >= 0 for r in res)
+    for i in (47, 121, 253):
+        p, r = patches[i], res[i]
+        ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
+        assert ref.outer_iters < tp.max_outer and r["outer_iters"] < tp.max_outer, i
+        assert O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n) <= 1e-4, i
+        assert abs(r["objective"] - ref.objective) <= 1e-4 * ref.objective, i
+        assert same_numerical_rank(O, r["A"], ref.A)[0], (i, same_numerical_rank(O, r["A"], ref.A))
