@@ -376,7 +376,7 @@ def spectral_norm(X):
     return float(np.linalg.svd(X, compute_uv=False)[0])
 
 
-def ladmap_inner(I, Jp: Annihilator, lam, A0, E0, Y0, prm: Params, mu0=None) -> InnerResult:
+def ladmap_inner(I, Jp: Annihilator, lam, A0, E0, Y0, prm: Params, mu0=None, trace=None) -> InnerResult:
     """LADMAP for min ||A||_* + lam ||E||_1 s.t. J_perp(A + E) = J_perp I.
 
     Updates (Sec. 4.2):
@@ -386,6 +386,10 @@ def ladmap_inner(I, Jp: Annihilator, lam, A0, E0, Y0, prm: Params, mu0=None) -> 
       E_{k+1} = T_{lam/mu_k}(N_k)
       Y_{k+1} = Y_k + mu_k J_perp(A_{k+1} + E_{k+1} - I)
       mu_{k+1}= min(mu_max, rho mu_k), rho = rho0 if the Cond2 quantity < eps2
+
+    ``trace`` (a list, optional) receives one (A_k, E_k, mu_k) tuple per
+    iteration and the final (A, E, mu), so tests can check the penalty
+    schedule against the iterates; it changes nothing in the iteration.
     """
     A = A0.copy()
     E = E0.copy()
@@ -400,6 +404,8 @@ def ladmap_inner(I, Jp: Annihilator, lam, A0, E0, Y0, prm: Params, mu0=None) -> 
     sv = np.zeros(0)
     svt_count = 0
     while k < prm.max_inner:
+        if trace is not None:
+            trace.append((A, E, mu))
         M = A - R - Y / mu
         A1, sv = svt(M, 1.0 / mu)
         svt_count = int(np.sum(sv > 1.0 / mu))
@@ -417,6 +423,8 @@ def ladmap_inner(I, Jp: Annihilator, lam, A0, E0, Y0, prm: Params, mu0=None) -> 
             break
         if cond2 < prm.eps2:
             mu = min(prm.mu_max, prm.rho0 * mu)
+    if trace is not None:
+        trace.append((A, E, mu))
     return InnerResult(A, E, Y, k, mu, cond1, cond2, svt_count, sv)
 
 

@@ -415,3 +415,140 @@ def test_bilinear_gradient_cell_edge_convention():
         assert abs(v[0] - 1.5) < 1e-9
     v, dx, _ = O.bilinear_with_gradient(img, np.array([1.0 - 1e-6]), np.array([0.5]))
     assert abs(dx[0] - ((1 - 0.5) * (1 - 0) + 0.5 * (2 - 0))) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Adaptive penalty (Eqs. mu, rho): special cases the equations fix
+# ---------------------------------------------------------------------------
+
+
+def _penalty_problem():
+    rng = np.random.default_rng(21)
+    I, J = _random_inner_problem(rng, 10, 8, 2)
+    return I, O.Annihilator(J), 1 / math.sqrt(10), np.zeros_like(I)
+
+
+def test_penalty_rho0_one_keeps_mu_fixed():
+    """rho_0 = 1 makes Eq. rho give rho = 1 in both branches: mu_k = mu_0."""
+    I, Jp, lam, Z0 = _penalty_problem()
+    for eps2 in (0.0, 1e-2, np.inf):
+        prm = O.Params(rho0=1.0, eps2=eps2, max_inner=30, fixed_iters=True)
+        r = O.ladmap_inner(I, Jp, lam, I, Z0, Z0, prm, mu0=0.7)
+        assert r.mu == 0.7
+
+
+def test_penalty_eps2_infinite_grows_geometrically():
+    """With eps2 = inf the Cond2 test of Eq. rho always passes, so after K
+    iterations mu = min(mu_max, rho_0^K mu_0) exactly (rho_0 = 2 scales by
+    powers of two without rounding)."""
+    I, Jp, lam, Z0 = _penalty_problem()
+    for K in (1, 5, 17):
+        prm = O.Params(rho0=2.0, eps2=np.inf, max_inner=K, fixed_iters=True, mu_max=1e300)
+        r = O.ladmap_inner(I, Jp, lam, I, Z0, Z0, prm, mu0=0.75)
+        assert r.mu == 0.75 * 2.0**K
+
+
+def test_penalty_eps2_zero_never_grows():
+    """eps2 = 0: the Cond2 quantity is never below it, rho = 1 throughout."""
+    I, Jp, lam, Z0 = _penalty_problem()
+    prm = O.Params(rho0=1.5, eps2=0.0, max_inner=40, fixed_iters=True)
+    r = O.ladmap_inner(I, Jp, lam, I, Z0, Z0, prm, mu0=0.3)
+    assert r.mu == 0.3
+
+
+def test_penalty_mu_max_clamps():
+    """Eq. mu: mu never exceeds mu_max; once rho_0 mu_k passes it, mu stays
+    at mu_max."""
+    I, Jp, lam, Z0 = _penalty_problem()
+    mu_max = 0.75 * 2.0**3.5
+    r3 = O.ladmap_inner(I, Jp, lam, I, Z0, Z0,
+                        O.Params(rho0=2.0, eps2=np.inf, max_inner=3, fixed_iters=True, mu_max=mu_max), mu0=0.75)
+    assert r3.mu == 6.0
+    r9 = O.ladmap_inner(I, Jp, lam, I, Z0, Z0,
+                        O.Params(rho0=2.0, eps2=np.inf, max_inner=9, fixed_iters=True, mu_max=mu_max), mu0=0.75)
+    assert r9.mu == mu_max
+
+
+def test_penalty_schedule_follows_cond2_of_the_iterates():
+    """mu_{k+1} = min(mu_max, rho_0 mu_k) exactly when
+    mu_k max(||A_{k+1} - A_k||, ||E_{k+1} - E_k||) / ||J_perp(D o tau)|| < eps2,
+    and mu_{k+1} = mu_k otherwise, with the quantity recomputed here from
+    the recorded iterates; eps2 is chosen so that both branches occur."""
+    I, Jp, lam, Z0 = _penalty_problem()
+    c = float(np.linalg.norm(Jp(I)))
+    prm = O.Params(rho0=1.5, eps2=0.05, max_inner=60, fixed_iters=True, mu_max=1e3)
+    tr = []
+    O.ladmap_inner(I, Jp, lam, I, Z0, Z0, prm, trace=tr)
+    assert len(tr) == 61
+    grew = kept = 0
+    for (A0, E0, mu0), (A1, E1, mu1) in zip(tr[:-1], tr[1:]):
+        q = mu0 * max(np.linalg.norm(A1 - A0), np.linalg.norm(E1 - E0)) / c
+        if q < prm.eps2:
+            assert mu1 == min(prm.mu_max, prm.rho0 * mu0)
+            grew += 1
+        else:
+            assert mu1 == mu0
+            kept += 1
+    assert grew > 0 and kept > 0
+
+
+# ---------------------------------------------------------------------------
+# tau error metric (relative Frobenius error in the reference window's
+# scaled coordinates)
+# ---------------------------------------------------------------------------
+
+
+def _window(cx, cy, a=1.0):
+    return np.array([[a, 0.0, cx], [0.0, a, cy], [0.0, 0.0, 1.0]])
+
+
+def test_tau_rel_err_equal_transforms_is_zero():
+    H = _window(200.0, 150.0)
+    H[0, 1] = 0.1
+    H[2, 0] = 1e-4
+    assert O.tau_rel_err(H, H, 100, 100) == 0.0
+    assert O.tau_rel_err(3.0 * H, H, 100, 100) < 1e-15     # a homography is defined up to scale
+
+
+def test_tau_rel_err_half_pixel_translation():
+    """A half-pixel shift of a 100x100 window: in scaled coordinates
+    (s = 50) the translation entry changes by 0.5/s and ||H_ref||_F = sqrt(3)."""
+    Hb = _window(200.0, 150.0)
+    Ha = _window(200.5, 150.0)
+    assert abs(O.tau_rel_err(Ha, Hb, 100, 100) - 0.5 / 50.0 / math.sqrt(3.0)) < 1e-15
+    # the window size enters through s = max(m, n) / 2
+    assert abs(O.tau_rel_err(Ha, Hb, 40, 80) - 0.5 / 40.0 / math.sqrt(3.0)) < 1e-15
+
+
+def test_tau_rel_err_is_scale_invariant():
+    rng = np.random.default_rng(22)
+    Hb = _window(120.0, 90.0, 1.1)
+    Hb[2, :2] = [2e-4, -1e-4]
+    Ha = Hb + rng.standard_normal((3, 3)) * 1e-3
+    Ha[2, 2] = 1.0
+    e = O.tau_rel_err(Ha, Hb, 60, 70)
+    assert e > 0
+    assert abs(O.tau_rel_err(-2.5 * Ha, Hb, 60, 70) - e) <= 1e-12 * e
+    assert abs(O.tau_rel_err(Ha, 7.0 * Hb, 60, 70) - e) <= 1e-12 * e
+
+
+def test_tau_rel_err_perspective_closed_form():
+    """H_a adds a perspective entry h31 to the identity window at c: in H_b's
+    scaled frame the difference is h31 (-cx, -cy, s) in the first column, so
+    the error is |h31| sqrt(cx^2 + cy^2 + s^2) / sqrt(3)."""
+    cx, cy, h = 130.0, 70.0, 3e-5
+    Hb = _window(cx, cy)
+    Ha = Hb.copy()
+    Ha[2, 0] = h
+    want = h * math.sqrt(cx * cx + cy * cy + 50.0**2) / math.sqrt(3.0)
+    assert abs(O.tau_rel_err(Ha, Hb, 100, 100) - want) <= 1e-12 * want
+
+
+def test_tau_rel_err_uses_the_reference_frame():
+    """The error is measured in the second argument's window: a 2x scale
+    against the identity gives sqrt(2)/3 in the scaled window's frame and
+    sqrt(2)/sqrt(3) in the identity's frame."""
+    Hs = _window(100.0, 100.0, 2.0)
+    Hi = _window(100.0, 100.0, 1.0)
+    assert abs(O.tau_rel_err(Hi, Hs, 50, 50) - math.sqrt(2.0) / 3.0) < 1e-15
+    assert abs(O.tau_rel_err(Hs, Hi, 50, 50) - math.sqrt(2.0) / math.sqrt(3.0)) < 1e-15
