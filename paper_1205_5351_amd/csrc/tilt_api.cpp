@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -71,7 +72,7 @@ void split_row(int nr4, int bs, int lpp, bool tails, int* nch, int* tl) {
 // width, plus the row loads/stores), and divides by the number of
 // concurrent groups' worth of issue slots when fewer groups than slots are
 // busy.  The cheapest layout wins.
-int pick_svt_cfg(int nc, int nr4, bool tails) {
+int pick_svt_cfg(int nc, int nr4, bool tails, double* cost_out = nullptr) {
     const int nc4 = (nc + 3) & ~3;
     int best = -1;
     double best_cost = 1e300;
@@ -106,6 +107,7 @@ int pick_svt_cfg(int nc, int nr4, bool tails) {
             }
         }
     }
+    if (cost_out) *cost_out = best_cost;
     return best;
 }
 
@@ -227,31 +229,52 @@ int shape_config(int m, int n, ShapeCfg* out) {
         }
     }
     if (c.nr > SVT_MAX_COLS) return TILT_ERR_TOO_LARGE;
+    // Tiled: the super-block size is chosen for a gang of up to
+    // kGangPlan workgroups (the fused kernel splits each round's pairs over
+    // them): the modelled time of a sweep is (rounds) x (pairs per member)
+    // x (one staged sweep over 2 sb rows, plus staging the rows through
+    // LDS).  Ties within 10 % go to fewer super-blocks (fewer members and
+    // barriers).  The choice fixes the arithmetic, so every path uses it.
+    ShapeCfg best;
+    double best_t = 1e300;
+    bool found = false;
     for (int nsb = 2; nsb <= SVT_MAX_TILED_ROWS / 4; nsb += 2) {
         const int sb = (((nc4 + nsb - 1) / nsb) + 3) & ~3;
         if (2 * sb > SVT_MAX_ROWS) continue;
+        if (sb < 4 || (nsb > 2 && ((nc4 + nsb - 3) / (nsb - 2) + 3 & ~3) == sb)) continue;  // same blocks, more rounds
         const int ncp = nsb * sb;
         if (ncp > SVT_MAX_TILED_ROWS) continue;  // rounding sb up to 4 rows: ncp is not monotonic in nsb
-        const int cfg = pick_svt_cfg(2 * sb, c.ldg / 4, false);
+        double task = 0.0;
+        const int cfg = pick_svt_cfg(2 * sb, c.ldg / 4, false, &task);
         if (cfg < 0) return TILT_ERR_TOO_LARGE;
         const int ld = pick_ld(cfg);
+        task += 8.0 * (2.0 * sb) * (c.ldg / 4);  // staging both blocks in and out
+        const int pairs = nsb / 2;
+        const int members = std::min(pairs, kGangPlan);
+        const double t = (nsb - 1) * (double)((pairs + members - 1) / members) * task;
         for (int tb = 32; tb >= 16; tb -= 16) {
             const size_t lds = lds_bytes_tiled(sb, ncp, ld, c.ldg, tb);
             if (lds <= budget) {
-                c.cfg = cfg;
-                c.ld = ld;
-                c.tb = tb;
-                c.sb = sb;
-                c.nsb = nsb;
-                c.ncp = ncp;
-                c.lds = lds;
-                c.ws_floats = (size_t)NPLANES * c.nc * c.ldg + (size_t)ncp * c.ldg;
-                *out = c;
-                return TILT_OK;
+                if (!found || t < 0.9 * best_t) {
+                    best = c;
+                    best.cfg = cfg;
+                    best.ld = ld;
+                    best.tb = tb;
+                    best.sb = sb;
+                    best.nsb = nsb;
+                    best.ncp = ncp;
+                    best.lds = lds;
+                    best.ws_floats = (size_t)NPLANES * c.nc * c.ldg + (size_t)ncp * c.ldg;
+                    best_t = t;
+                    found = true;
+                }
+                break;
             }
         }
     }
-    return TILT_ERR_TOO_LARGE;
+    if (!found) return TILT_ERR_TOO_LARGE;
+    *out = best;
+    return TILT_OK;
 }
 
 // Predicted relative cost of a solve (one-sided Jacobi work per iteration).
@@ -642,6 +665,18 @@ int run_plain_request(tilt_ctx* ctx, size_t lds, const SolverParams& sp, int L, 
     return TILT_OK;
 }
 
+// Most workgroups of the fused kernel one tiled window may take:
+// TILT_GANG_MAX from the environment (1 turns gangs off), else kGangPlan.
+// Only who runs which super-block pair depends on it, not the results.
+int gang_max() {
+    const char* e = std::getenv("TILT_GANG_MAX");
+    if (e && *e) {
+        const int v = std::atoi(e);
+        if (v >= 1) return std::min(v, 64);
+    }
+    return kGangPlan;
+}
+
 int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const tilt_params* prm,
                      tilt_result* results, void* hip_stream, bool plain) {
     if (!ctx || !probs || count < 0 || !prm || !results) return TILT_ERR_ARG;
@@ -689,22 +724,56 @@ int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const 
             if (r != TILT_OK) return r;
         } else {
             if (ctx->queue.reserve(256) != hipSuccess) return TILT_ERR_NOMEM;
-            if (ctx->order.reserve(sizeof(int) * nlive) != hipSuccess) return TILT_ERR_NOMEM;
-            // longest predicted solve first (stable: equal shapes keep their order)
+            // Gangs: a request with a tiled level gets up to gang_max()
+            // workgroups for its Jacobi rounds (no more than the pairs of a
+            // round), when the device runs enough workgroups at once.
+            int per_cu = 0;
+            HIP_TRY(fused_blocks_per_cu(max_lds, &per_cu));
+            const int resident = std::max(1, per_cu) * ctx->num_cus;
+            const int gmax = gang_max();
+            std::vector<int> members(nlive, 1);
+            bool gangs = false;
+            for (int k = 0; k < nlive && gmax > 1 && resident >= 4 * gmax; ++k) {
+                for (int l = 0; l < L; ++l)
+                    if (plans[k].d[l].sb > 0) members[k] = std::max(members[k], std::min(gmax, plans[k].d[l].nsb / 2));
+                gangs |= members[k] > 1;
+            }
+            if (gangs) {
+                if (ctx->gangs.reserve(sizeof(GangCtl) * nlive) != hipSuccess) return TILT_ERR_NOMEM;
+                HIP_TRY(hipMemsetAsync(ctx->gangs.p, 0, sizeof(GangCtl) * nlive, stream));
+                std::vector<PatchDesc> descs((size_t)L * nlive);
+                for (int k = 0; k < nlive; ++k)
+                    for (int l = 0; l < L; ++l) {
+                        PatchDesc& d = plans[k].d[l];
+                        d.gsize = members[k];
+                        d.gang = members[k] > 1 ? reinterpret_cast<GangCtl*>(ctx->gangs.p) + k : nullptr;
+                        descs[(size_t)k * L + l] = d;
+                    }
+                HIP_TRY(hipMemcpyAsync(ctx->descs.p, descs.data(), sizeof(PatchDesc) * L * nlive,
+                                       hipMemcpyHostToDevice, stream));
+            }
+            // longest predicted solve first (per member of its gang; stable:
+            // equal shapes keep their order), each gang's tickets together
             std::vector<int> order(nlive);
             for (int k = 0; k < nlive; ++k) order[k] = k;
             std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-                return predicted_cost(plans[a].d[0]) > predicted_cost(plans[b].d[0]);
+                return predicted_cost(plans[a].d[0]) / members[a] > predicted_cost(plans[b].d[0]) / members[b];
             });
-            HIP_TRY(hipMemcpyAsync(ctx->order.p, order.data(), sizeof(int) * nlive, hipMemcpyHostToDevice, stream));
+            std::vector<Ticket> tickets;
+            for (int k : order)
+                for (int r = 0; r < members[k]; ++r) tickets.push_back(Ticket{k, r, members[k], 0});
+            const int ntickets = (int)tickets.size();
+            if (ctx->order.reserve(sizeof(Ticket) * ntickets) != hipSuccess) return TILT_ERR_NOMEM;
+            HIP_TRY(hipMemcpyAsync(ctx->order.p, tickets.data(), sizeof(Ticket) * ntickets, hipMemcpyHostToDevice,
+                                   stream));
             HIP_TRY(hipMemsetAsync(ctx->queue.p, 0, sizeof(int), stream));
-            const int per_cu = std::max<int>(1, (int)(LDS_LIMIT / (max_lds + kStaticLdsMargin)));
-            const int grid = std::max(1, std::min(nlive, ctx->num_cus * std::min(per_cu, 2)));
+            const int grid = gangs ? std::min(ntickets, resident)
+                                   : std::max(1, std::min(nlive, ctx->num_cus * std::max(1, std::min(per_cu, 2))));
             HIP_TRY(hipEventRecord(ctx->ev0, stream));
             HIP_TRY(launch_fused(reinterpret_cast<const PatchDesc*>(ctx->descs.p),
-                                 reinterpret_cast<PatchState*>(ctx->states.p), sp, nlive, L,
-                                 reinterpret_cast<const int*>(ctx->order.p), reinterpret_cast<int*>(ctx->queue.p),
-                                 grid, max_lds, stream));
+                                 reinterpret_cast<PatchState*>(ctx->states.p), sp, ntickets, L,
+                                 reinterpret_cast<const Ticket*>(ctx->order.p), reinterpret_cast<int*>(ctx->queue.p),
+                                 grid, max_lds, gangs, stream));
             HIP_TRY(hipEventRecord(ctx->ev1, stream));
         }
         std::vector<PatchState> out(nlive);
@@ -1056,6 +1125,7 @@ int tilt_ctx_destroy(tilt_ctx* ctx) {
     ctx->jobs.release();
     ctx->counters.release();
     ctx->img.release();
+    ctx->gangs.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;

@@ -33,6 +33,32 @@ constexpr int SVT_MAX_ROWS = 256;  // rows of the Jacobi matrix held in LDS at o
 constexpr int SVT_MAX_TILED_ROWS = 1024;  // rows of the working plane (min(m, n) rounded up to whole super-blocks)
 constexpr int SVT_MAX_COLS = 2048;       // max(m, n): 64 lanes x 8 chunks x 4 floats
 
+// A gang is the set of workgroups of the fused kernel that share one
+// window whose SVT is tiled through device memory: the first member (the
+// leader) runs every step of the solve; each Jacobi sweep's super-block
+// pairs are split over all members, one round at a time, with a barrier
+// between rounds.  The control block lives in device memory, one per
+// window, zeroed before the launch.  Counters only grow, so no member ever
+// waits on a value another member has to reset.
+struct alignas(128) GangCtl {
+    int post;            // jobs posted by the leader (a job: one tiled decomposition, or the end)
+    int bar;             // barrier arrivals: barrier b completes when bar reaches (b + 1) * members
+    int rot;             // largest sweep tag in which some pair rotated
+    int end;             // the posted job is the end of the request
+    float* Bg;           // job: working plane (ncp x ldg rows)
+    int sb, nsb, ldg, ld, cfg, max_sweeps;
+    float tol;
+    int pad0;
+    unsigned long long pairs, rotations;  // work of the members in the current job
+    int pad[14];
+};
+
+// Work-queue entry of the fused kernel: window `idx`, member `rank` of a
+// gang of `members` workgroups (1: the window is solved by one workgroup).
+struct Ticket {
+    int idx, rank, members, pad;
+};
+
 struct PatchDesc {
     const float* image;
     long long stride;
@@ -47,13 +73,14 @@ struct PatchDesc {
     int ncp;                  // tiled SVT: rows of the working plane (nsb * sb >= nc)
     int warm;                 // SVT warm-started from the previous rotation: 1 FP32 start,
                               // 2 bfloat16 start + FP32 refinement, 3 bfloat16 start
-    int pad1;
+    int gsize;                // workgroups sharing the tiled Jacobi of this window (1: one)
     double cx, cy, s;         // scaled coordinates of the level being solved (the
                               // kernels take them from PatchState::geo)
     double lam;
     float* ws;                // NPLANES planes (+ one ncp x ldg working plane when tiled)
     float* A_out;             // m x n row-major (may be null)
     float* E_out;
+    GangCtl* gang;            // gang control block when gsize > 1 (fused kernel only)
 };
 
 struct PatchState {
@@ -205,8 +232,13 @@ struct ServeCtl {
 };
 
 // Kernel launchers (tilt_kernels.hip).
-hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, int levels,
-                        const int* order, int* queue, int grid, size_t lds, hipStream_t s);
+// Fused kernel over `ntickets` queue entries; cooperative (every workgroup
+// resident at once) when the tickets form gangs.
+hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int ntickets, int levels,
+                        const Ticket* tickets, int* queue, int grid, size_t lds, bool cooperative, hipStream_t s);
+// Workgroups of the fused kernel one compute unit holds at once with `lds`
+// bytes of dynamic LDS.
+hipError_t fused_blocks_per_cu(size_t lds, int* blocks);
 hipError_t launch_wide_setup(const PatchDesc* d, PatchState* st, const SolverParams& prm, const float* I,
                              const float* J, int count, size_t lds, hipStream_t s);
 hipError_t launch_wide_stage(const PatchDesc* d, PatchState* st, const int* active, int nactive, int form_m,

@@ -683,38 +683,182 @@ __device__ void store_block(float* Bg, int r0, int cnt, int ldg, const float* mi
     }
 }
 
+// Pair k of round r of the circle ordering over nsb super-blocks: the
+// super-blocks I and J it joins.
+__device__ inline void superblock_pair(int nsb, int r, int k, int& I, int& J) {
+    const int Nb = nsb - 1;
+    if (k == 0) {
+        I = Nb;
+        J = r;
+    } else {
+        I = r + k;
+        if (I >= Nb) I -= Nb;
+        J = r - k;
+        if (J < 0) J += Nb;
+    }
+}
+
+// One super-block pair: stage both blocks into LDS, one full Jacobi sweep
+// over their 2 sb rows, write them back if anything rotated.  Returns 1 if
+// a pair rotated (uniform over the workgroup).
+__device__ int superblock_task(int cfg, float* Bg, int sb, int nsb, int ldg, int ld, float* mini, float tol, int r,
+                               int k, JacobiStats& js) {
+    int I, J;
+    superblock_pair(nsb, r, k, I, J);
+    load_block(Bg, I * sb, sb, ldg, mini, 0, ld);
+    load_block(Bg, J * sb, sb, ldg, mini, sb, ld);
+    clear_lds_padding(mini, 2 * sb, ldg, ld);
+    __syncthreads();
+    const int rot = jacobi_sweep_dispatch(cfg, mini, 2 * sb, ld, tol, js);
+    if (rot) {
+        store_block(Bg, I * sb, sb, ldg, mini, 0, ld);
+        store_block(Bg, J * sb, sb, ldg, mini, sb, ld);
+    }
+    __syncthreads();
+    return rot;
+}
+
+// ---------------------------------------------------------------------------
+// Gangs (several workgroups of the fused kernel on one tiled window).
+//
+// Barrier: every member adds 1 to `bar`; barrier b is complete when `bar`
+// reaches (b + 1) * members.  A member can only arrive at barrier b + 1
+// after barrier b completed, so the arrival count alone names the barrier
+// and nothing is ever reset.  Each wave makes its own stores visible at
+// agent scope before the workgroup arrives (the members may sit on
+// different XCDs, each with its own L2), and the arriving thread acquires
+// at agent scope once the barrier completes.
+// ---------------------------------------------------------------------------
+
+__device__ inline int gang_load(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Returns the barrier's index, the same in every member.
+__device__ int gang_barrier(GangCtl* c, int members) {
+    __shared__ int sh_b;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int old = __hip_atomic_fetch_add(&c->bar, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const int b = old / members;
+        const int target = (b + 1) * members;
+        while (gang_load(&c->bar) < target) __builtin_amdgcn_s_sleep(1);
+        sh_b = b;
+    }
+    __syncthreads();
+    return sh_b;
+}
+
+// The tiled Jacobi of one staged plane, run by every member of the gang
+// with the same arguments: in each round member `rank` takes super-block
+// pairs rank, rank + members, ...  The pairs of one round touch disjoint
+// rows, so the result is the one-workgroup tiled Jacobi's whatever member
+// takes which pair.  A sweep's tag is one more than the index of the
+// barrier before it; a rotating pair raises `rot` to the tag, so after the
+// sweep's last barrier `rot >= tag` tells every member alike whether the
+// sweep rotated (a later sweep can only have started if it did).
+__device__ void gang_jacobi(GangCtl* c, int rank, int members, int cfg, float* Bg, int sb, int nsb, int ldg, int ld,
+                            float* mini, float tol, int max_sweeps, JacobiStats& js) {
+    __shared__ int sh_rot;
+    const int Nb = nsb - 1, Pb = nsb >> 1;
+    int b = gang_barrier(c, members);  // the staged plane is visible to every member
+    int sweeps = 0;
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+        const int tag = b + 1;
+        for (int r = 0; r < Nb; ++r) {
+            JacobiStats jr{0, 0, 0};
+            int rot = 0;
+            for (int k = rank; k < Pb; k += members)
+                rot |= superblock_task(cfg, Bg, sb, nsb, ldg, ld, mini, tol, r, k, jr);
+            if (threadIdx.x == 0) {
+                if (rot) atomicMax(&c->rot, tag);
+                if (jr.pairs) atomicAdd(&c->pairs, (unsigned long long)jr.pairs);
+                if (jr.rotations) atomicAdd(&c->rotations, (unsigned long long)jr.rotations);
+            }
+            b = gang_barrier(c, members);
+        }
+        ++sweeps;
+        if (threadIdx.x == 0) sh_rot = gang_load(&c->rot) >= tag;
+        __syncthreads();
+        const int any = sh_rot;
+        __syncthreads();
+        if (!any) break;
+    }
+    js.sweeps += sweeps;
+}
+
+// Leader: post one job (a decomposition of the staged plane Bg, or the end
+// of the request) to the other members.
+__device__ void gang_post(GangCtl* c, int end, int cfg, float* Bg, int sb, int nsb, int ldg, int ld, float tol,
+                          int max_sweeps) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        c->end = end;
+        c->Bg = Bg;
+        c->sb = sb;
+        c->nsb = nsb;
+        c->ldg = ldg;
+        c->ld = ld;
+        c->cfg = cfg;
+        c->tol = tol;
+        c->max_sweeps = max_sweeps;
+        __hip_atomic_fetch_add(&c->post, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+}
+
+// Member rank > 0: take part in every decomposition the leader posts until
+// it posts the end of the request.
+__device__ void gang_member(GangCtl* c, int rank, int members, float* mini) {
+    __shared__ GangCtl sh_job;
+    for (int seen = 0;; ++seen) {
+        if (threadIdx.x == 0) {
+            while (gang_load(&c->post) <= seen) __builtin_amdgcn_s_sleep(2);
+            sh_job.end = c->end;
+            sh_job.Bg = c->Bg;
+            sh_job.sb = c->sb;
+            sh_job.nsb = c->nsb;
+            sh_job.ldg = c->ldg;
+            sh_job.ld = c->ld;
+            sh_job.cfg = c->cfg;
+            sh_job.tol = c->tol;
+            sh_job.max_sweeps = c->max_sweeps;
+        }
+        __syncthreads();
+        const GangCtl job = sh_job;
+        __syncthreads();
+        if (job.end) break;
+        JacobiStats js{0, 0, 0};
+        gang_jacobi(c, rank, members, job.cfg, job.Bg, job.sb, job.nsb, job.ldg, job.ld, mini, job.tol,
+                    job.max_sweeps, js);
+    }
+}
+
+// The tiled Jacobi of the ncp rows of Bg: on this workgroup alone, or, for
+// a gang, posted to the other members and run together with them (the
+// leader then adds their pair counts to its own).
 __device__ void jacobi_tiled(int cfg, float* Bg, int sb, int nsb, int ldg, int ld, float* mini, float tol,
-                             int max_sweeps, JacobiStats& js) {
+                             int max_sweeps, JacobiStats& js, GangCtl* gang = nullptr, int members = 1) {
+    if (gang && members > 1) {
+        gang_post(gang, 0, cfg, Bg, sb, nsb, ldg, ld, tol, max_sweeps);
+        gang_jacobi(gang, 0, members, cfg, Bg, sb, nsb, ldg, ld, mini, tol, max_sweeps, js);
+        if (threadIdx.x == 0) {
+            // every member added its counts before the last barrier, and no
+            // member adds again before the next job is posted
+            js.pairs += (long long)__hip_atomic_exchange(&gang->pairs, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            js.rotations +=
+                (long long)__hip_atomic_exchange(&gang->rotations, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
     const int Nb = nsb - 1, Pb = nsb >> 1;
     const long long sweeps0 = js.sweeps;
     int sweeps = 0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
         int any = 0;
-        for (int r = 0; r < Nb; ++r) {
-            for (int k = 0; k < Pb; ++k) {
-                int I, J;
-                if (k == 0) {
-                    I = Nb;
-                    J = r;
-                } else {
-                    I = r + k;
-                    if (I >= Nb) I -= Nb;
-                    J = r - k;
-                    if (J < 0) J += Nb;
-                }
-                load_block(Bg, I * sb, sb, ldg, mini, 0, ld);
-                load_block(Bg, J * sb, sb, ldg, mini, sb, ld);
-                clear_lds_padding(mini, 2 * sb, ldg, ld);
-                __syncthreads();
-                const int rot = jacobi_sweep_dispatch(cfg, mini, 2 * sb, ld, tol, js);
-                if (rot) {
-                    store_block(Bg, I * sb, sb, ldg, mini, 0, ld);
-                    store_block(Bg, J * sb, sb, ldg, mini, sb, ld);
-                }
-                any |= rot;
-                __syncthreads();
-            }
-        }
+        for (int r = 0; r < Nb; ++r)
+            for (int k = 0; k < Pb; ++k) any |= superblock_task(cfg, Bg, sb, nsb, ldg, ld, mini, tol, r, k, js);
         ++sweeps;
         if (!any) break;
     }
@@ -965,7 +1109,7 @@ __device__ void svd_rows(const PatchDesc& d, const float* X, float* Bg, const Sv
             reinterpret_cast<float4*>(Bg + (size_t)row * d.ldg)[c] = v;
         }
         __syncthreads();
-        jacobi_tiled(d.svt_cfg, Bg, d.sb, d.nsb, d.ldg, d.ld, L.B, tol, max_sweeps, js);
+        jacobi_tiled(d.svt_cfg, Bg, d.sb, d.nsb, d.ldg, d.ld, L.B, tol, max_sweeps, js, d.gang, d.gsize);
         row_norms_global(Bg, d.nc, d.ldg, L.s2);
     } else {
         load_rows_lds(X, d.nc, d.ldg, d.ld, L.B);
@@ -2127,25 +2271,38 @@ __device__ void solve_request(const PatchDesc* dl, int levels, PatchState* st, c
     if (threadIdx.x == 0) st->t_end = (long long)wall_clock64();
 }
 
-// Persistent solver: each workgroup takes the next request from the queue
-// (in the order given by `order`, longest predicted solve first) until the
-// queue is exhausted.  Request i has its level descriptors at
-// descs[i * levels ...].
+// Persistent solver: each workgroup takes the next ticket from the queue
+// (tickets are in the order of the predicted solve, longest first) until
+// the queue is exhausted.  A ticket names a request and the workgroup's
+// rank in the request's gang: rank 0 solves the request (request i has its
+// level descriptors at descs[i * levels ...]); ranks above 0 join its tiled
+// Jacobi sweeps until the leader posts the end.  The tickets of one gang
+// are consecutive, so only the gang at the head of the queue can be
+// incomplete; every other workgroup that holds a ticket finishes its work
+// and claims the next one, so that gang completes as long as it has no more
+// members than workgroups run at once (the launch is cooperative when there
+// are gangs).
 __global__ void __launch_bounds__(NT) k_fused(const PatchDesc* __restrict__ descs, PatchState* states,
-                                               SolverParams prm, int count, int levels,
-                                               const int* __restrict__ order, int* queue) {
-    __shared__ int sh_idx;
+                                               SolverParams prm, int ntickets, int levels,
+                                               const Ticket* __restrict__ tickets, int* queue) {
+    __shared__ Ticket sh_t;
     float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
     for (;;) {
         if (threadIdx.x == 0) {
             const int q = atomicAdd(queue, 1);
-            sh_idx = q < count ? order[q] : count;
+            sh_t = q < ntickets ? tickets[q] : Ticket{-1, 0, 1, 0};
         }
         __syncthreads();
-        const int idx = sh_idx;
+        const Ticket t = sh_t;
         __syncthreads();
-        if (idx >= count) break;
-        solve_request(descs + (size_t)idx * levels, levels, states + idx, prm, lds);
+        if (t.idx < 0) break;
+        const PatchDesc* dl = descs + (size_t)t.idx * levels;
+        if (t.rank > 0) {
+            gang_member(dl[0].gang, t.rank, t.members, lds);
+            continue;
+        }
+        solve_request(dl, levels, states + t.idx, prm, lds);
+        if (t.members > 1) gang_post(dl[0].gang, 1, 0, nullptr, 0, 0, 0, 0, 0.f, 0);
     }
 }
 
@@ -2654,12 +2811,23 @@ static hipError_t set_lds(const void* fn, size_t lds) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, int levels,
-                        const int* order, int* queue, int grid, size_t lds, hipStream_t s) {
+hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int ntickets, int levels,
+                        const Ticket* tickets, int* queue, int grid, size_t lds, bool cooperative, hipStream_t s) {
     hipError_t e = set_lds((const void*)k_fused, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(NT), lds, s, d, st, prm, count, levels, order, queue);
-    return hipGetLastError();
+    if (!cooperative) {
+        hipLaunchKernelGGL(k_fused, dim3(grid), dim3(NT), lds, s, d, st, prm, ntickets, levels, tickets, queue);
+        return hipGetLastError();
+    }
+    void* args[] = {(void*)&d, (void*)&st, (void*)&prm, (void*)&ntickets, (void*)&levels, (void*)&tickets,
+                    (void*)&queue};
+    return hipLaunchCooperativeKernel((const void*)k_fused, dim3(grid), dim3(NT), args, (unsigned)lds, s);
+}
+
+hipError_t fused_blocks_per_cu(size_t lds, int* blocks) {
+    hipError_t e = set_lds((const void*)k_fused, lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k_fused, NT, lds);
 }
 
 hipError_t launch_serve(ServeCtl* ctl, ServeSlot* slots, PatchDesc* ddesc, PatchState* dstates,
