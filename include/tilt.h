@@ -87,7 +87,11 @@ typedef struct {
                            and the Jacobi continues (FP32 accuracy).
                            3: bfloat16 start without refinement (precision
                            study; errors of order 1e-3).                      */
-    float jacobi_tol;   /* rotate a pair when |a.b| > tol ||a|| ||b||; 1e-6   */
+    float jacobi_tol;   /* rotate a pair when |a.b| > tol ||a|| ||b||; 1e-7.
+                           The SVT's rounding enters Cond2 multiplied by mu
+                           (up to ~1e3 on large windows), so it must stay
+                           well below eps2 / mu; at 1e-6 large windows never
+                           meet Cond2.                                       */
     int max_sweeps;     /* Jacobi sweep cap, default 40                       */
     int pyramid_levels; /* 1 (default): solve the window as given.  L in 2..4:
                            solve coarse to fine over L levels; level l has the

@@ -143,8 +143,8 @@ size_t lds_bytes(int nc, int ld, int tb) {
     return sizeof(float) * ((size_t)nc4 * ld + (size_t)tb * ld + (size_t)nc4 * tb + 3 * (size_t)nc4);
 }
 
-size_t lds_bytes_tiled(int sb, int ncp, int ld, int ldg, int tb) {
-    const size_t front = std::max((size_t)2 * sb * ld, (size_t)tb * ldg + (size_t)ncp * tb);
+size_t lds_bytes_tiled(int sb, int ncp, int ld, int ldg, int tb, bool warm = false) {
+    const size_t front = std::max((size_t)(warm ? 4 : 2) * sb * ld, (size_t)tb * ldg + (size_t)ncp * tb);
     return sizeof(float) * (front + 3 * (size_t)ncp);
 }
 
@@ -229,12 +229,12 @@ int shape_config(int m, int n, ShapeCfg* out) {
         }
     }
     if (c.nr > SVT_MAX_COLS) return TILT_ERR_TOO_LARGE;
-    // Tiled: the super-block size is chosen for a gang of up to
-    // kGangPlan workgroups (the fused kernel splits each round's pairs over
-    // them): the modelled time of a sweep is (rounds) x (pairs per member)
-    // x (one staged sweep over 2 sb rows, plus staging the rows through
-    // LDS).  Ties within 10 % go to fewer super-blocks (fewer members and
-    // barriers).  The choice fixes the arithmetic, so every path uses it.
+    // Tiled: the super-block size is chosen for up to kHelpPlan
+    // workgroups on one window (the fused kernel lets idle workgroups take
+    // pairs of a round): the modelled time of a sweep is (rounds) x (pairs
+    // per workgroup) x (one staged sweep over 2 sb rows, plus staging the
+    // rows through LDS).  Ties within 10 % go to fewer super-blocks (fewer
+    // rounds).  The choice fixes the arithmetic, so every path uses it.
     ShapeCfg best;
     double best_t = 1e300;
     bool found = false;
@@ -250,7 +250,7 @@ int shape_config(int m, int n, ShapeCfg* out) {
         const int ld = pick_ld(cfg);
         task += 8.0 * (2.0 * sb) * (c.ldg / 4);  // staging both blocks in and out
         const int pairs = nsb / 2;
-        const int members = std::min(pairs, kGangPlan);
+        const int members = std::min(pairs, kHelpPlan);
         const double t = (nsb - 1) * (double)((pairs + members - 1) / members) * task;
         for (int tb = 32; tb >= 16; tb -= 16) {
             const size_t lds = lds_bytes_tiled(sb, ncp, ld, c.ldg, tb);
@@ -264,9 +264,22 @@ int shape_config(int m, int n, ShapeCfg* out) {
                     best.nsb = nsb;
                     best.ncp = ncp;
                     best.lds = lds;
-                    best.ws_floats = (size_t)NPLANES * c.nc * c.ldg + (size_t)ncp * c.ldg;
+                    best.ws_floats = (size_t)NPLANES * c.nc * c.ldg + 2 * (size_t)ncp * c.ldg;
                     best_t = t;
                     found = true;
+                    // warm start: the staged rotation rows double the
+                    // staged pair (chunks per lane up to 4, as in LDS)
+                    best.warm_tb = 0;
+                    best.warm_lds = 0;
+                    if (svt_nch(cfg) <= 4 && svt_lpp(cfg) <= 16)
+                        for (int wtb = 32; wtb >= 16; wtb -= 16) {
+                            const size_t wl = lds_bytes_tiled(sb, ncp, ld, c.ldg, wtb, true);
+                            if (wl <= budget) {
+                                best.warm_tb = wtb;
+                                best.warm_lds = wl;
+                                break;
+                            }
+                        }
                 }
                 break;
             }
@@ -364,6 +377,13 @@ int worse(int a, int b) {
     return std::max(a, b);
 }
 
+// Whether a window's SVT is warm-started: svt_mode >= 1 where the rotation
+// fits beside the Jacobi rows (in LDS, or staged with them when tiled; the
+// tiled warm start takes its start product in FP32 only).
+bool warm_level(const tilt_params* prm, const ShapeCfg& sc) {
+    return prm->svt_mode >= 1 && sc.warm_lds > 0 && (sc.sb == 0 || prm->svt_mode == 1);
+}
+
 // Level l of a request: window ceil(m/2^l) x ceil(n/2^l) in an image of
 // ceil(H/2^l) x ceil(W/2^l) pixels.  The workspace holds the solver planes
 // (sized for the largest level) followed by the images of levels 1.. .
@@ -387,8 +407,7 @@ int plan_request(const tilt_problem& pr, const tilt_params* prm, float* A_out, f
         st = shape_config(ml[l], nl[l], &sc[l]);
         if (st != TILT_OK) return st;
         planes = std::max(planes, sc[l].ws_floats);
-        const bool warm = prm->svt_mode >= 1 && sc[l].warm_lds > 0;
-        P.lds = std::max(P.lds, warm ? sc[l].warm_lds : sc[l].lds);
+        P.lds = std::max(P.lds, warm_level(prm, sc[l]) ? sc[l].warm_lds : sc[l].lds);
     }
     size_t off = (planes + 63) & ~(size_t)63;
     size_t img_off[MAX_LEVELS] = {0};
@@ -420,7 +439,7 @@ int plan_request(const tilt_problem& pr, const tilt_params* prm, float* A_out, f
         d.colmajor = sc[l].colmajor;
         d.ld = sc[l].ld;
         d.svt_cfg = sc[l].cfg;
-        d.warm = (prm->svt_mode >= 1 && sc[l].warm_lds > 0) ? prm->svt_mode : 0;
+        d.warm = warm_level(prm, sc[l]) ? prm->svt_mode : 0;
         d.tb = d.warm ? sc[l].warm_tb : sc[l].tb;
         d.sb = sc[l].sb;
         d.nsb = sc[l].nsb;
@@ -665,16 +684,12 @@ int run_plain_request(tilt_ctx* ctx, size_t lds, const SolverParams& sp, int L, 
     return TILT_OK;
 }
 
-// Most workgroups of the fused kernel one tiled window may take:
-// TILT_GANG_MAX from the environment (1 turns gangs off), else kGangPlan.
-// Only who runs which super-block pair depends on it, not the results.
-int gang_max() {
-    const char* e = std::getenv("TILT_GANG_MAX");
-    if (e && *e) {
-        const int v = std::atoi(e);
-        if (v >= 1) return std::min(v, 64);
-    }
-    return kGangPlan;
+// Whether idle workgroups of the fused kernel help windows beyond LDS with
+// their Jacobi rounds: on unless TILT_HELPERS=0 in the environment.  Only
+// who runs which super-block pair depends on it, not the results.
+bool helpers_enabled() {
+    const char* e = std::getenv("TILT_HELPERS");
+    return !(e && e[0] == '0');
 }
 
 int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const tilt_params* prm,
@@ -723,57 +738,49 @@ int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const 
             }
             if (r != TILT_OK) return r;
         } else {
-            if (ctx->queue.reserve(256) != hipSuccess) return TILT_ERR_NOMEM;
-            // Gangs: a request with a tiled level gets up to gang_max()
-            // workgroups for its Jacobi rounds (no more than the pairs of a
-            // round), when the device runs enough workgroups at once.
-            int per_cu = 0;
-            HIP_TRY(fused_blocks_per_cu(max_lds, &per_cu));
-            const int resident = std::max(1, per_cu) * ctx->num_cus;
-            const int gmax = gang_max();
-            std::vector<int> members(nlive, 1);
-            bool gangs = false;
-            for (int k = 0; k < nlive && gmax > 1 && resident >= 4 * gmax; ++k) {
-                for (int l = 0; l < L; ++l)
-                    if (plans[k].d[l].sb > 0) members[k] = std::max(members[k], std::min(gmax, plans[k].d[l].nsb / 2));
-                gangs |= members[k] > 1;
+            // Control blocks: the queue and, for requests with a level whose
+            // SVT is tiled, the block through which idle workgroups help.
+            const size_t fc_bytes = (sizeof(FusedCtl) + 255) & ~(size_t)255;
+            if (ctx->queue.reserve(fc_bytes + sizeof(GangCtl) * nlive) != hipSuccess) return TILT_ERR_NOMEM;
+            FusedCtl* dfc = reinterpret_cast<FusedCtl*>(ctx->queue.p);
+            GangCtl* dgang = reinterpret_cast<GangCtl*>(reinterpret_cast<char*>(ctx->queue.p) + fc_bytes);
+            std::vector<char> blob(fc_bytes + sizeof(GangCtl) * nlive, 0);
+            FusedCtl* hfc = reinterpret_cast<FusedCtl*>(blob.data());
+            GangCtl* hgang = reinterpret_cast<GangCtl*>(blob.data() + fc_bytes);
+            hfc->remaining = nlive;
+            hfc->gangs = dgang;
+            bool any_tiled = false;
+            for (int k = 0; k < nlive; ++k) {
+                hgang[k].slot = -1;
+                hgang[k].fc = dfc;
+                bool tiled = false;
+                for (int l = 0; l < L; ++l) tiled |= plans[k].d[l].sb > 0;
+                if (tiled && helpers_enabled())
+                    for (int l = 0; l < L; ++l) plans[k].d[l].gang = dgang + k;
+                any_tiled |= tiled;
             }
-            if (gangs) {
-                if (ctx->gangs.reserve(sizeof(GangCtl) * nlive) != hipSuccess) return TILT_ERR_NOMEM;
-                HIP_TRY(hipMemsetAsync(ctx->gangs.p, 0, sizeof(GangCtl) * nlive, stream));
+            HIP_TRY(hipMemcpyAsync(ctx->queue.p, blob.data(), blob.size(), hipMemcpyHostToDevice, stream));
+            if (any_tiled && helpers_enabled()) {
                 std::vector<PatchDesc> descs((size_t)L * nlive);
                 for (int k = 0; k < nlive; ++k)
-                    for (int l = 0; l < L; ++l) {
-                        PatchDesc& d = plans[k].d[l];
-                        d.gsize = members[k];
-                        d.gang = members[k] > 1 ? reinterpret_cast<GangCtl*>(ctx->gangs.p) + k : nullptr;
-                        descs[(size_t)k * L + l] = d;
-                    }
+                    for (int l = 0; l < L; ++l) descs[(size_t)k * L + l] = plans[k].d[l];
                 HIP_TRY(hipMemcpyAsync(ctx->descs.p, descs.data(), sizeof(PatchDesc) * L * nlive,
                                        hipMemcpyHostToDevice, stream));
             }
-            // longest predicted solve first (per member of its gang; stable:
-            // equal shapes keep their order), each gang's tickets together
+            if (ctx->order.reserve(sizeof(int) * nlive) != hipSuccess) return TILT_ERR_NOMEM;
+            // longest predicted solve first (stable: equal shapes keep their order)
             std::vector<int> order(nlive);
             for (int k = 0; k < nlive; ++k) order[k] = k;
             std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-                return predicted_cost(plans[a].d[0]) / members[a] > predicted_cost(plans[b].d[0]) / members[b];
+                return predicted_cost(plans[a].d[0]) > predicted_cost(plans[b].d[0]);
             });
-            std::vector<Ticket> tickets;
-            for (int k : order)
-                for (int r = 0; r < members[k]; ++r) tickets.push_back(Ticket{k, r, members[k], 0});
-            const int ntickets = (int)tickets.size();
-            if (ctx->order.reserve(sizeof(Ticket) * ntickets) != hipSuccess) return TILT_ERR_NOMEM;
-            HIP_TRY(hipMemcpyAsync(ctx->order.p, tickets.data(), sizeof(Ticket) * ntickets, hipMemcpyHostToDevice,
-                                   stream));
-            HIP_TRY(hipMemsetAsync(ctx->queue.p, 0, sizeof(int), stream));
-            const int grid = gangs ? std::min(ntickets, resident)
-                                   : std::max(1, std::min(nlive, ctx->num_cus * std::max(1, std::min(per_cu, 2))));
+            HIP_TRY(hipMemcpyAsync(ctx->order.p, order.data(), sizeof(int) * nlive, hipMemcpyHostToDevice, stream));
+            const int per_cu = std::max<int>(1, (int)(LDS_LIMIT / (max_lds + kStaticLdsMargin)));
+            const int grid = std::max(1, std::min(nlive, ctx->num_cus * std::min(per_cu, 2)));
             HIP_TRY(hipEventRecord(ctx->ev0, stream));
             HIP_TRY(launch_fused(reinterpret_cast<const PatchDesc*>(ctx->descs.p),
-                                 reinterpret_cast<PatchState*>(ctx->states.p), sp, ntickets, L,
-                                 reinterpret_cast<const Ticket*>(ctx->order.p), reinterpret_cast<int*>(ctx->queue.p),
-                                 grid, max_lds, gangs, stream));
+                                 reinterpret_cast<PatchState*>(ctx->states.p), sp, nlive, L,
+                                 reinterpret_cast<const int*>(ctx->order.p), dfc, grid, max_lds, stream));
             HIP_TRY(hipEventRecord(ctx->ev1, stream));
         }
         std::vector<PatchState> out(nlive);
@@ -1007,7 +1014,7 @@ void tilt_default_params(tilt_params* p) {
     p->max_outer = 50;
     p->fixed_iters = 0;
     p->svt_mode = 0;
-    p->jacobi_tol = 1e-6f;
+    p->jacobi_tol = 1e-7f;
     p->max_sweeps = 40;
     p->pyramid_levels = 1;
 }
@@ -1125,7 +1132,6 @@ int tilt_ctx_destroy(tilt_ctx* ctx) {
     ctx->jobs.release();
     ctx->counters.release();
     ctx->img.release();
-    ctx->gangs.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;
@@ -1363,7 +1369,7 @@ int tilt_inner_batch(tilt_ctx* ctx, const float* I, const float* J, int count, i
     ShapeCfg sc{};
     st = shape_config(m, n, &sc);
     if (st != TILT_OK) return st;
-    const bool warm = prm->svt_mode >= 1 && sc.warm_lds > 0;
+    const bool warm = prm->svt_mode >= 1 && sc.warm_lds > 0 && sc.sb == 0;
     const size_t lds = warm ? sc.warm_lds : sc.lds;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);

@@ -15,8 +15,9 @@ namespace host {
 
 constexpr int kStaticLdsMargin = 8 * 1024;  // static __shared__ use of the kernels (checked at launch)
 // Workgroups per tiled window the super-block size is planned for (the
-// fused kernel's gangs; see shape_config).
-constexpr int kGangPlan = 4;
+// leader and the idle workgroups that help it in the fused kernel; see
+// shape_config).
+constexpr int kHelpPlan = 4;
 
 // Device buffer that grows on demand.
 struct DevBuf {
@@ -74,7 +75,7 @@ void serve_release(ServeState* s);
 struct tilt_ctx {
     int device = 0;
     size_t budget = 0;
-    tilt::host::DevBuf descs, states, ws, queue, order, scratch, jobs, counters, img, gangs;
+    tilt::host::DevBuf descs, states, ws, queue, order, scratch, jobs, counters, img;
     double wall_rate_khz = 100000.0;  // device wall clock
     int num_cus = 256;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;

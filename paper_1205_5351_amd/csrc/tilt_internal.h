@@ -33,31 +33,41 @@ constexpr int SVT_MAX_ROWS = 256;  // rows of the Jacobi matrix held in LDS at o
 constexpr int SVT_MAX_TILED_ROWS = 1024;  // rows of the working plane (min(m, n) rounded up to whole super-blocks)
 constexpr int SVT_MAX_COLS = 2048;       // max(m, n): 64 lanes x 8 chunks x 4 floats
 
-// A gang is the set of workgroups of the fused kernel that share one
-// window whose SVT is tiled through device memory: the first member (the
-// leader) runs every step of the solve; each Jacobi sweep's super-block
-// pairs are split over all members, one round at a time, with a barrier
-// between rounds.  The control block lives in device memory, one per
-// window, zeroed before the launch.  Counters only grow, so no member ever
-// waits on a value another member has to reset.
-struct alignas(128) GangCtl {
-    int post;            // jobs posted by the leader (a job: one tiled decomposition, or the end)
-    int bar;             // barrier arrivals: barrier b completes when bar reaches (b + 1) * members
-    int rot;             // largest sweep tag in which some pair rotated
-    int end;             // the posted job is the end of the request
-    float* Bg;           // job: working plane (ncp x ldg rows)
-    int sb, nsb, ldg, ld, cfg, max_sweeps;
-    float tol;
+// Helpers for windows whose SVT is tiled through device memory (fused
+// kernel only): the window's leader publishes the rounds of its tiled
+// Jacobi in its GangCtl while workgroups that ran out of work are idle, and
+// those claim super-block pairs of it.  Both blocks live in device memory,
+// zeroed (slot = -1) before the launch.
+constexpr int HELP_SLOTS = 1024;  // registered leaders at once (power of 2, >= workgroups of a launch)
+
+struct GangCtl;
+
+struct FusedCtl {
+    int queue;          // next entry of the order to claim
+    int remaining;      // requests not finished yet
+    int idle;           // workgroups that have left the queue and help
     int pad0;
-    unsigned long long pairs, rotations;  // work of the members in the current job
-    int pad[14];
+    GangCtl* gangs;     // one control block per request
+    int pad[26];
+    int slots[HELP_SLOTS];  // request index + 1 of leaders that publish rounds, 0 = free
 };
 
-// Work-queue entry of the fused kernel: window `idx`, member `rank` of a
-// gang of `members` workgroups (1: the window is solved by one workgroup).
-struct Ticket {
-    int idx, rank, members, pad;
+struct alignas(128) GangCtl {
+    unsigned long long word;  // published round: (id << 32) | (pairs << 16) | pairs claimed
+    int done;                 // pairs finished by helpers (only grows)
+    int rot;                  // largest round id in which a helper's pair rotated
+    float* Bg;                // round: working plane (ncp x ldg Jacobi rows)
+    float* Rg;                // round: rotation rows of a warm-started decomposition, or null
+    int sb, nsb, ldg, ld, cfg, r;
+    float tol;
+    int rid;                  // leader: rounds published so far
+    int slot;                 // leader: its entry in FusedCtl::slots (-1: none yet)
+    int pad0;
+    unsigned long long pairs, rotations;  // helpers' work counts, taken by the leader
+    FusedCtl* fc;
+    int pad[8];
 };
+static_assert(sizeof(GangCtl) == 128, "one control block per 128-byte line");
 
 struct PatchDesc {
     const float* image;
@@ -73,14 +83,15 @@ struct PatchDesc {
     int ncp;                  // tiled SVT: rows of the working plane (nsb * sb >= nc)
     int warm;                 // SVT warm-started from the previous rotation: 1 FP32 start,
                               // 2 bfloat16 start + FP32 refinement, 3 bfloat16 start
-    int gsize;                // workgroups sharing the tiled Jacobi of this window (1: one)
+    int pad1;
     double cx, cy, s;         // scaled coordinates of the level being solved (the
                               // kernels take them from PatchState::geo)
     double lam;
-    float* ws;                // NPLANES planes (+ one ncp x ldg working plane when tiled)
+    float* ws;                // NPLANES planes (+ two ncp x ldg working planes when tiled:
+                              // the Jacobi rows, then the rotation rows of the warm start)
     float* A_out;             // m x n row-major (may be null)
     float* E_out;
-    GangCtl* gang;            // gang control block when gsize > 1 (fused kernel only)
+    GangCtl* gang;            // fused kernel, tiled windows: where helpers find its rounds (else null)
 };
 
 struct PatchState {
@@ -232,13 +243,8 @@ struct ServeCtl {
 };
 
 // Kernel launchers (tilt_kernels.hip).
-// Fused kernel over `ntickets` queue entries; cooperative (every workgroup
-// resident at once) when the tickets form gangs.
-hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int ntickets, int levels,
-                        const Ticket* tickets, int* queue, int grid, size_t lds, bool cooperative, hipStream_t s);
-// Workgroups of the fused kernel one compute unit holds at once with `lds`
-// bytes of dynamic LDS.
-hipError_t fused_blocks_per_cu(size_t lds, int* blocks);
+hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, int levels,
+                        const int* order, FusedCtl* fc, int grid, size_t lds, hipStream_t s);
 hipError_t launch_wide_setup(const PatchDesc* d, PatchState* st, const SolverParams& prm, const float* I,
                              const float* J, int count, size_t lds, hipStream_t s);
 hipError_t launch_wide_stage(const PatchDesc* d, PatchState* st, const int* active, int nactive, int form_m,

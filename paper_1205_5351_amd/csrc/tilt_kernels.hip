@@ -649,6 +649,27 @@ __device__ int jacobi_sweep_dispatch(int cfg, float* B, int nrows, int ld, float
 #undef TILT_SWEEP_CASES8
 #undef TILT_SWEEP_CASE
 
+// One sweep of the warm-started tiled Jacobi: the rotations are applied to
+// the rotation rows Rm as well (same layout as B; chunks per lane up to 4).
+#define TILT_WSWEEP_CASE(S, L, C) \
+    case svt_make_cfg(S, L, C):   \
+        return jacobi_rows<S, L, C, 0, true>(B, Rm, nrows, ld, tol, 1, js);
+#define TILT_WSWEEP_CASES4(S, L) \
+    TILT_WSWEEP_CASE(S, L, 1) TILT_WSWEEP_CASE(S, L, 2) TILT_WSWEEP_CASE(S, L, 3) TILT_WSWEEP_CASE(S, L, 4)
+
+__device__ int jacobi_sweep_dispatch_warm(int cfg, float* B, float* Rm, int nrows, int ld, float tol,
+                                          JacobiStats& js) {
+    switch (cfg) {
+        TILT_WSWEEP_CASES4(1, 4) TILT_WSWEEP_CASES4(1, 8) TILT_WSWEEP_CASES4(1, 16)
+        TILT_WSWEEP_CASES4(2, 4) TILT_WSWEEP_CASES4(2, 8) TILT_WSWEEP_CASES4(2, 16)
+        default:
+            break;
+    }
+    return 0;
+}
+#undef TILT_WSWEEP_CASES4
+#undef TILT_WSWEEP_CASE
+
 // ---------------------------------------------------------------------------
 // Tiled one-sided Jacobi for matrices that do not fit in LDS.
 //
@@ -699,157 +720,266 @@ __device__ inline void superblock_pair(int nsb, int r, int k, int& I, int& J) {
 }
 
 // One super-block pair: stage both blocks into LDS, one full Jacobi sweep
-// over their 2 sb rows, write them back if anything rotated.  Returns 1 if
-// a pair rotated (uniform over the workgroup).
-__device__ int superblock_task(int cfg, float* Bg, int sb, int nsb, int ldg, int ld, float* mini, float tol, int r,
-                               int k, JacobiStats& js) {
+// over their 2 sb rows, write them back if anything rotated.  With Rg (the
+// warm start) the matching rows of the rotation are staged after them and
+// take the same rotations.  Returns 1 if a pair rotated (uniform over the
+// workgroup).
+__device__ int superblock_task(int cfg, float* Bg, float* Rg, int sb, int nsb, int ldg, int ld, float* mini,
+                               float tol, int r, int k, JacobiStats& js) {
     int I, J;
     superblock_pair(nsb, r, k, I, J);
+    float* rmini = mini + 2 * sb * ld;
     load_block(Bg, I * sb, sb, ldg, mini, 0, ld);
     load_block(Bg, J * sb, sb, ldg, mini, sb, ld);
     clear_lds_padding(mini, 2 * sb, ldg, ld);
+    if (Rg) {
+        load_block(Rg, I * sb, sb, ldg, rmini, 0, ld);
+        load_block(Rg, J * sb, sb, ldg, rmini, sb, ld);
+        clear_lds_padding(rmini, 2 * sb, ldg, ld);
+    }
     __syncthreads();
-    const int rot = jacobi_sweep_dispatch(cfg, mini, 2 * sb, ld, tol, js);
+    const int rot = Rg ? jacobi_sweep_dispatch_warm(cfg, mini, rmini, 2 * sb, ld, tol, js)
+                       : jacobi_sweep_dispatch(cfg, mini, 2 * sb, ld, tol, js);
     if (rot) {
         store_block(Bg, I * sb, sb, ldg, mini, 0, ld);
         store_block(Bg, J * sb, sb, ldg, mini, sb, ld);
+        if (Rg) {
+            store_block(Rg, I * sb, sb, ldg, rmini, 0, ld);
+            store_block(Rg, J * sb, sb, ldg, rmini, sb, ld);
+        }
     }
     __syncthreads();
     return rot;
 }
 
 // ---------------------------------------------------------------------------
-// Gangs (several workgroups of the fused kernel on one tiled window).
+// Help for windows beyond LDS inside the fused kernel.
 //
-// Barrier: every member adds 1 to `bar`; barrier b is complete when `bar`
-// reaches (b + 1) * members.  A member can only arrive at barrier b + 1
-// after barrier b completed, so the arrival count alone names the barrier
-// and nothing is ever reset.  Each wave makes its own stores visible at
-// agent scope before the workgroup arrives (the members may sit on
-// different XCDs, each with its own L2), and the arriving thread acquires
-// at agent scope once the barrier completes.
+// A window whose SVT is tiled is solved by one workgroup, its leader, like
+// every other window.  Once the work queue is empty, workgroups with nothing
+// left to solve become helpers.  While helpers are idle, a leader publishes
+// each round of its tiled Jacobi in its control block: the round's
+// parameters, then one 64-bit word (round id, pairs, pairs claimed).  Any
+// helper, and the leader itself, claims a pair by a compare-and-swap on the
+// word and runs it; the leader then waits only for the pairs helpers have
+// claimed.  A round never waits for a helper to arrive, nobody waits on a
+// workgroup that has not claimed work, and the pairs of a round touch
+// disjoint rows, so the result is the same whoever takes which pair.
+// Members may sit on different XCDs (each with its own L2): data goes out
+// with an agent-scope release before a round is published or a finished
+// pair is counted, and comes in with an agent-scope acquire after a claim
+// or the leader's wait.
 // ---------------------------------------------------------------------------
 
 __device__ inline int gang_load(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Returns the barrier's index, the same in every member.
-__device__ int gang_barrier(GangCtl* c, int members) {
-    __shared__ int sh_b;
-    __threadfence();
+__device__ inline void release_all_waves() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const int old = __hip_atomic_fetch_add(&c->bar, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        const int b = old / members;
-        const int target = (b + 1) * members;
-        while (gang_load(&c->bar) < target) __builtin_amdgcn_s_sleep(1);
-        sh_b = b;
-    }
-    __syncthreads();
-    return sh_b;
 }
 
-// The tiled Jacobi of one staged plane, run by every member of the gang
-// with the same arguments: in each round member `rank` takes super-block
-// pairs rank, rank + members, ...  The pairs of one round touch disjoint
-// rows, so the result is the one-workgroup tiled Jacobi's whatever member
-// takes which pair.  A sweep's tag is one more than the index of the
-// barrier before it; a rotating pair raises `rot` to the tag, so after the
-// sweep's last barrier `rot >= tag` tells every member alike whether the
-// sweep rotated (a later sweep can only have started if it did).
-__device__ void gang_jacobi(GangCtl* c, int rank, int members, int cfg, float* Bg, int sb, int nsb, int ldg, int ld,
-                            float* mini, float tol, int max_sweeps, JacobiStats& js) {
-    __shared__ int sh_rot;
+__device__ inline void acquire_all_waves() {
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+constexpr unsigned long long kRoundIdShift = 32;
+
+// Claim the next pair of the published round `w` of c (thread 0 only).
+// Returns the pair index, or -1 if the round is fully claimed or moved on.
+__device__ int gang_try_claim(GangCtl* c, unsigned long long w) {
+    const int pairs = (int)((w >> 16) & 0xffffu), claimed = (int)(w & 0xffffu);
+    if (claimed >= pairs) return -1;
+    unsigned long long expect = w;
+    if (__hip_atomic_compare_exchange_strong(&c->word, &expect, w + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+        return claimed;
+    return -1;
+}
+
+// Leader: the tiled Jacobi of the ncp rows of Bg (with the rotation rows Rg
+// when warm-started), publishing rounds while helpers are idle.  The
+// helpers' pair counts are added to js at the end.
+__device__ void jacobi_tiled_shared(GangCtl* c, int cfg, float* Bg, float* Rg, int sb, int nsb, int ldg, int ld,
+                                    float* mini, float tol, int max_sweeps, JacobiStats& js) {
+    __shared__ int sh_v;
+    const int tid = threadIdx.x;
     const int Nb = nsb - 1, Pb = nsb >> 1;
-    int b = gang_barrier(c, members);  // the staged plane is visible to every member
+    FusedCtl* fc = c->fc;
+    const long long sweeps0 = js.sweeps;  // the staged sweeps of single pairs are not sweeps of the matrix
     int sweeps = 0;
+    int helped = 0;  // pairs run by helpers so far in this decomposition
+    int base_done = 0;
+    if (tid == 0) sh_v = gang_load(&c->done);
+    __syncthreads();
+    base_done = sh_v;
+    __syncthreads();
     for (int sw = 0; sw < max_sweeps; ++sw) {
-        const int tag = b + 1;
+        int any = 0;
+        int first_id = 0;  // id of this sweep's first published round (0: none)
         for (int r = 0; r < Nb; ++r) {
-            JacobiStats jr{0, 0, 0};
-            int rot = 0;
-            for (int k = rank; k < Pb; k += members)
-                rot |= superblock_task(cfg, Bg, sb, nsb, ldg, ld, mini, tol, r, k, jr);
-            if (threadIdx.x == 0) {
-                if (rot) atomicMax(&c->rot, tag);
-                if (jr.pairs) atomicAdd(&c->pairs, (unsigned long long)jr.pairs);
-                if (jr.rotations) atomicAdd(&c->rotations, (unsigned long long)jr.rotations);
+            if (tid == 0) sh_v = (Pb > 1 && gang_load(&fc->idle) > 0) ? 1 : 0;
+            __syncthreads();
+            const int publish = sh_v;
+            __syncthreads();
+            if (!publish) {
+                for (int k = 0; k < Pb; ++k) any |= superblock_task(cfg, Bg, Rg, sb, nsb, ldg, ld, mini, tol, r, k, js);
+                continue;
             }
-            b = gang_barrier(c, members);
+            release_all_waves();
+            if (tid == 0) {
+                if (c->slot < 0) {
+                    // register where helpers look (once per request)
+                    const int idx = (int)(c - fc->gangs);
+                    for (int i = 0; i < HELP_SLOTS; ++i) {
+                        const int sl = (idx + i) & (HELP_SLOTS - 1);
+                        int zero = 0;
+                        if (__hip_atomic_compare_exchange_strong(&fc->slots[sl], &zero, idx + 1, __ATOMIC_RELAXED,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                            c->slot = sl;
+                            break;
+                        }
+                    }
+                }
+                c->Bg = Bg;
+                c->Rg = Rg;
+                c->sb = sb;
+                c->nsb = nsb;
+                c->ldg = ldg;
+                c->ld = ld;
+                c->cfg = cfg;
+                c->r = r;
+                c->tol = tol;
+                const unsigned id = (unsigned)(++c->rid);
+                __hip_atomic_store(&c->word, ((unsigned long long)id << kRoundIdShift) | ((unsigned long long)Pb << 16),
+                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                sh_v = (int)id;
+            }
+            __syncthreads();
+            const int id = sh_v;
+            if (!first_id) first_id = id;
+            __syncthreads();
+            int mine = 0;
+            for (;;) {
+                if (tid == 0) {
+                    int k = -1;
+                    for (;;) {
+                        const unsigned long long w =
+                            __hip_atomic_load(&c->word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if ((w & 0xffffu) >= ((w >> 16) & 0xffffu)) break;
+                        k = gang_try_claim(c, w);
+                        if (k >= 0) break;
+                    }
+                    sh_v = k;
+                }
+                __syncthreads();
+                const int k = sh_v;
+                __syncthreads();
+                if (k < 0) break;
+                any |= superblock_task(cfg, Bg, Rg, sb, nsb, ldg, ld, mini, tol, r, k, js);
+                ++mine;
+            }
+            helped += Pb - mine;
+            if (tid == 0)
+                while (gang_load(&c->done) < base_done + helped) __builtin_amdgcn_s_sleep(1);
+            acquire_all_waves();
         }
         ++sweeps;
-        if (threadIdx.x == 0) sh_rot = gang_load(&c->rot) >= tag;
+        // a helper's pair that rotated raised `rot` to its round's id
+        if (tid == 0) sh_v = any || (first_id > 0 && gang_load(&c->rot) >= first_id);
         __syncthreads();
-        const int any = sh_rot;
+        const int rotated = sh_v;
         __syncthreads();
-        if (!any) break;
+        if (!rotated) break;
     }
-    js.sweeps += sweeps;
+    js.sweeps = sweeps0 + sweeps;
+    if (tid == 0 && helped > 0) {
+        // every helper added its counts before counting its pair done
+        js.pairs += (long long)__hip_atomic_exchange(&c->pairs, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        js.rotations += (long long)__hip_atomic_exchange(&c->rotations, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
-// Leader: post one job (a decomposition of the staged plane Bg, or the end
-// of the request) to the other members.
-__device__ void gang_post(GangCtl* c, int end, int cfg, float* Bg, int sb, int nsb, int ldg, int ld, float tol,
-                          int max_sweeps) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        c->end = end;
-        c->Bg = Bg;
-        c->sb = sb;
-        c->nsb = nsb;
-        c->ldg = ldg;
-        c->ld = ld;
-        c->cfg = cfg;
-        c->tol = tol;
-        c->max_sweeps = max_sweeps;
-        __hip_atomic_fetch_add(&c->post, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-}
-
-// Member rank > 0: take part in every decomposition the leader posts until
-// it posts the end of the request.
-__device__ void gang_member(GangCtl* c, int rank, int members, float* mini) {
+// Helper: find a published round with an unclaimed pair among the
+// registered leaders, claim it and run it; returns 0 when nothing was open.
+__device__ int help_once(FusedCtl* fc, float* mini) {
+    __shared__ int sh_g, sh_k;
+    __shared__ unsigned sh_id;
     __shared__ GangCtl sh_job;
-    for (int seen = 0;; ++seen) {
-        if (threadIdx.x == 0) {
-            while (gang_load(&c->post) <= seen) __builtin_amdgcn_s_sleep(2);
-            sh_job.end = c->end;
-            sh_job.Bg = c->Bg;
-            sh_job.sb = c->sb;
-            sh_job.nsb = c->nsb;
-            sh_job.ldg = c->ldg;
-            sh_job.ld = c->ld;
-            sh_job.cfg = c->cfg;
-            sh_job.tol = c->tol;
-            sh_job.max_sweeps = c->max_sweeps;
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        // wave 0 scans the slots, 64 at a time, from a start that differs
+        // between workgroups
+        const int start = (int)((blockIdx.x * 97u) & (HELP_SLOTS - 1));
+        int found = -1;
+        for (int base = 0; base < HELP_SLOTS && found < 0; base += 64) {
+            const int sl = (start + base + tid) & (HELP_SLOTS - 1);
+            const int v = __hip_atomic_load(&fc->slots[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bool open = false;
+            if (v > 0) {
+                const unsigned long long w =
+                    __hip_atomic_load(&fc->gangs[v - 1].word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                open = (w & 0xffffu) < ((w >> 16) & 0xffffu);
+            }
+            const unsigned long long bal = __ballot(open);
+            if (bal) {
+                const int lane = __ffsll((long long)bal) - 1;
+                found = __shfl(v, lane) - 1;
+            }
         }
-        __syncthreads();
-        const GangCtl job = sh_job;
-        __syncthreads();
-        if (job.end) break;
-        JacobiStats js{0, 0, 0};
-        gang_jacobi(c, rank, members, job.cfg, job.Bg, job.sb, job.nsb, job.ldg, job.ld, mini, job.tol,
-                    job.max_sweeps, js);
+        if (tid == 0) {
+            sh_g = found;
+            sh_k = -1;
+            if (found >= 0) {
+                GangCtl* c = fc->gangs + found;
+                const unsigned long long w = __hip_atomic_load(&c->word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                // parameters of the round named by w: valid if the claim below
+                // succeeds (a newer round is published only after every pair
+                // of this one was claimed and finished)
+                sh_job.Bg = c->Bg;
+                sh_job.Rg = c->Rg;
+                sh_job.sb = c->sb;
+                sh_job.nsb = c->nsb;
+                sh_job.ldg = c->ldg;
+                sh_job.ld = c->ld;
+                sh_job.cfg = c->cfg;
+                sh_job.r = c->r;
+                sh_job.tol = c->tol;
+                sh_id = (unsigned)(w >> kRoundIdShift);
+                sh_k = gang_try_claim(c, w);
+            }
+        }
     }
+    __syncthreads();
+    const int g = sh_g, k = sh_k;
+    if (g < 0 || k < 0) {
+        __syncthreads();
+        return 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    GangCtl* c = fc->gangs + g;
+    JacobiStats jr{0, 0, 0};
+    const int rot = superblock_task(sh_job.cfg, sh_job.Bg, sh_job.Rg, sh_job.sb, sh_job.nsb, sh_job.ldg, sh_job.ld,
+                                    mini, sh_job.tol, sh_job.r, k, jr);
+    release_all_waves();
+    if (tid == 0) {
+        if (rot) atomicMax(&c->rot, (int)sh_id);
+        if (jr.pairs) atomicAdd(&c->pairs, (unsigned long long)jr.pairs);
+        if (jr.rotations) atomicAdd(&c->rotations, (unsigned long long)jr.rotations);
+        __hip_atomic_fetch_add(&c->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    return 1;
 }
 
-// The tiled Jacobi of the ncp rows of Bg: on this workgroup alone, or, for
-// a gang, posted to the other members and run together with them (the
-// leader then adds their pair counts to its own).
-__device__ void jacobi_tiled(int cfg, float* Bg, int sb, int nsb, int ldg, int ld, float* mini, float tol,
-                             int max_sweeps, JacobiStats& js, GangCtl* gang = nullptr, int members = 1) {
-    if (gang && members > 1) {
-        gang_post(gang, 0, cfg, Bg, sb, nsb, ldg, ld, tol, max_sweeps);
-        gang_jacobi(gang, 0, members, cfg, Bg, sb, nsb, ldg, ld, mini, tol, max_sweeps, js);
-        if (threadIdx.x == 0) {
-            // every member added its counts before the last barrier, and no
-            // member adds again before the next job is posted
-            js.pairs += (long long)__hip_atomic_exchange(&gang->pairs, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            js.rotations +=
-                (long long)__hip_atomic_exchange(&gang->rotations, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+// The tiled Jacobi of the ncp rows of Bg (with the rotation rows Rg when
+// warm-started) on this workgroup, with helpers when `gang` is given.
+__device__ void jacobi_tiled(int cfg, float* Bg, float* Rg, int sb, int nsb, int ldg, int ld, float* mini, float tol,
+                             int max_sweeps, JacobiStats& js, GangCtl* gang = nullptr) {
+    if (gang) {
+        jacobi_tiled_shared(gang, cfg, Bg, Rg, sb, nsb, ldg, ld, mini, tol, max_sweeps, js);
         return;
     }
     const int Nb = nsb - 1, Pb = nsb >> 1;
@@ -858,7 +988,7 @@ __device__ void jacobi_tiled(int cfg, float* Bg, int sb, int nsb, int ldg, int l
     for (int sw = 0; sw < max_sweeps; ++sw) {
         int any = 0;
         for (int r = 0; r < Nb; ++r)
-            for (int k = 0; k < Pb; ++k) any |= superblock_task(cfg, Bg, sb, nsb, ldg, ld, mini, tol, r, k, js);
+            for (int k = 0; k < Pb; ++k) any |= superblock_task(cfg, Bg, Rg, sb, nsb, ldg, ld, mini, tol, r, k, js);
         ++sweeps;
         if (!any) break;
     }
@@ -1047,15 +1177,16 @@ __device__ inline SvtLds carve_lds(float* base, int nc, int ld, int tb) {
     return L;
 }
 
-// Tiled SVT: the staged super-block pair (2 sb rows of stride ld) and the
-// reconstruction blocks (tb rows of stride ldg, ncp x tb products) share
-// the front of LDS; the per-row arrays follow.
-__device__ inline SvtLds carve_lds_tiled(float* base, int sb, int ncp, int ld, int ldg, int tb) {
+// Tiled SVT: the staged super-block pair (2 sb rows of stride ld, followed
+// by their 2 sb rotation rows when warm-started) and the reconstruction
+// blocks (tb rows of stride ldg, ncp x tb products) share the front of LDS;
+// the per-row arrays follow.
+__device__ inline SvtLds carve_lds_tiled(float* base, int sb, int ncp, int ld, int ldg, int tb, bool warm) {
     SvtLds L;
     L.B = base;
     L.xblk = base;
     L.cwt = L.xblk + tb * ldg;
-    const int front = max(2 * sb * ld, tb * ldg + ncp * tb);
+    const int front = max((warm ? 4 : 2) * sb * ld, tb * ldg + ncp * tb);
     L.s2 = base + front;
     L.w = L.s2 + ncp;
     L.act = reinterpret_cast<int*>(L.w + ncp);
@@ -1109,7 +1240,7 @@ __device__ void svd_rows(const PatchDesc& d, const float* X, float* Bg, const Sv
             reinterpret_cast<float4*>(Bg + (size_t)row * d.ldg)[c] = v;
         }
         __syncthreads();
-        jacobi_tiled(d.svt_cfg, Bg, d.sb, d.nsb, d.ldg, d.ld, L.B, tol, max_sweeps, js, d.gang, d.gsize);
+        jacobi_tiled(d.svt_cfg, Bg, nullptr, d.sb, d.nsb, d.ldg, d.ld, L.B, tol, max_sweeps, js, d.gang);
         row_norms_global(Bg, d.nc, d.ldg, L.s2);
     } else {
         load_rows_lds(X, d.nc, d.ldg, d.ld, L.B);
@@ -1118,7 +1249,8 @@ __device__ void svd_rows(const PatchDesc& d, const float* X, float* Bg, const Sv
 }
 
 __device__ inline SvtLds carve_for(const PatchDesc& d, float* lds) {
-    return d.sb > 0 ? carve_lds_tiled(lds, d.sb, d.ncp, d.ld, d.ldg, d.tb) : carve_lds(lds, d.nc, d.ld, d.tb);
+    return d.sb > 0 ? carve_lds_tiled(lds, d.sb, d.ncp, d.ld, d.ldg, d.tb, d.warm != 0)
+                    : carve_lds(lds, d.nc, d.ld, d.tb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1787,6 +1919,36 @@ __device__ void save_rotation(const float* Rl, int ld, int nc, float* V, int ldg
     __syncthreads();
 }
 
+// Tiled matrices: the rotation is an ncp x ldg device plane whose first nc
+// rows and columns hold R; everything else stays zero (padding rows of the
+// Jacobi matrix are zero and never rotate, so their rotation rows never
+// change).
+__device__ void rotation_identity_global(float* Rg, int nc, int ncp, int ldg) {
+    for (size_t e = threadIdx.x; e < (size_t)ncp * ldg; e += NT) {
+        const int i = (int)(e / ldg), j = (int)(e - (size_t)i * ldg);
+        Rg[e] = (i == j && i < nc) ? 1.f : 0.f;
+    }
+    __syncthreads();
+}
+
+// R <- 1.5 R - 0.5 (R R^T) R on the rotation plane: G = R R^T into the
+// device plane G, T = G R into T (both nc x nc, stride ldg).
+__device__ void newton_schulz_global(float* Rg, int nc, int ldg, float* G, float* T, float* unused) {
+    (void)unused;
+    mfma_gemm<true>(Rg, ldg, nc, Rg, ldg, nc, nc, G, ldg);
+    __threadfence_block();
+    __syncthreads();
+    mfma_gemm<false>(G, ldg, nc, Rg, ldg, nc, nc, T, ldg);
+    __threadfence_block();
+    __syncthreads();
+    for (int e = threadIdx.x; e < nc * nc; e += NT) {
+        const int i = e / nc, j = e - i * nc;
+        const size_t o = (size_t)i * ldg + j;
+        Rg[o] = fmaf(-0.5f, T[o], 1.5f * Rg[o]);
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // A-update: M = A - R - Y/mu, A <- S_{1/mu}(M)
 // ---------------------------------------------------------------------------
@@ -1835,7 +1997,7 @@ __device__ void svt_finish(const PatchDesc& d, PatchState* st, const SvtLds& L, 
     double nuc;
     shrink_weights(L.s2, nc, eps, L.w, L.act, &k, &nuc);
     float dA[1];
-    dA[0] = d.sb > 0 && !d.warm
+    dA[0] = d.sb > 0
                 ? reconstruct(Bg, ldg, M, A, nc, nr4, ldg, L.w, L.act, k, d.tb, L.xblk, L.cwt, true)
                 : reconstruct(L.B, ld, M, A, nc, nr4, ldg, L.w, L.act, k, d.tb, L.xblk, L.cwt, true);
     block_sum_f<1>(dA);
@@ -1860,11 +2022,30 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
     const bool warm = d.warm != 0;
     float* Bg = d.ws + NPLANES * np;
     float* Rl = nullptr;
-    const SvtLds L = warm ? carve_lds_warm(lds, nc, ld, d.tb, &Rl) : carve_for(d, lds);
+    const SvtLds L = (warm && !tiled) ? carve_lds_warm(lds, nc, ld, d.tb, &Rl) : carve_for(d, lds);
 
     svt_form_m(d, st, (!tiled && !warm) ? L.B : nullptr);
     JacobiStats js{0, 0, 0};
-    if (warm) {
+    if (warm && tiled) {
+        // The rotation lives in its own working plane (ncp rows, so that it
+        // is staged by super-blocks with the Jacobi rows).
+        float* Rg = Bg + (size_t)d.ncp * ldg;
+        const bool saved = st->warm_ok != 0;
+        __syncthreads();
+        if (!saved) rotation_identity_global(Rg, nc, d.ncp, ldg);
+        else if (prm.ns_every > 0 && st->warm_count % prm.ns_every == 0)
+            newton_schulz_global(Rg, nc, ldg, d.ws + (PL_Q + 6) * np, d.ws + (PL_Q + 7) * np, Bg);
+        // B = R M into the Jacobi rows (rows nc.. of Bg stay zero)
+        mfma_gemm<false>(Rg, ldg, nc, M, ldg, ldg, nc, Bg, ldg);
+        for (int e = threadIdx.x; e < (d.ncp - nc) * ldg; e += NT) Bg[(size_t)nc * ldg + e] = 0.f;
+        __syncthreads();
+        jacobi_tiled(d.svt_cfg, Bg, Rg, d.sb, d.nsb, ldg, ld, L.B, prm.jacobi_tol, prm.max_sweeps, js, d.gang);
+        row_norms_global(Bg, nc, ldg, L.s2);
+        if (threadIdx.x == 0) {
+            st->warm_ok = 1;
+            st->warm_count += 1;
+        }
+    } else if (warm) {
         float* V = d.ws + PL_V * np;
         const bool saved = st->warm_ok != 0;
         load_rotation(Rl, ld, nc, V, ldg, saved);
@@ -2271,38 +2452,43 @@ __device__ void solve_request(const PatchDesc* dl, int levels, PatchState* st, c
     if (threadIdx.x == 0) st->t_end = (long long)wall_clock64();
 }
 
-// Persistent solver: each workgroup takes the next ticket from the queue
-// (tickets are in the order of the predicted solve, longest first) until
-// the queue is exhausted.  A ticket names a request and the workgroup's
-// rank in the request's gang: rank 0 solves the request (request i has its
-// level descriptors at descs[i * levels ...]); ranks above 0 join its tiled
-// Jacobi sweeps until the leader posts the end.  The tickets of one gang
-// are consecutive, so only the gang at the head of the queue can be
-// incomplete; every other workgroup that holds a ticket finishes its work
-// and claims the next one, so that gang completes as long as it has no more
-// members than workgroups run at once (the launch is cooperative when there
-// are gangs).
+// Persistent solver: each workgroup takes the next request from the queue
+// (in the order given by `order`, longest predicted solve first) until the
+// queue is exhausted, then helps the leaders of windows beyond LDS with
+// their Jacobi rounds until every request is finished.  Request i has its
+// level descriptors at descs[i * levels ...].
 __global__ void __launch_bounds__(NT) k_fused(const PatchDesc* __restrict__ descs, PatchState* states,
-                                               SolverParams prm, int ntickets, int levels,
-                                               const Ticket* __restrict__ tickets, int* queue) {
-    __shared__ Ticket sh_t;
+                                               SolverParams prm, int count, int levels,
+                                               const int* __restrict__ order, FusedCtl* fc) {
+    __shared__ int sh_idx;
     float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
     for (;;) {
         if (threadIdx.x == 0) {
-            const int q = atomicAdd(queue, 1);
-            sh_t = q < ntickets ? tickets[q] : Ticket{-1, 0, 1, 0};
+            const int q = atomicAdd(&fc->queue, 1);
+            sh_idx = q < count ? order[q] : count;
         }
         __syncthreads();
-        const Ticket t = sh_t;
+        const int idx = sh_idx;
         __syncthreads();
-        if (t.idx < 0) break;
-        const PatchDesc* dl = descs + (size_t)t.idx * levels;
-        if (t.rank > 0) {
-            gang_member(dl[0].gang, t.rank, t.members, lds);
-            continue;
+        if (idx >= count) break;
+        const PatchDesc* dl = descs + (size_t)idx * levels;
+        solve_request(dl, levels, states + idx, prm, lds);
+        if (threadIdx.x == 0) {
+            GangCtl* c = dl[0].gang;
+            if (c && c->slot >= 0)
+                __hip_atomic_store(&fc->slots[c->slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&fc->remaining, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
-        solve_request(dl, levels, states + t.idx, prm, lds);
-        if (t.members > 1) gang_post(dl[0].gang, 1, 0, nullptr, 0, 0, 0, 0, 0.f, 0);
+    }
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(&fc->idle, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        if (help_once(fc, lds)) continue;
+        if (threadIdx.x == 0) sh_idx = gang_load(&fc->remaining);
+        __syncthreads();
+        const int left = sh_idx;
+        __syncthreads();
+        if (left <= 0) break;
+        __builtin_amdgcn_s_sleep(8);
     }
 }
 
@@ -2811,23 +2997,12 @@ static hipError_t set_lds(const void* fn, size_t lds) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int ntickets, int levels,
-                        const Ticket* tickets, int* queue, int grid, size_t lds, bool cooperative, hipStream_t s) {
+hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, int levels,
+                        const int* order, FusedCtl* fc, int grid, size_t lds, hipStream_t s) {
     hipError_t e = set_lds((const void*)k_fused, lds);
     if (e != hipSuccess) return e;
-    if (!cooperative) {
-        hipLaunchKernelGGL(k_fused, dim3(grid), dim3(NT), lds, s, d, st, prm, ntickets, levels, tickets, queue);
-        return hipGetLastError();
-    }
-    void* args[] = {(void*)&d, (void*)&st, (void*)&prm, (void*)&ntickets, (void*)&levels, (void*)&tickets,
-                    (void*)&queue};
-    return hipLaunchCooperativeKernel((const void*)k_fused, dim3(grid), dim3(NT), args, (unsigned)lds, s);
-}
-
-hipError_t fused_blocks_per_cu(size_t lds, int* blocks) {
-    hipError_t e = set_lds((const void*)k_fused, lds);
-    if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, (const void*)k_fused, NT, lds);
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(NT), lds, s, d, st, prm, count, levels, order, fc);
+    return hipGetLastError();
 }
 
 hipError_t launch_serve(ServeCtl* ctl, ServeSlot* slots, PatchDesc* ddesc, PatchState* dstates,
