@@ -160,12 +160,23 @@ def _oracle_worker(args):
         r, _ = O.pyramid.tilt_solve_pyramid(p.image, p.tau0, p.m, p.n, p.model, O.Params(**prm_kw), levels=levels)
     else:
         r = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, O.Params(**prm_kw), lam=p.lam)
-    return time.perf_counter() - t0, r.outer_iters, sum(r.inner_iters)
+    return {"idx": idx, "seconds": time.perf_counter() - t0, "outer": r.outer_iters, "inner": sum(r.inner_iters),
+            "tau": r.tau_px.tolist(), "objective": r.objective}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(cfg, indices, prm_kw, workers):
-    """The FP64 oracle on host cores: one patch per worker process, one BLAS
-    thread each."""
+    """The FP64 oracle on host cores: one patch per task, one worker process
+    per core, one BLAS thread each."""
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[k] = "1"
     ctx = mp.get_context("spawn")
@@ -176,6 +187,48 @@ def cpu_baseline(cfg, indices, prm_kw, workers):
     return wall, out
 
 
+def cold_jacobi_work(res, p):
+    """Section-8(d) work of the cold one-sided Jacobi of one patch's solve:
+    6 S m n^2 flops and 8 S m n^2 LDS bytes per SVD of an m x n matrix
+    (n = min side) after S sweeps, i.e. 6 and 8 x m n^2 per sweep summed
+    over all the patch's sweeps (pyramid levels counted at the level-0
+    shape, an upper bound)."""
+    nr, nc = max(p.m, p.n), min(p.m, p.n)
+    sweeps = res["counters"]["jacobi_sweeps"]
+    return 6.0 * nr * nc * nc * sweeps, 8.0 * nr * nc * nc * sweeps
+
+
+class Progress:
+    """Prints the finished-request count of a long fused launch every
+    `period` seconds (read from the device by tilt_ctx_progress), so a
+    watcher sees the batch advance."""
+
+    def __init__(self, ctx, label, period=20.0):
+        import threading
+
+        self.ctx, self.label, self.period = ctx, label, period
+        self.stop = threading.Event()
+        self.t0 = time.perf_counter()
+        self.th = threading.Thread(target=self.run, daemon=True)
+
+    def run(self):
+        while not self.stop.wait(self.period):
+            try:
+                done, total = self.ctx.progress()
+            except Exception:  # noqa: BLE001 - progress is best effort
+                return
+            if total:
+                log(f"{self.label}: {done}/{total} requests finished after {time.perf_counter() - self.t0:.0f} s")
+
+    def __enter__(self):
+        self.th.start()
+        return self
+
+    def __exit__(self, *exc):
+        self.stop.set()
+        self.th.join()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,10 +237,12 @@ def main():
     ap.add_argument("--workload", type=int, default=1, help="workload index in tilt_synth (default 1)")
     ap.add_argument("--patches", type=int, default=None, help="number of patches (default: all)")
     ap.add_argument("--plain-sample", type=int, default=8, help="patches re-solved by the plain path")
-    ap.add_argument("--cpu-sample", type=int, default=4, help="patches solved by the CPU oracle")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="patches solved by the CPU oracle (default: one per host core)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--svt-mode", type=int, default=0, choices=(0, 1),
-                    help="0: cold Jacobi SVT every iteration (the workload's definition); 1: warm start")
+    ap.add_argument("--svt-mode", type=int, default=None, choices=(0, 1),
+                    help="0: cold Jacobi SVT every iteration; 1: warm start (default: the workload's definition, "
+                         "cold for workload 1, warm for workload 2)")
     ap.add_argument("--pyramid", type=int, default=1, help="pyramid levels (1 = none)")
     ap.add_argument("--serve", action="store_true",
                     help="serving mode: Poisson arrivals through tilt_submit/tilt_poll (workload 4 by default)")
@@ -253,6 +308,8 @@ def main():
         return convergence_main(args)
     dev = torch.device("cuda:0")
     names = ts.config_names()
+    if args.svt_mode is None:
+        args.svt_mode = 1 if args.workload == 2 else 0
     t_gen = time.perf_counter()
     patches = ts.make_config(args.workload, count=args.patches)
     log(f"generated {len(patches)} patches of '{names[args.workload]}' in {time.perf_counter() - t_gen:.1f}s")
@@ -280,25 +337,35 @@ def main():
         del src, dst
 
     for w in range(args.warmup):
-        rc, res = ctx.solve_batch(probs, prm, Ap, Ep, stream)
+        with Progress(ctx, f"warmup {w}"):
+            rc, res = ctx.solve_batch(probs, prm, Ap, Ep, stream)
         log(f"warmup {w}: rc={rc} kernel {ctx.last_kernel_ms():.1f} ms")
 
     kernel_ms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        rc, res = ctx.solve_batch(probs, prm, Ap, Ep, stream)
+        with Progress(ctx, f"step {k}"):
+            rc, res = ctx.solve_batch(probs, prm, Ap, Ep, stream)
         kernel_ms.append(ctx.last_kernel_ms())
         log(f"step {k}: rc={rc} kernel {kernel_ms[-1]:.1f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1000.0 * wall / args.steps
     statuses = [r["status"] for r in res]
-    n_ok = sum(1 for s in statuses if s >= 0)
+    outer_all = [r["outer_iters"] for r in res]
+    # rectified: the solve finished normally, every inner loop met Cond1 and
+    # Cond2 (no TILT_WARN_MAXITER) and the outer loop stopped on its own
+    # before max_outer
+    rectified = [s == 0 and o < prm.max_outer for s, o in zip(statuses, outer_all)]
+    n_ok = sum(rectified)
 
-    # Agreement with the plain (step-by-step) GPU path on a spread sample.
-    S = min(args.plain_sample, len(patches))
-    sample = sorted(set(int(round(i * (len(patches) - 1) / max(S - 1, 1))) for i in range(S))) if S > 0 else []
+    # Agreement with the plain (step-by-step) GPU path on a spread sample
+    # (on the uneven workload among windows of at most 96x96 pixels: the
+    # plain path drives each Jacobi round of a tiled window from the host)
+    cand = [i for i in range(len(patches)) if args.workload != 2 or patches[i].m * patches[i].n <= 96 * 96]
+    S = min(args.plain_sample, len(cand))
+    sample = sorted(set(cand[int(round(i * (len(cand) - 1) / max(S - 1, 1)))] for i in range(S))) if S > 0 else []
     errs, plain_s, bitwise = [], 0.0, 0
     agree = 1.0
     if sample:
@@ -318,34 +385,74 @@ def main():
     done_ms = np.array([r["done_ms"] for r in res])
 
     flops = sum(solve_flops(r, p, warm=args.svt_mode == 1) for r, p in zip(res, patches))
+    jac = [cold_jacobi_work(r, p) for r, p in zip(res, patches)]
+    jac_flops = sum(f for f, _ in jac)
+    jac_lds = sum(b for _, b in jac)
+    mfma_flops = (sum(2.0 * min(p.m, p.n) ** 2 * max(p.m, p.n) * r["counters"]["svt_calls"]
+                      for r, p in zip(res, patches)) if args.svt_mode == 1 else 0.0)
     # attainable FP32 vector rate of this build (no packed FP32), measured
     # after the timed region by a probe kernel of a few ms
     fma_peak = measure_peak(T, torch, "fp32_fma", reps=3, nbytes=8 << 20)
     k_ms = float(np.mean(kernel_ms))
-    achieved = flops / (k_ms * 1e-3) / 1e12
-    outer = np.array([r["outer_iters"] for r in res])
+    achieved = jac_flops / (k_ms * 1e-3) / 1e12
+    achieved_counted = flops / (k_ms * 1e-3) / 1e12
+    lds_tbs = jac_lds / (k_ms * 1e-3) / 1e12
+    outer = np.array(outer_all)
     inner = np.array([r["inner_iters_total"] for r in res])
     sweeps = sum(r["counters"]["jacobi_sweeps"] for r in res) / max(sum(r["counters"]["svt_calls"] for r in res), 1)
 
     cpu = None
-    if not args.no_cpu and args.cpu_sample > 0:
-        idx = (sample or list(range(len(patches))))[: args.cpu_sample]
+    oracle_check = None
+    if not args.no_cpu:
+        cores = len(os.sched_getaffinity(0))
+        n_cpu = args.cpu_sample if args.cpu_sample is not None else cores
+        # spread over the batch; on the uneven workload only windows of at
+        # most 96 x 96 pixels, so the FP64 oracle sample stays at tens of
+        # CPU-seconds
+        pool_idx = [i for i in range(len(patches))
+                    if args.workload != 2 or patches[i].m * patches[i].n <= 96 * 96]
+        step = max(1, len(pool_idx) // max(n_cpu, 1))
+        idx = pool_idx[::step][:n_cpu]
         prm_kw = dict(eps1=prm.eps1, eps2=prm.eps2, eps_outer=prm.eps_outer, mu0=prm.mu0, rho0=prm.rho0,
                       mu_max=prm.mu_max, max_inner=prm.max_inner, max_outer=prm.max_outer,
                       levels=args.pyramid)
-        workers = len(idx)
-        log(f"CPU oracle on {len(idx)} patches with {workers} worker processes ...")
+        workers = min(cores, len(idx))
+        log(f"CPU oracle on {len(idx)} patches with {workers} worker processes ({cores} cores) ...")
         cwall, cout = cpu_baseline(args.workload, idx, prm_kw, workers)
+        secs = np.array([c["seconds"] for c in cout])
         cpu = {
             "value": round(len(idx) / cwall, 4),
             "unit": "patches/s",
             "cores": workers,
             "kind": "oracle",
-            "sample": (f"{len(idx)} of the {n_patches} patches (indices {idx}), FP64 NumPy oracle with "
-                       f"the same parameters, one process and one BLAS thread per patch; "
-                       f"{sum(c[0] for c in cout):.1f} CPU-s in {cwall:.1f} s wall"),
+            "cpu_model": cpu_model(),
+            "host_cores": cores,
+            "patch_s_p50": round(float(np.percentile(secs, 50)), 3),
+            "patch_s_p99": round(float(np.percentile(secs, 99)), 3),
+            "outer_mean": round(float(np.mean([c["outer"] for c in cout])), 2),
+            "inner_total_mean": round(float(np.mean([c["inner"] for c in cout])), 1),
+            "inner_total_max": int(max(c["inner"] for c in cout)),
+            "sample": (f"{len(idx)} of the {n_patches} patches (indices {idx}"
+                       + ("; windows of at most 96x96 px" if args.workload == 2 else "")
+                       + f"), FP64 NumPy oracle with the same parameters, one process per core and one BLAS "
+                       f"thread each; {secs.sum():.1f} CPU-s in {cwall:.1f} s wall"),
         }
         log(f"CPU oracle: {cpu['value']} patches/s")
+        # the oracle gate: tau of the device result against the oracle on
+        # the sampled patches whose outer loops both converged
+        errs_o, obj_o, nconv = [], [], 0
+        for c in cout:
+            i = c["idx"]
+            if res[i]["outer_iters"] < prm.max_outer and c["outer"] < prm.max_outer:
+                nconv += 1
+                errs_o.append(tau_rel_err(res[i]["tau"], np.array(c["tau"]), patches[i].tau0, patches[i].m,
+                                          patches[i].n))
+                obj_o.append(abs(res[i]["objective"] - c["objective"]) / c["objective"])
+        oracle_check = {"sample": len(cout), "both_converged": nconv,
+                        "within_1e-4": (sum(1 for e in errs_o if e <= 1e-4) / nconv) if nconv else None,
+                        "max_tau_rel_err": max(errs_o) if errs_o else None,
+                        "max_objective_rel_err": max(obj_o) if obj_o else None}
+        log(f"oracle check: {oracle_check}")
 
     p0 = patches[0]
     out = {
@@ -382,11 +489,15 @@ def main():
         },
         "plain_check": {"sample": len(sample), "within_1e-4": agree, "bitwise_equal": bitwise,
                         "max_tau_rel_err": max(errs) if errs else None},
+        "oracle_check": oracle_check,
         "work": {"outer_mean": float(outer.mean()), "inner_total_mean": float(inner.mean()),
                  "inner_total_max": int(inner.max()), "jacobi_sweeps_per_svd": round(sweeps, 2),
-                 "status_ok": n_ok, "status_maxiter": sum(1 for s in statuses if s == 1)},
+                 "rectified": n_ok, "status_ok": sum(1 for s in statuses if s == 0),
+                 "status_maxiter": sum(1 for s in statuses if s == 1),
+                 "outer_at_max": int(np.sum(outer >= prm.max_outer)),
+                 "errors": sum(1 for s in statuses if s < 0)},
         "roofline": {
-            "kernel": "k_fused (whole solves, one workgroup per patch)",
+            "kernel": "k_fused (whole solves; one workgroup per patch, idle workgroups help tiled windows)",
             "bound": "alu",
             "achieved": round(achieved, 3),
             "peak": PEAK_FP32_VECTOR_TFLOPS,
@@ -395,10 +506,21 @@ def main():
             "traffic": (profiled_traffic("k_fused_batch256x100x100.md")
                         if names[args.workload] == "batch-256x100x100-projective" and args.svt_mode == 0
                         and args.pyramid == 1 and args.patches in (None, 256) else None),
+            "work_model": "cold one-sided Jacobi, 6 S m n^2 flops and 8 S m n^2 LDS bytes per SVD (S: measured "
+                          "sweeps, n = min side)",
             "kernel_ms": round(k_ms, 2),
-            "flops_per_launch": flops,
+            "flops_per_launch": jac_flops,
             "peak_measured": round(fma_peak, 2),
             "frac_of_measured": round(achieved / fma_peak, 4),
+            "lds": {"achieved": round(lds_tbs, 3), "peak": NOMINAL_PEAKS["lds_read"][0], "unit": "TB/s",
+                    "frac": round(lds_tbs / NOMINAL_PEAKS["lds_read"][0], 4), "bytes_per_launch": jac_lds},
+            "mfma": ({"achieved": round(mfma_flops / (k_ms * 1e-3) / 1e12, 4), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                      "unit": "TFLOP/s", "frac": round(mfma_flops / (k_ms * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 6),
+                      "flops_per_launch": mfma_flops, "what": "warm-start products R M, 2 n^2 m per SVD"}
+                     if args.svt_mode == 1 else None),
+            "counted": {"achieved": round(achieved_counted, 3), "flops_per_launch": flops,
+                        "what": "flops from the work counters: 2 m per examined pair, 6 m per rotation, "
+                                "shrinkage and updates"},
         },
         "cpu_baseline": cpu,
     }

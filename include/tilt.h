@@ -87,11 +87,11 @@ typedef struct {
                            and the Jacobi continues (FP32 accuracy).
                            3: bfloat16 start without refinement (precision
                            study; errors of order 1e-3).                      */
-    float jacobi_tol;   /* rotate a pair when |a.b| > tol ||a|| ||b||; 1e-7.
-                           The SVT's rounding enters Cond2 multiplied by mu
-                           (up to ~1e3 on large windows), so it must stay
-                           well below eps2 / mu; at 1e-6 large windows never
-                           meet Cond2.                                       */
+    float jacobi_tol;   /* rotate a pair when |a.b| > tol ||a|| ||b||, with
+                           tol = min(jacobi_tol, max(1e-7, eps2 / (10 mu)))
+                           in the inner loop (the SVT's rounding enters Cond2
+                           multiplied by mu, up to ~1e3 on large windows) and
+                           tol = jacobi_tol elsewhere; default 1e-6          */
     int max_sweeps;     /* Jacobi sweep cap, default 40                       */
     int pyramid_levels; /* 1 (default): solve the window as given.  L in 2..4:
                            solve coarse to fine over L levels; level l has the
@@ -187,6 +187,13 @@ int tilt_ctx_destroy(tilt_ctx* ctx);
  * this context, measured with HIP events recorded around the launch on its
  * stream (0 if none). */
 int tilt_ctx_last_kernel_ms(tilt_ctx* ctx, double* ms);
+
+/* Progress of the fused kernel that tilt_solve_batch is running on this
+ * context, for callers that watch a long batch from another thread:
+ * *finished of *total requests are done (both 0 when no fused launch is in
+ * flight).  Reads one word of device memory on a stream of its own, so it
+ * neither waits for nor delays the batch. */
+int tilt_ctx_progress(tilt_ctx* ctx, int* finished, int* total);
 
 /* Bytes of device workspace one problem needs (for admission control). */
 size_t tilt_workspace_bytes(const tilt_problem* prob);

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -614,8 +615,8 @@ int run_plain_request(tilt_ctx* ctx, size_t lds, const SolverParams& sp, int L, 
         int sweeps = 0, flag = 1;
         for (int sw = 0; sw < sp.max_sweeps && flag; ++sw) {
             for (int r = 0; r < hd.nsb - 1; ++r) {
-                HIP_TRY(launch_wide_round(d, ds, d_ints, 1, hd.nsb / 2, r, sp.jacobi_tol, d_ints + 1, lr, !configured,
-                                          stream));
+                HIP_TRY(launch_wide_round(d, ds, d_ints, 1, hd.nsb / 2, r, sp.jacobi_tol, form_m ? sp.eps2 : 0.0,
+                                          d_ints + 1, lr, !configured, stream));
                 configured = true;
             }
             HIP_TRY(hipMemcpyAsync(&flag, d_ints + 1, sizeof(int), hipMemcpyDeviceToHost, stream));
@@ -782,11 +783,15 @@ int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const 
                                  reinterpret_cast<PatchState*>(ctx->states.p), sp, nlive, L,
                                  reinterpret_cast<const int*>(ctx->order.p), dfc, grid, max_lds, stream));
             HIP_TRY(hipEventRecord(ctx->ev1, stream));
+            ctx->live_count.store(nlive);
+            ctx->live_fc.store(dfc);
         }
         std::vector<PatchState> out(nlive);
         HIP_TRY(hipMemcpyAsync(out.data(), ctx->states.p, sizeof(PatchState) * nlive, hipMemcpyDeviceToHost,
                                stream));
-        HIP_TRY(hipStreamSynchronize(stream));
+        const hipError_t se = hipStreamSynchronize(stream);
+        ctx->live_fc.store(nullptr);
+        HIP_TRY(se);
         if (!plain) {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
@@ -928,8 +933,8 @@ int inner_wide(tilt_ctx* ctx, const float* I, const float* J, int count, int m, 
         for (int sw = 0; sw < prm->max_sweeps && !cur.empty(); ++sw) {
             HIP_TRY(hipMemcpyAsync(d_cur, cur.data(), sizeof(int) * cur.size(), hipMemcpyHostToDevice, stream));
             for (int r = 0; r < wt.nsb - 1; ++r) {
-                HIP_TRY(launch_wide_round(dd, ds, d_cur, (int)cur.size(), wt.nsb / 2, r, sp.jacobi_tol, d_flags,
-                                          wt.lds_round, !configured, stream));
+                HIP_TRY(launch_wide_round(dd, ds, d_cur, (int)cur.size(), wt.nsb / 2, r, sp.jacobi_tol,
+                                          form_m ? sp.eps2 : 0.0, d_flags, wt.lds_round, !configured, stream));
                 configured = true;
             }
             HIP_TRY(hipMemcpyAsync(flags.data(), d_flags, sizeof(int) * count, hipMemcpyDeviceToHost, stream));
@@ -1014,7 +1019,7 @@ void tilt_default_params(tilt_params* p) {
     p->max_outer = 50;
     p->fixed_iters = 0;
     p->svt_mode = 0;
-    p->jacobi_tol = 1e-7f;
+    p->jacobi_tol = 1e-6f;
     p->max_sweeps = 40;
     p->pyramid_levels = 1;
 }
@@ -1134,7 +1139,27 @@ int tilt_ctx_destroy(tilt_ctx* ctx) {
     ctx->img.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
+    return TILT_OK;
+}
+
+int tilt_ctx_progress(tilt_ctx* ctx, int* finished, int* total) {
+    if (!ctx || !finished || !total) return TILT_ERR_ARG;
+    *finished = 0;
+    *total = 0;
+    void* fc = ctx->live_fc.load();
+    if (!fc) return TILT_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (!ctx->side) HIP_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    if (!ctx->pinned) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), sizeof(int)));
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, reinterpret_cast<char*>(fc) + offsetof(FusedCtl, remaining), sizeof(int),
+                           hipMemcpyDeviceToHost, ctx->side));
+    HIP_TRY(hipStreamSynchronize(ctx->side));
+    const int n = ctx->live_count.load();
+    *total = n;
+    *finished = std::max(0, std::min(n, n - *ctx->pinned));
     return TILT_OK;
 }
 

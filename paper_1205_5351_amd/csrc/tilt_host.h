@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstddef>
 #include <vector>
 
@@ -81,6 +82,12 @@ struct tilt_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_kernel_ms = 0.0;
     tilt::host::ServeState* serve = nullptr;
+    // progress of a running fused launch (tilt_ctx_progress): its control
+    // block, the request count, a side stream and a pinned word to read into
+    std::atomic<void*> live_fc{nullptr};
+    std::atomic<int> live_count{0};
+    hipStream_t side = nullptr;
+    int* pinned = nullptr;
 };
 
 #define HIP_TRY(x)                                                                   \

@@ -115,6 +115,18 @@ struct SolverParams {
     int ns_every;  // warm SVT: Newton-Schulz re-orthonormalisation of the rotation every ns_every SVTs
 };
 
+// Jacobi tolerance of an inner-loop SVT.  The SVT's rounding (of the order
+// of the tolerance, relative to ||M|| ~ 1 for the normalised window) enters
+// the Cond2 quantity multiplied by mu, so the tolerance follows a tenth of
+// the resolution Cond2 needs, eps2 / (10 mu), between the FP32 floor 1e-7
+// and the configured tolerance.
+__host__ __device__ inline float svt_tolerance(float tol_max, double eps2, double mu) {
+    double t = 0.1 * eps2 / mu;
+    if (!(t >= 1e-7)) t = 1e-7;
+    if (t > (double)tol_max) t = (double)tol_max;
+    return (float)t;
+}
+
 // Scaled coordinates of an m x n window (shared by host and device, FP64).
 // Hn = T^{-1} H diag(s, s, 1) with T = [[s, 0, cx], [0, s, cy], [0, 0, 1]],
 // (cx, cy) the image of the grid centre, s = max(m, n)/2, h33 = 1.
@@ -250,7 +262,7 @@ hipError_t launch_wide_setup(const PatchDesc* d, PatchState* st, const SolverPar
 hipError_t launch_wide_stage(const PatchDesc* d, PatchState* st, const int* active, int nactive, int form_m,
                              int* flags, hipStream_t s);
 hipError_t launch_wide_round(const PatchDesc* d, PatchState* st, const int* active, int nactive, int pairs, int r,
-                             float tol, int* flags, size_t lds, bool configure, hipStream_t s);
+                             float tol, double eps2, int* flags, size_t lds, bool configure, hipStream_t s);
 hipError_t launch_wide_finish(const PatchDesc* d, PatchState* st, const int* active, int nactive,
                               const SolverParams& prm, const int* sweeps, int mode, size_t lds, hipStream_t s);
 hipError_t launch_wide_update(const PatchDesc* d, PatchState* st, const int* active, int nactive,

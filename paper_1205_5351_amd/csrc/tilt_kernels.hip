@@ -2025,6 +2025,7 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
     const SvtLds L = (warm && !tiled) ? carve_lds_warm(lds, nc, ld, d.tb, &Rl) : carve_for(d, lds);
 
     svt_form_m(d, st, (!tiled && !warm) ? L.B : nullptr);
+    const float tol = svt_tolerance(prm.jacobi_tol, prm.eps2, st->mu);
     JacobiStats js{0, 0, 0};
     if (warm && tiled) {
         // The rotation lives in its own working plane (ncp rows, so that it
@@ -2039,7 +2040,7 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
         mfma_gemm<false>(Rg, ldg, nc, M, ldg, ldg, nc, Bg, ldg);
         for (int e = threadIdx.x; e < (d.ncp - nc) * ldg; e += NT) Bg[(size_t)nc * ldg + e] = 0.f;
         __syncthreads();
-        jacobi_tiled(d.svt_cfg, Bg, Rg, d.sb, d.nsb, ldg, ld, L.B, prm.jacobi_tol, prm.max_sweeps, js, d.gang);
+        jacobi_tiled(d.svt_cfg, Bg, Rg, d.sb, d.nsb, ldg, ld, L.B, tol, prm.max_sweeps, js, d.gang);
         row_norms_global(Bg, nc, ldg, L.s2);
         if (threadIdx.x == 0) {
             st->warm_ok = 1;
@@ -2064,12 +2065,12 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
             mfma_gemm_bf16(Rl, ld, nc4, M, ldg, ldg, nc, L.B, ld);
         clear_lds_padding(L.B, nc, ldg, ld);
         __syncthreads();
-        jacobi_dispatch_warm(d.svt_cfg, L.B, Rl, nc, ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
+        jacobi_dispatch_warm(d.svt_cfg, L.B, Rl, nc, ld, tol, prm.max_sweeps, js, L.s2);
         if (d.warm == 2) {
             mfma_gemm<false>(Rl, ld, nc4, M, ldg, ldg, nc, L.B, ld);
             clear_lds_padding(L.B, nc, ldg, ld);
             __syncthreads();
-            jacobi_dispatch_warm(d.svt_cfg, L.B, Rl, nc, ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
+            jacobi_dispatch_warm(d.svt_cfg, L.B, Rl, nc, ld, tol, prm.max_sweeps, js, L.s2);
         }
         save_rotation(Rl, ld, nc, V, ldg);
         if (threadIdx.x == 0) {
@@ -2078,11 +2079,11 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
         }
     } else if (tiled) {
         __syncthreads();
-        svd_rows(d, M, Bg, L, prm.jacobi_tol, prm.max_sweeps, js);
+        svd_rows(d, M, Bg, L, tol, prm.max_sweeps, js);
     } else {
         clear_lds_padding(L.B, nc, ldg, ld);
         __syncthreads();
-        jacobi_dispatch(d.svt_cfg, L.B, nc, ld, prm.jacobi_tol, prm.max_sweeps, js, L.s2);
+        jacobi_dispatch(d.svt_cfg, L.B, nc, ld, tol, prm.max_sweeps, js, L.s2);
     }
     svt_finish(d, st, L, js);
 }
@@ -2722,12 +2723,15 @@ __global__ void __launch_bounds__(NT) k_wide_stage(const PatchDesc* descs, Patch
 // One super-block pair of round r of the circle ordering over super-blocks:
 // workgroup g takes problem active[g / pairs], pair g % pairs.
 __global__ void __launch_bounds__(NT) k_wide_round(const PatchDesc* descs, PatchState* states, const int* active,
-                                                    int pairs, int r, float tol, int* flags) {
+                                                    int pairs, int r, float tol_max, double eps2, int* flags) {
     float* mini = reinterpret_cast<float*>(tilt_dyn_lds);
     const int slot = blockIdx.x / pairs, k = blockIdx.x - slot * pairs;
     const int idx = active[slot];
     PatchState* st = states + idx;
     const PatchDesc& d = descs[idx];
+    // inner-loop SVTs (eps2 > 0) follow mu as in dev_svt; the decomposition
+    // of I for mu_0 uses tol_max
+    const float tol = eps2 > 0.0 ? svt_tolerance(tol_max, eps2, st->mu) : tol_max;
     const int Nb = d.nsb - 1, sb = d.sb;
     int I, J;
     if (k == 0) {
@@ -3069,12 +3073,13 @@ hipError_t launch_wide_stage(const PatchDesc* d, PatchState* st, const int* acti
 }
 
 hipError_t launch_wide_round(const PatchDesc* d, PatchState* st, const int* active, int nactive, int pairs, int r,
-                             float tol, int* flags, size_t lds, bool configure, hipStream_t s) {
+                             float tol, double eps2, int* flags, size_t lds, bool configure, hipStream_t s) {
     if (configure) {
         hipError_t e = set_lds((const void*)k_wide_round, lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_wide_round, dim3(nactive * pairs), dim3(NT), lds, s, d, st, active, pairs, r, tol, flags);
+    hipLaunchKernelGGL(k_wide_round, dim3(nactive * pairs), dim3(NT), lds, s, d, st, active, pairs, r, tol, eps2,
+                       flags);
     return hipGetLastError();
 }
 

@@ -171,6 +171,8 @@ _lib.tilt_ctx_destroy.argtypes = [C.c_void_p]
 _lib.tilt_ctx_destroy.restype = C.c_int
 _lib.tilt_ctx_last_kernel_ms.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
 _lib.tilt_ctx_last_kernel_ms.restype = C.c_int
+_lib.tilt_ctx_progress.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+_lib.tilt_ctx_progress.restype = C.c_int
 _lib.tilt_workspace_bytes.argtypes = [C.POINTER(Problem)]
 _lib.tilt_workspace_bytes.restype = C.c_size_t
 _lib.tilt_solve_batch.argtypes = [C.c_void_p, C.POINTER(Problem), C.c_int, C.POINTER(Params),
@@ -217,7 +219,7 @@ EXPORTS = [
     "tilt_default_params", "tilt_status_string", "tilt_version", "tilt_tau_from_quad", "tilt_solve",
     "tilt_ctx_create", "tilt_ctx_destroy", "tilt_workspace_bytes", "tilt_solve_batch",
     "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_warp_jacobian", "tilt_last_error",
-    "tilt_ctx_last_kernel_ms", "tilt_submit", "tilt_poll", "tilt_serve_stop", "tilt_pyramid",
+    "tilt_ctx_last_kernel_ms", "tilt_ctx_progress", "tilt_submit", "tilt_poll", "tilt_serve_stop", "tilt_pyramid",
     "tilt_inner_batch", "tilt_svt_layouts", "tilt_svt_layout", "tilt_tune_set", "tilt_tune_clear",
     "tilt_rasl_solve_batch", "tilt_peak_probe",
 ]
@@ -434,6 +436,14 @@ class Context:
         ms = C.c_double()
         _lib.tilt_ctx_last_kernel_ms(self._h, C.byref(ms))
         return ms.value
+
+    def progress(self):
+        """(finished, total) requests of the fused launch in flight, (0, 0) if none."""
+        f, t = C.c_int(), C.c_int()
+        rc = _lib.tilt_ctx_progress(self._h, C.byref(f), C.byref(t))
+        if rc != TILT_OK:
+            raise TiltError(rc, "tilt_ctx_progress")
+        return f.value, t.value
 
     def solve_batch(self, problems, params=None, outs_A=None, outs_E=None, stream=None):
         """Fused persistent kernel over all problems (device images/outputs)."""

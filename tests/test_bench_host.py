@@ -22,12 +22,24 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_profiled_traffic_follows_the_kernel_source(monkeypatch):
-    t = bench.profiled_traffic("k_fused_batch256x100x100.md")
-    assert t is not None and t > 0                       # the committed profile matches the source
+def test_profiled_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "k.md").write_text("- kernel_source_sha256_16: abcd\n- traffic_bytes: 123\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_sha", lambda sources=None: "abcd")
+    assert bench.profiled_traffic("k.md") == 123       # the profile matches the source
     monkeypatch.setattr(bench, "kernel_source_sha", lambda sources=None: "0" * 16)
-    assert bench.profiled_traffic("k_fused_batch256x100x100.md") is None
+    assert bench.profiled_traffic("k.md") is None       # the kernel changed since the counters were taken
     assert bench.profiled_traffic("no_such_profile.md") is None
+
+
+def test_cold_jacobi_work_is_the_stated_model():
+    """6 S m n^2 flops and 8 S m n^2 LDS bytes (n = min side), S summed
+    over the patch's sweeps."""
+    p = SimpleNamespace(m=30, n=50, model=8)
+    res = {"counters": {"jacobi_sweeps": 7}}
+    f, b = bench.cold_jacobi_work(res, p)
+    assert f == 6 * 50 * 30 * 30 * 7 and b == 8 * 50 * 30 * 30 * 7
 
 
 def test_solve_flops_counts_the_stated_terms():

@@ -3,9 +3,9 @@
 Tolerances (FP32 arithmetic on the device, FP64 in the oracle):
   * SVT: ||A_gpu - A_ref||_F <= 1e-5 ||A_ref||_F and singular values within
     1e-5 sigma_max.  The Jacobi stops when every pair satisfies
-    |a.b| <= 1e-7 ||a|| ||b|| (the default tolerance; tests of the 1e-6
-    setting use the same bounds), so the orthogonalised rows (and the
-    shrinkage built from them) carry a relative error of order 1e-7-1e-6,
+    |a.b| <= 1e-6 ||a|| ||b|| (the configured tolerance; inside the inner
+    loop it tightens towards 1e-7 as mu grows), so the orthogonalised rows
+    (and the shrinkage built from them) carry a relative error of order 1e-6,
     plus FP32 rounding of length-n sums (~sqrt(n) 6e-8); 1e-5 leaves a 10x
     margin.
   * warp: |I_gpu - I_ref| <= 2e-6 max|I| (FP32 bilinear blend of FP32 data);
