@@ -260,6 +260,27 @@ int tilt_svt_batch(tilt_ctx* ctx, const float* M, float* A, float* sigma, int co
                    const float* eps, const tilt_params* prm, int* ranks, tilt_counters* counters,
                    void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * tilt_svt_batch without a context and without any device allocation.  The
+ * same shrinkage by the same kernels; every device buffer beyond the
+ * caller's inputs and outputs (job table, per-matrix work counters and
+ * ranks, per-matrix working planes) comes from one fixed array of
+ * TILT_SVT_NOALLOC_BYTES in the library, one per GPU, held until the
+ * process ends.  Runs on the current device and on `hip_stream`; other
+ * arguments as in tilt_svt_batch (eps, ranks and counters are HOST arrays).
+ * Per matrix the batch needs 8 min(m,n) ldg bytes (ldg = max(m,n) rounded
+ * up to 4), plus 4 ncp ldg bytes when the shape's SVT is tiled (ncp: its
+ * rows rounded up to whole super-blocks), plus about 64 bytes; a batch that
+ * needs more than the array returns TILT_ERR_TOO_LARGE before any device
+ * work.  Every call on a GPU shares that GPU's array and leaves its
+ * contents behind: calls that overlap on one GPU race; calls in sequence
+ * (one stream, or synchronised) are safe.  Synchronous. */
+#define TILT_SVT_NOALLOC_BYTES ((size_t)64 << 20)
+int tilt_svt_batch_noalloc(const float* M, float* A, float* sigma, int count, int m, int n,
+                           const float* eps, const tilt_params* prm, int* ranks, tilt_counters* counters,
+                           void* hip_stream);
+
 /* Alg. 1 Step 1 on its own: the normalised warp D o tau / ||D o tau||_F
  * (I_out: count x m x n) and the Jacobian of the normalised warp w.r.t.
  * the p entries of tau in scaled coordinates (J_out: count x p x m x n,

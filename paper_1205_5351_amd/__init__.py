@@ -26,6 +26,7 @@ from .tilt import (  # noqa: F401
     peak_probe,
     svt_layout,
     svt_layouts,
+    svt_batch_noalloc,
     tune_clear,
     tune_set,
 )

@@ -46,6 +46,7 @@ TILT_ERR_SINGULAR = -4
 TILT_ERR_NONFINITE = -5
 TILT_ERR_TOO_LARGE = -6
 TILT_ERR_NOT_FOUND = -7
+TILT_SVT_NOALLOC_BYTES = 64 << 20  # fixed working array of tilt_svt_batch_noalloc, per GPU
 
 AFFINE = 6
 PROJECTIVE = 8
@@ -184,6 +185,10 @@ _lib.tilt_svt_batch.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, 
                                 C.POINTER(C.c_float), C.POINTER(Params), C.POINTER(C.c_int),
                                 C.POINTER(Counters), C.c_void_p]
 _lib.tilt_svt_batch.restype = C.c_int
+_lib.tilt_svt_batch_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
+                                        C.POINTER(C.c_float), C.POINTER(Params), C.POINTER(C.c_int),
+                                        C.POINTER(Counters), C.c_void_p]
+_lib.tilt_svt_batch_noalloc.restype = C.c_int
 _lib.tilt_warp_jacobian.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(C.c_double), C.c_int,
                                     C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.tilt_warp_jacobian.restype = C.c_int
@@ -218,7 +223,7 @@ _lib.tilt_rasl_solve_batch.restype = C.c_int
 EXPORTS = [
     "tilt_default_params", "tilt_status_string", "tilt_version", "tilt_tau_from_quad", "tilt_solve",
     "tilt_ctx_create", "tilt_ctx_destroy", "tilt_workspace_bytes", "tilt_solve_batch",
-    "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_warp_jacobian", "tilt_last_error",
+    "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_svt_batch_noalloc", "tilt_warp_jacobian", "tilt_last_error",
     "tilt_ctx_last_kernel_ms", "tilt_ctx_progress", "tilt_submit", "tilt_poll", "tilt_serve_stop", "tilt_pyramid",
     "tilt_inner_batch", "tilt_svt_layouts", "tilt_svt_layout", "tilt_tune_set", "tilt_tune_clear",
     "tilt_rasl_solve_batch", "tilt_peak_probe",
@@ -381,6 +386,26 @@ def solve(image: np.ndarray, tau0, m: int, n: int, model: int, params: Optional[
     out["E"] = E
     out["rc"] = rc
     return out
+
+
+def svt_batch_noalloc(M_ptr: int, A_ptr: int, sigma_ptr: int, count: int, m: int, n: int, eps,
+                      params: Optional[Params] = None, stream=None):
+    """tilt_svt_batch_noalloc: the SVT of `count` m x n matrices (DEVICE
+    pointers) on the current device, working memory from the library's fixed
+    array (no device allocation).  Returns (ranks, counters)."""
+    prm = params if params is not None else default_params()
+    e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.float32), (count,)))
+    earr = (C.c_float * count)(*e.tolist())
+    ranks = (C.c_int * count)()
+    cnt = Counters()
+    rc = _lib.tilt_svt_batch_noalloc(C.c_void_p(int(M_ptr)), C.c_void_p(int(A_ptr)),
+                                     C.c_void_p(int(sigma_ptr)) if sigma_ptr else None, int(count), int(m), int(n),
+                                     earr, C.byref(prm), ranks, C.byref(cnt), C.c_void_p(_stream_ptr(stream)))
+    if rc != TILT_OK:
+        raise TiltError(rc, "tilt_svt_batch_noalloc")
+    return list(ranks), dict(svt_calls=cnt.svt_calls, jacobi_sweeps=cnt.jacobi_sweeps,
+                             jacobi_pairs=cnt.jacobi_pairs, jacobi_rotations=cnt.jacobi_rotations,
+                             recon_rows=cnt.recon_rows)
 
 
 def _stream_ptr(stream) -> int:
