@@ -104,17 +104,29 @@ typedef struct {
                            iterations one by one; K in 1..256 runs them as
                            replays of a HIP graph of K captured iterations
                            (one stop-flag read per replay).  Same results.   */
+    double eps_obj;     /* second outer stop (Alg. 1 "while not converged"):
+                           from the second outer iteration of a level on,
+                           stop when |f_i - f_{i-1}| < eps_obj f_{i-1} with
+                           f = ||A||_* + lambda ||E||_1.  0 (default): off,
+                           only ||Delta tau|| < eps_outer and max_outer stop.
+                           Not applied by the RASL entry point.              */
 } tilt_params;
 
-/* One window of one image. */
+/* One window of one image.  The window is given by an initial transform
+ * (the problem statement of Eq. TILT_2 starts from D o tau0), either
+ * directly (init = 0: tau0) or as the quadrilateral the m x n grid covers
+ * in the image (init = 1: quad, mapped as by tilt_tau_from_quad; tau0 is
+ * then ignored). */
 typedef struct {
     const float* image;     /* host (tilt_solve) or device (batch) pointer    */
     int height, width;
     long long row_stride;   /* elements between rows, >= width                */
     int m, n;               /* rectified rows, columns (>= 2 each)            */
     int model;              /* TILT_AFFINE or TILT_PROJECTIVE                 */
-    int reserved;
-    double tau0[9];         /* initial pixel homography                       */
+    int init;               /* 0: start from tau0; 1: from quad               */
+    double tau0[9];         /* initial pixel homography (init = 0)            */
+    double quad[8];         /* window corners TL, TR, BR, BL as (x, y) image
+                               pixels (init = 1)                              */
 } tilt_problem;
 
 /* Work counters of one solve (used for roofline accounting). */
@@ -135,6 +147,10 @@ typedef struct {
     int inner_iters_total;
     int svt_rank;           /* #singular values of the last M above 1/mu      */
     int status;
+    int rank;               /* numerical rank of A: #{sigma_i(A) >
+                               1e-3 sigma_1(A)} (FP32 singular values of the
+                               last SVT)                                      */
+    int reserved;
     double objective;       /* ||A||_* + lambda ||E||_1 of the returned A, E  */
     double mu;              /* penalty at the end of the last inner loop      */
     double cond1, cond2;    /* last values of the Cond1 / Cond2 quantities    */

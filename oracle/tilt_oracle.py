@@ -80,6 +80,7 @@ class Params:
     max_inner: int = 2000
     max_outer: int = 50
     fixed_iters: bool = False  # run exactly max_outer x max_inner, no stop tests
+    eps_obj: float = 0.0       # also stop when |f_i - f_{i-1}| < eps_obj f_{i-1} (0: off)
 
 
 # ---------------------------------------------------------------------------
@@ -549,12 +550,18 @@ def tilt_solve(image, tau0_px, m, n, model, prm: Optional[Params] = None, lam=No
         dtau = delta_tau(Jp, NQ, A, E, I)                    # Step 3
         tau = tau + dtau                                     # Step 4
         i += 1
+        f = objective(A, E, lam) if prm.eps_obj > 0 else None
         hist.append(dict(dtau_norm=float(np.linalg.norm(dtau)), inner=res.iters,
-                         mu=res.mu, cond1=res.cond1, cond2=res.cond2))
+                         mu=res.mu, cond1=res.cond1, cond2=res.cond2, objective=f))
         if not np.all(np.isfinite(tau)):
             status = -5
             break
         if not prm.fixed_iters and float(np.linalg.norm(dtau)) < prm.eps_outer:
+            break
+        # "while not converged" (Alg. 1): the objective of Eq. TILT_2 no
+        # longer changes between outer iterations (reading R7)
+        if (not prm.fixed_iters and prm.eps_obj > 0 and i > 1
+                and abs(f - hist[-2]["objective"]) < prm.eps_obj * hist[-2]["objective"]):
             break
     Hn = matrix_from_tau(tau, model)
     H_px = denormalise_transform(Hn, c, s)

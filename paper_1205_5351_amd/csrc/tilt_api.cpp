@@ -327,7 +327,7 @@ thread_local char g_last_error[512] = "";
 
 int validate_params(const tilt_params* p) {
     if (!p) return TILT_ERR_ARG;
-    if (!(p->eps1 > 0) || !(p->eps2 > 0) || !(p->eps_outer >= 0)) return TILT_ERR_ARG;
+    if (!(p->eps1 > 0) || !(p->eps2 > 0) || !(p->eps_outer >= 0) || !(p->eps_obj >= 0)) return TILT_ERR_ARG;
     if (!(p->rho0 >= 1.0) || !(p->mu_max > 0)) return TILT_ERR_ARG;
     if (p->max_inner < 1 || p->max_outer < 1 || p->max_sweeps < 1) return TILT_ERR_ARG;
     if (!(p->jacobi_tol > 0.f) || !(p->jacobi_tol < 1.f)) return TILT_ERR_ARG;
@@ -343,7 +343,16 @@ int validate_problem(const tilt_problem* pr) {
     if (pr->height < 2 || pr->width < 2 || pr->row_stride < pr->width) return TILT_ERR_ARG;
     if (pr->m < 2 || pr->n < 2) return TILT_ERR_ARG;
     if (pr->model != TILT_AFFINE && pr->model != TILT_PROJECTIVE) return TILT_ERR_ARG;
-    if (!finite9(pr->tau0)) return TILT_ERR_ARG;
+    double H[9];
+    return initial_transform(*pr, H);
+}
+
+// The problem's initial pixel homography: tau0, or the map of the grid
+// onto quad (init = 1).
+int initial_transform(const tilt_problem& pr, double* H) {
+    if (pr.init == 1) return tilt_tau_from_quad(pr.quad, pr.m, pr.n, pr.model, H);
+    if (pr.init != 0 || !finite9(pr.tau0)) return TILT_ERR_ARG;
+    for (int k = 0; k < 9; ++k) H[k] = pr.tau0[k];
     return TILT_OK;
 }
 
@@ -355,6 +364,7 @@ SolverParams to_solver(const tilt_params* p) {
     s.mu0 = p->mu0;
     s.rho0 = p->rho0;
     s.mu_max = p->mu_max;
+    s.eps_obj = p->eps_obj;
     s.max_inner = p->max_inner;
     s.max_outer = p->max_outer;
     s.fixed_iters = p->fixed_iters ? 1 : 0;
@@ -419,7 +429,8 @@ int plan_request(const tilt_problem& pr, const tilt_params* prm, float* A_out, f
     P.ws_floats = off;
     // initial transform at the coarsest level
     double H[9];
-    for (int k = 0; k < 9; ++k) H[k] = pr.tau0[k];
+    st = initial_transform(pr, H);
+    if (st != TILT_OK) return st;
     for (int l = 1; l < levels; ++l) to_coarser_h(H);
     PatchState& s0 = P.init;
     st = normalise_window(H, ml[levels - 1], nl[levels - 1], pr.model, s0.geo, s0.tau);
@@ -476,6 +487,7 @@ void fill_result(const PatchDesc& d0, const PatchState& s, tilt_result* r, doubl
     r->outer_iters = s.outer;
     r->inner_iters_total = s.inner_total;
     r->svt_rank = s.svt_rank;
+    r->rank = s.num_rank;
     r->status = s.status < 0 ? s.status : (s.warn ? TILT_WARN_MAXITER : TILT_OK);
     r->objective = s.objective;
     r->mu = s.mu;
@@ -1022,6 +1034,7 @@ void tilt_default_params(tilt_params* p) {
     p->jacobi_tol = 1e-6f;
     p->max_sweeps = 40;
     p->pyramid_levels = 1;
+    p->eps_obj = 0.0;
 }
 
 const char* tilt_status_string(int s) {
@@ -1317,8 +1330,10 @@ int tilt_warp_jacobian(tilt_ctx* ctx, const tilt_problem* probs, const double* t
         int st = validate_problem(&pr);
         if (st != TILT_OK) return st;
         if (pr.m != m || pr.n != n || pr.model != model) return TILT_ERR_ARG;
-        double geo[3], tau0n[MAXP];
-        st = normalise_window(pr.tau0, m, n, model, geo, tau0n);
+        double geo[3], tau0n[MAXP], H0[9];
+        st = initial_transform(pr, H0);
+        if (st != TILT_OK) return st;
+        st = normalise_window(H0, m, n, model, geo, tau0n);
         if (st != TILT_OK) return st;
         // The transform being evaluated, expressed in the window's scaled
         // coordinates (centre = image of the grid centre under tau0).

@@ -43,6 +43,7 @@ double predicted_cost(const PatchDesc& d);
 
 int validate_params(const tilt_params* p);
 int validate_problem(const tilt_problem* pr);
+int initial_transform(const tilt_problem& pr, double* H);
 SolverParams to_solver(const tilt_params* p);
 int worse(int a, int b);
 int record_hip_error(hipError_t e, const char* what, int line);

@@ -101,6 +101,9 @@ struct PatchState {
     double mu, c, dtau_norm, cond1, cond2, nuc, l1, objective;
     double dA2, dE2;
     int outer, inner, inner_total, done_inner, done_outer, status, svt_rank, warn;
+    int num_rank;              // #{sigma_i(A) > 1e-3 sigma_1(A)} of the last SVT's result A
+    int pad_rank;
+    double f_prev;             // ||A||_* + lam ||E||_1 after the previous outer iteration of this level
     long long svt_calls, sweeps, pairs, rotations, recon_rows;
     long long t_begin, t_end;  // device wall clock at the start / end of the solve
     double geo[3];             // cx, cy, s of the level being solved
@@ -110,6 +113,7 @@ struct PatchState {
 
 struct SolverParams {
     double eps1, eps2, eps_outer, mu0, rho0, mu_max;
+    double eps_obj;  // outer stop when the objective changes by less than eps_obj times itself (0: off)
     int max_inner, max_outer, fixed_iters, max_sweeps;
     float jacobi_tol;
     int ns_every;  // warm SVT: Newton-Schulz re-orthonormalisation of the rotation every ns_every SVTs

@@ -2002,6 +2002,13 @@ __device__ void svt_finish(const PatchDesc& d, PatchState* st, const SvtLds& L, 
                 : reconstruct(L.B, ld, M, A, nc, nr4, ldg, L.w, L.act, k, d.tb, L.xblk, L.cwt, true);
     block_sum_f<1>(dA);
     if (tid == 0) {
+        // numerical rank of the result: its singular values are s_j - eps
+        // for the kept rows
+        double top = 0.0;
+        for (int j = 0; j < nc; ++j) top = fmax(top, (double)sqrtf(L.s2[j]) - (double)eps);
+        int nr_rank = 0;
+        for (int j = 0; j < nc; ++j) nr_rank += ((double)sqrtf(L.s2[j]) - (double)eps) > 1e-3 * top ? 1 : 0;
+        st->num_rank = top > 0.0 ? nr_rank : 0;
         st->dA2 = (double)dA[0];
         st->nuc = nuc;
         st->svt_rank = k;
@@ -2237,7 +2244,7 @@ __device__ void dev_update(const PatchDesc& d, PatchState* st, const SolverParam
 // ---------------------------------------------------------------------------
 
 // Outer stop from ||Delta tau||^2 (one thread).
-__device__ void finish_outer_iteration(PatchState* st, const SolverParams& prm, double nrm2, bool finite) {
+__device__ void finish_outer_iteration(PatchState* st, const SolverParams& prm, double nrm2, bool finite, double f) {
     st->dtau_norm = sqrt(nrm2);
     st->outer += 1;
     int stop = 0;
@@ -2246,6 +2253,10 @@ __device__ void finish_outer_iteration(PatchState* st, const SolverParams& prm, 
         stop = 1;
     }
     if (!prm.fixed_iters && st->dtau_norm < prm.eps_outer) stop = 1;
+    // the objective no longer changes (from the second outer iteration of a level on)
+    if (!prm.fixed_iters && prm.eps_obj > 0.0 && st->outer > 1 && fabs(f - st->f_prev) < prm.eps_obj * st->f_prev)
+        stop = 1;
+    st->f_prev = f;
     if (st->outer >= prm.max_outer) stop = 1;
     st->done_outer = stop;
 }
@@ -2258,15 +2269,17 @@ __device__ void dev_dtau(const PatchDesc& d, PatchState* st, const SolverParams&
     const float* E = d.ws + PL_E * np;
     const float* I = d.ws + PL_I * np;
     const float* Qp = d.ws + PL_Q * np;
-    double t[MAXPP];
+    // t = Qb^T (A + E - I); t[MAXPP] = ||E||_1 for the objective
+    double t[MAXPP + 1];
 #pragma unroll
-    for (int l = 0; l < MAXPP; ++l) t[l] = 0.0;
+    for (int l = 0; l <= MAXPP; ++l) t[l] = 0.0;
     for (size_t e = tid; e < np; e += NT) {
         const float s = A[e] + E[e] - I[e];
         #pragma unroll
         for (int l = 0; l < MAXPP; ++l) if (l < pp) t[l] += (double)Qp[l * np + e] * (double)s;
+        t[MAXPP] += fabs((double)E[e]);
     }
-    block_sum_d<MAXPP>(t);
+    block_sum_d<MAXPP + 1>(t);
     if (tid == 0) {
         // y = R^{-1} t (back substitution), Delta tau = N_Q y.
         double y[MAXPP];
@@ -2286,7 +2299,7 @@ __device__ void dev_dtau(const PatchDesc& d, PatchState* st, const SolverParams&
             nrm2 += dk * dk;
             finite = finite && isfinite(st->tau[k]);
         }
-        finish_outer_iteration(st, prm, nrm2, finite);
+        finish_outer_iteration(st, prm, nrm2, finite, st->nuc + d.lam * t[MAXPP]);
     }
     __syncthreads();
 }

@@ -76,6 +76,7 @@ class Params(C.Structure):
         ("max_sweeps", C.c_int),
         ("pyramid_levels", C.c_int),
         ("graph_inner", C.c_int),
+        ("eps_obj", C.c_double),
     ]
 
 
@@ -88,8 +89,9 @@ class Problem(C.Structure):
         ("m", C.c_int),
         ("n", C.c_int),
         ("model", C.c_int),
-        ("reserved", C.c_int),
+        ("init", C.c_int),
         ("tau0", C.c_double * 9),
+        ("quad", C.c_double * 8),
     ]
 
 
@@ -113,6 +115,8 @@ class Result(C.Structure):
         ("inner_iters_total", C.c_int),
         ("svt_rank", C.c_int),
         ("status", C.c_int),
+        ("rank", C.c_int),
+        ("reserved", C.c_int),
         ("objective", C.c_double),
         ("mu", C.c_double),
         ("cond1", C.c_double),
@@ -321,7 +325,11 @@ def tau_from_quad(quad: Sequence[float], m: int, n: int, model: int) -> np.ndarr
 
 
 def make_problem(image_ptr: int, height: int, width: int, row_stride: int, m: int, n: int, model: int,
-                 tau0) -> Problem:
+                 tau0=None, quad=None) -> Problem:
+    """One window: start from the pixel homography tau0, or (quad given,
+    tau0 None) from the map of the grid onto quad = TL, TR, BR, BL (x, y)."""
+    if (tau0 is None) == (quad is None):
+        raise ValueError("give exactly one of tau0 and quad")
     pr = Problem()
     pr.image = C.c_void_p(int(image_ptr))
     pr.height = int(height)
@@ -330,10 +338,16 @@ def make_problem(image_ptr: int, height: int, width: int, row_stride: int, m: in
     pr.m = int(m)
     pr.n = int(n)
     pr.model = int(model)
-    pr.reserved = 0
-    t = np.asarray(tau0, dtype=np.float64).reshape(9)
-    for k in range(9):
-        pr.tau0[k] = float(t[k])
+    if quad is not None:
+        pr.init = 1
+        q = np.asarray(quad, dtype=np.float64).reshape(8)
+        for k in range(8):
+            pr.quad[k] = float(q[k])
+    else:
+        pr.init = 0
+        t = np.asarray(tau0, dtype=np.float64).reshape(9)
+        for k in range(9):
+            pr.tau0[k] = float(t[k])
     return pr
 
 
@@ -349,6 +363,7 @@ def result_dict(r: Result) -> dict:
         outer_iters=r.outer_iters,
         inner_iters_total=r.inner_iters_total,
         svt_rank=r.svt_rank,
+        rank=r.rank,
         status=r.status,
         objective=r.objective,
         mu=r.mu,

@@ -70,4 +70,4 @@ def oracle_params(O, tp, **kw):
     """Oracle parameters equal to the library's parameter struct."""
     return O.Params(lam=tp.lambda_, eps1=tp.eps1, eps2=tp.eps2, eps_outer=tp.eps_outer, mu0=tp.mu0,
                     rho0=tp.rho0, mu_max=tp.mu_max, max_inner=tp.max_inner, max_outer=tp.max_outer,
-                    fixed_iters=bool(tp.fixed_iters), **kw)
+                    fixed_iters=bool(tp.fixed_iters), eps_obj=tp.eps_obj, **kw)

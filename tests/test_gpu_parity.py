@@ -16,6 +16,7 @@ Tolerances (FP32 arithmetic on the device, FP64 in the oracle):
 """
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -181,6 +182,79 @@ def test_full_solve_matches_oracle(tilt, ctx, device, cfg, idx):
     assert terr <= 1e-4, (terr, r["outer_iters"], ref.outer_iters)
     assert abs(r["objective"] - ref.objective) <= 1e-4 * ref.objective
     assert same_numerical_rank(O, r["A"], ref.A)[0], same_numerical_rank(O, r["A"], ref.A)
+    assert_reported_rank(r)
+
+
+def assert_reported_rank(r):
+    """The rank the library reports (FP32 singular values of its last SVT)
+    is the FP64 count #{sigma > 1e-3 sigma_1} of the A it returns, unless a
+    singular value lies within 1e-5 (relative) of the cut."""
+    sv = np.linalg.svd(np.asarray(r["A"], np.float64), compute_uv=False)
+    cut = 1e-3 * sv[0]
+    if not np.any(np.abs(sv - cut) <= 1e-5 * sv[0]):
+        assert r["rank"] == O.numerical_rank(r["A"]), (r["rank"], O.numerical_rank(r["A"]))
+
+
+def test_quad_start_equals_tau0_start(tilt, ctx, device):
+    """A window given as the quadrilateral the grid covers solves exactly
+    as the same window given by the homography that maps the grid onto it."""
+    p = ts.make_batch(1, [3])[0]
+    a, b = (p.n - 1) / 2.0, (p.m - 1) / 2.0
+    corners = [(-a, -b), (a, -b), (a, b), (-a, b)]
+    quad = []
+    for u, v in corners:
+        x = p.tau0 @ np.array([u, v, 1.0])
+        quad += [x[0] / x[2], x[1] / x[2]]
+    H = tilt.tau_from_quad(quad, p.m, p.n, p.model)
+    tp = tilt.default_params(lam=p.lam, fixed_iters=1, max_outer=2, max_inner=10)
+    img = to_device(p.image, device)
+    import torch
+
+    outs = []
+    for prob in (tilt.make_problem(img.data_ptr(), p.height, p.width, p.width, p.m, p.n, p.model, quad=quad),
+                 tilt.make_problem(img.data_ptr(), p.height, p.width, p.width, p.m, p.n, p.model, H)):
+        A = torch.zeros((p.m, p.n), dtype=torch.float32, device=device)
+        rc, res = ctx.solve_batch([prob], tp, [A.data_ptr()], [0])
+        torch.cuda.synchronize()
+        assert rc >= 0
+        outs.append((res[0], A.cpu().numpy()))
+    assert np.array_equal(outs[0][0]["tau"], outs[1][0]["tau"]) and np.array_equal(outs[0][1], outs[1][1])
+    assert np.allclose(H, p.tau0, atol=1e-9)
+
+
+def test_c1_at_its_stated_inner_tolerance(tilt, ctx, device):
+    """The 50x50 affine workload at its stated inner tolerance 1e-7 (eps1 =
+    eps2 = 1e-7): no inner loop meets it within max_inner = 5000, in FP32 or
+    in the FP64 oracle (Cond2 = mu max(||dA||, ||dE||)/c stays above 1e-7
+    once mu has grown), so both paths run the same 3 x 5000 iterations and
+    must agree as fixed-count solves do: tau within 1e-5, objective within
+    1e-4.  (FP32 meets Cond2 down to about 1e-4 here: at eps2 = 1e-4 the
+    device's Cond2 sits at its noise floor mu 6e-7.)"""
+    p = ts.make_batch(0, [0])[0]
+    tp = tilt.default_params(lam=p.lam, eps1=1e-7, eps2=1e-7, max_outer=3, max_inner=5000)
+    _, res = solve_on_device(tilt, ctx, [p], device, tp)
+    r = res[0]
+    ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
+    assert ref.inner_iters == [5000, 5000, 5000] and ref.status == 1
+    assert r["inner_iters_total"] == 15000 and r["status"] == 1
+    assert O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n) <= 1e-5
+    assert abs(r["objective"] - ref.objective) <= 1e-4 * ref.objective
+
+
+def test_objective_stop_matches_oracle(tilt, ctx, device):
+    """The outer stop on the objective (|f_i - f_{i-1}| < eps_obj f_{i-1},
+    here 1e-4 with the step-size stop off) ends the device solve at the same
+    outer iteration as the oracle's, with tau within 1e-4."""
+    rng = ts.patch_rng(78, 1)
+    p = ts.make_patch(rng, m=24, n=26, height=80, width=80, rank=2, model=6, corruption=0.05,
+                      theta_deg=6.0, skew=0.05)
+    tp = tilt.default_params(lam=p.lam, eps_outer=0.0, max_outer=12, max_inner=400, eps_obj=1e-4)
+    _, res = solve_on_device(tilt, ctx, [p], device, tp)
+    r = res[0]
+    ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
+    assert 2 <= ref.outer_iters < 12
+    assert r["outer_iters"] == ref.outer_iters
+    assert O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n) <= 1e-4
 
 
 def test_unconverged_outer_loop_tracks_oracle(tilt, ctx, device):
@@ -576,22 +650,61 @@ def test_warm_svt_single_float_tail_layouts_match_oracle(tilt, ctx, device, lpp,
     assert O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n) <= 1e-5
 
 
+def _oracle_solve(args):
+    cfg, idx, kw = args
+    import oracle as Oc
+    import tilt_synth as tsc
+
+    p = tsc.make_batch(cfg, [idx])[0]
+    r = Oc.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, Oc.Params(**kw), lam=p.lam)
+    return idx, r.tau_px, r.objective, r.A, r.outer_iters, sum(r.inner_iters)
+
+
 def test_full_headline_batch_sampled_against_oracle(tilt, ctx, device):
     """The 256-patch 100x100 projective workload in one fused launch (the
-    launch configuration bench.py times): every patch returns a status >= 0,
-    and sampled patches, solved one by one by the oracle, agree (tau within
-    1e-4, objective within 1e-4, the same numerical rank).  The samples are
-    patches whose solves converge in few iterations, so the oracle leg stays
-    short."""
+    launch configuration bench.py times): every patch returns a status >= 0;
+    three patches whose solves converge quickly, and the two slowest patches
+    of the launch (the ones that set its time), are solved one by one by the
+    oracle.  Where both outer loops converged: tau within 1e-4, objective
+    within 1e-4, the same numerical rank; where both ran to max_outer (tau
+    still drifting along the axis scaling that keeps a separable texture
+    low-rank): after the same number of outer iterations, tau within 1e-3
+    and objective within 1e-4 (reading R13)."""
+    import multiprocessing as mp
+
     patches = ts.make_config(1)
     assert len(patches) == 256
     tp = tilt.default_params(lam=patches[0].lam)
     _, res = solve_on_device(tilt, ctx, patches, device, tp)
     assert all(r["status"] >= 0 for r in res)
-    for i in (47, 121, 253):
+    slowest = sorted(range(256), key=lambda i: -res[i]["inner_iters_total"])[:2]
+    picks = [47, 121, 253] + [i for i in slowest if i not in (47, 121, 253)]
+    kw = dict(lam=tp.lambda_, eps1=tp.eps1, eps2=tp.eps2, eps_outer=tp.eps_outer, mu0=tp.mu0, rho0=tp.rho0,
+              mu_max=tp.mu_max, max_inner=tp.max_inner, max_outer=tp.max_outer)
+    print(f"oracle on patches {picks} (slowest: {slowest})", flush=True)
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    os.environ.update({k: "1" for k in saved})        # one BLAS thread per worker process
+    try:
+        with mp.get_context("spawn").Pool(len(picks)) as pool:
+            refs = pool.map(_oracle_solve, [(1, i, kw) for i in picks])
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    for i, tau_ref, obj_ref, A_ref, outer_ref, inner_ref in refs:
         p, r = patches[i], res[i]
-        ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
-        assert ref.outer_iters < tp.max_outer and r["outer_iters"] < tp.max_outer, i
-        assert O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n) <= 1e-4, i
-        assert abs(r["objective"] - ref.objective) <= 1e-4 * ref.objective, i
-        assert same_numerical_rank(O, r["A"], ref.A)[0], (i, same_numerical_rank(O, r["A"], ref.A))
+        terr = O.tau_rel_err(r["tau"], tau_ref, p.m, p.n)
+        oerr = abs(r["objective"] - obj_ref) / obj_ref
+        print(f"patch {i}: outer {r['outer_iters']}/{outer_ref} inner {r['inner_iters_total']}/{inner_ref} "
+              f"tau {terr:.2e} objective {oerr:.2e}", flush=True)
+        if i in slowest:
+            assert r["outer_iters"] == outer_ref, (i, r["outer_iters"], outer_ref)
+        both_converged = r["outer_iters"] < tp.max_outer and outer_ref < tp.max_outer
+        both_at_max = r["outer_iters"] == outer_ref == tp.max_outer
+        assert both_converged or both_at_max, (i, r["outer_iters"], outer_ref)
+        assert terr <= (1e-4 if both_converged else 1e-3), (i, terr)
+        assert oerr <= 1e-4, (i, oerr)
+        if both_converged:
+            assert same_numerical_rank(O, r["A"], A_ref)[0], (i, same_numerical_rank(O, r["A"], A_ref))

@@ -187,3 +187,47 @@ def test_serving_tickets_errors_and_restart(tilt, device):
         assert out[0] == 0
         del keep
         torch.cuda.synchronize()
+
+
+def test_serving_admission_waits_for_hbm_budget(tilt, device):
+    """A context whose HBM budget holds the workspaces of two requests:
+    of six same-shape requests submitted at once only two run; the others
+    stay pending (however long they wait) until a finished request is
+    collected and frees its workspace; all six finish, each bit for bit as
+    in tilt_solve_batch."""
+    import torch
+
+    ps = ts.make_batch(4, [23] * 6)
+    tp = tilt.default_params(max_outer=3)
+    probs, keep = device_problems(tilt, ps, device)
+    per = tilt.workspace_bytes(ps[0].m, ps[0].n, ps[0].model)
+    As = [torch.zeros((p.m, p.n), dtype=torch.float32, device=device) for p in ps]
+    Es = [torch.zeros_like(a) for a in As]
+    with tilt.Context(0, budget_bytes=int(2.5 * per)) as c:
+        tickets = [c.submit(probs[k], tp, As[k].data_ptr(), Es[k].data_ptr()) for k in range(6)]
+        # long enough for the two admitted requests to finish on the device
+        t0 = time.time()
+        while time.time() - t0 < 4.0:
+            for t in tickets[2:]:
+                assert c.poll(t) is None, "a request ran beyond the HBM budget"
+            time.sleep(0.05)
+        results = [None] * 6
+        t0 = time.time()
+        while any(r is None for r in results):
+            assert time.time() - t0 < 120, "requests did not finish"
+            for k, t in enumerate(tickets):
+                if results[k] is None:
+                    out = c.poll(t)
+                    if out is not None:
+                        results[k] = out[1]
+            time.sleep(0.002)
+    torch.cuda.synchronize()
+    for r, a, e in zip(results, As, Es):
+        r["A"] = a.cpu().numpy()
+        r["E"] = e.cpu().numpy()
+    with tilt.Context(0) as c:
+        _, batched = solve_on_device(tilt, c, ps, device, tp)
+    for a, b in zip(results, batched):
+        assert a["status"] == b["status"] and _same(a, b)
+    del keep
+

@@ -109,6 +109,57 @@ def test_argument_validation_without_device(tilt):
     assert lib.tilt_rasl_solve_batch(None, rp, 1, C.byref(prm), rr, None) == tilt.tilt.TILT_ERR_ARG
 
 
+def test_quad_initialisation_is_validated(tilt):
+    import ctypes as C
+
+    lib = tilt.tilt.library()
+    prm = tilt.default_params()
+    img = np.zeros((10, 10), np.float32)
+    res = tilt.Result()
+    pr = tilt.make_problem(img.ctypes.data, 10, 10, 10, 5, 5, 6, quad=[0, 0, 0, 0, 0, 0, 0, 0])  # degenerate
+    assert lib.tilt_solve(C.byref(pr), C.byref(prm), C.byref(res)) == tilt.tilt.TILT_ERR_ARG
+    pr = tilt.make_problem(img.ctypes.data, 10, 10, 10, 5, 5, 6, quad=[1, 1, 2, 1, 2, 3, 1, 3])
+    pr.init = 2                                                                            # unknown mode
+    assert lib.tilt_solve(C.byref(pr), C.byref(prm), C.byref(res)) == tilt.tilt.TILT_ERR_ARG
+    with pytest.raises(ValueError):
+        tilt.make_problem(img.ctypes.data, 10, 10, 10, 5, 5, 6, np.eye(3), quad=[1, 1, 2, 1, 2, 3, 1, 3])
+
+
+def test_struct_layouts_match_the_header(tilt, tmp_path):
+    """sizeof and field offsets of the ABI structs, compiled from
+    include/tilt.h with the host C compiler, against the ctypes binding."""
+    fields = {"tilt_problem": ["image", "row_stride", "m", "model", "init", "tau0", "quad"],
+              "tilt_result": ["tau", "A", "E", "outer_iters", "svt_rank", "status", "rank", "objective", "mu",
+                              "solve_ms", "done_ms", "counters"],
+              "tilt_params": ["lambda", "eps1", "max_inner", "svt_mode", "jacobi_tol", "max_sweeps",
+                              "pyramid_levels", "graph_inner"]}
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "tilt.h"', "int main(void) {"]
+    for st, fs in fields.items():
+        src.append(f'  printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            src.append(f'  printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    src.append("  return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                          check=True).stdout.splitlines())
+    T = tilt.tilt
+    py = {"tilt_problem": T.Problem, "tilt_result": T.Result, "tilt_params": T.Params}
+    for st, cls in py.items():
+        assert int(got[st]) == C_sizeof(cls), st
+        for f in fields[st]:
+            name = "lambda_" if f == "lambda" else f
+            assert int(got[f"{st}.{f}"]) == getattr(cls, name).offset, (st, f)
+
+
+def C_sizeof(cls):
+    import ctypes
+
+    return ctypes.sizeof(cls)
+
+
 def test_missing_library_fails_loudly():
     code = "import paper_1205_5351_amd"
     env = dict(os.environ, TILT_LIB="/nonexistent/libtilt.so")

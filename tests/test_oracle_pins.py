@@ -552,3 +552,47 @@ def test_tau_rel_err_uses_the_reference_frame():
     Hi = _window(100.0, 100.0, 1.0)
     assert abs(O.tau_rel_err(Hi, Hs, 50, 50) - math.sqrt(2.0) / 3.0) < 1e-15
     assert abs(O.tau_rel_err(Hs, Hi, 50, 50) - math.sqrt(2.0) / math.sqrt(3.0)) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Outer stop on the objective (reading R7 of Alg. 1's "while not converged")
+# ---------------------------------------------------------------------------
+
+
+def test_objective_stop_only_stops():
+    """The clause |f_i - f_{i-1}| < eps_obj f_{i-1} ends the outer loop and
+    changes nothing else: the solve it stops equals, bit for bit, a solve
+    capped at the same number of outer iterations, and it stops at the
+    first outer iteration (from the second on) whose objective change is
+    below the threshold, with f the objective of Eq. TILT_2 of the iterates
+    (recomputed here by an independent SVD)."""
+    rng = ts.patch_rng(78, 1)
+    p = ts.make_patch(rng, m=24, n=26, height=80, width=80, rank=2, model=6, corruption=0.05,
+                      theta_deg=6.0, skew=0.05)
+    base = dict(eps_outer=0.0, max_outer=12, max_inner=400)
+    free = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, O.Params(eps_obj=0.0, **base), lam=p.lam)
+    assert free.outer_iters == 12
+    eps_obj = 1e-4
+    stop = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, O.Params(eps_obj=eps_obj, **base), lam=p.lam)
+    k = stop.outer_iters
+    assert 2 <= k < 12
+    capped = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, O.Params(eps_obj=0.0, **dict(base, max_outer=k)),
+                          lam=p.lam)
+    assert np.array_equal(stop.tau_px, capped.tau_px) and np.array_equal(stop.A, capped.A)
+    f = [h["objective"] for h in stop.history]
+    sv = np.linalg.svd(stop.A, compute_uv=False)
+    assert abs(f[-1] - (sv.sum() + p.lam * np.abs(stop.E).sum())) <= 1e-12 * f[-1]
+    assert abs(f[k - 1] - f[k - 2]) < eps_obj * f[k - 2]
+    assert all(abs(f[i] - f[i - 1]) >= eps_obj * f[i - 1] for i in range(1, k - 1))
+
+
+def test_objective_stop_does_not_end_a_descending_drift():
+    """On the 50x50 affine workload's window the outer loop does not
+    converge in 50 iterations; its objective still falls by more than 1e-6
+    of itself at every outer iteration, so the clause at the threshold of
+    an FP64 solve (1e-9) leaves the run as it is."""
+    p = ts.make_batch(0, [0])[0]
+    r = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, O.Params(eps_obj=1e-9), lam=p.lam)
+    assert r.outer_iters == 50
+    f = np.array([h["objective"] for h in r.history])
+    assert np.all(np.abs(np.diff(f)) > 1e-6 * f[:-1])
