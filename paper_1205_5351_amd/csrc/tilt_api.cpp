@@ -793,7 +793,8 @@ int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const 
             HIP_TRY(hipEventRecord(ctx->ev0, stream));
             HIP_TRY(launch_fused(reinterpret_cast<const PatchDesc*>(ctx->descs.p),
                                  reinterpret_cast<PatchState*>(ctx->states.p), sp, nlive, L,
-                                 reinterpret_cast<const int*>(ctx->order.p), dfc, grid, max_lds, stream));
+                                 reinterpret_cast<const int*>(ctx->order.p), dfc,
+                                 (any_tiled && helpers_enabled()) ? 1 : 0, grid, max_lds, stream));
             HIP_TRY(hipEventRecord(ctx->ev1, stream));
             ctx->live_count.store(nlive);
             ctx->live_fc.store(dfc);

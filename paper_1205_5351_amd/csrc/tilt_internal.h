@@ -259,8 +259,10 @@ struct ServeCtl {
 };
 
 // Kernel launchers (tilt_kernels.hip).
+// help = 1: workgroups that run out of requests help the leaders of tiled
+// windows until every request is done (else they exit).
 hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, int levels,
-                        const int* order, FusedCtl* fc, int grid, size_t lds, hipStream_t s);
+                        const int* order, FusedCtl* fc, int help, int grid, size_t lds, hipStream_t s);
 hipError_t launch_wide_setup(const PatchDesc* d, PatchState* st, const SolverParams& prm, const float* I,
                              const float* J, int count, size_t lds, hipStream_t s);
 hipError_t launch_wide_stage(const PatchDesc* d, PatchState* st, const int* active, int nactive, int form_m,

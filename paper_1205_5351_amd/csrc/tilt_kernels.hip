@@ -574,7 +574,7 @@ __device__ void jacobi_svd_rows(float* B, float* Rm, int nc, int ld, float tol, 
     TILT_SVT_CASE_T(S, L, 1, 1) TILT_SVT_CASE_T(S, L, 2, 1) TILT_SVT_CASE_T(S, L, 3, 1)           \
     TILT_SVT_CASE_T(S, L, 1, 2) TILT_SVT_CASE_T(S, L, 2, 2) TILT_SVT_CASE_T(S, L, 3, 2)
 
-__device__ void jacobi_dispatch(int cfg, float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js,
+__device__ __forceinline__ void jacobi_dispatch(int cfg, float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js,
                                 float* s2) {
     switch (cfg) {
         TILT_SVT_CASES8(1, 4) TILT_SVT_CASES8(1, 8) TILT_SVT_CASES8(1, 16)
@@ -602,7 +602,7 @@ __device__ void jacobi_dispatch(int cfg, float* B, int nc, int ld, float tol, in
     TILT_WARM_CASE_T(S, L, 1, 1) TILT_WARM_CASE_T(S, L, 2, 1) TILT_WARM_CASE_T(S, L, 3, 1)          \
     TILT_WARM_CASE_T(S, L, 1, 2) TILT_WARM_CASE_T(S, L, 2, 2) TILT_WARM_CASE_T(S, L, 3, 2)
 
-__device__ void jacobi_dispatch_warm(int cfg, float* B, float* Rm, int nc, int ld, float tol, int max_sweeps,
+__device__ __forceinline__ void jacobi_dispatch_warm(int cfg, float* B, float* Rm, int nc, int ld, float tol, int max_sweeps,
                                      JacobiStats& js, float* s2) {
     switch (cfg) {
         TILT_WARM_CASES4(1, 4) TILT_WARM_CASES4(1, 8) TILT_WARM_CASES4(1, 16)
@@ -775,6 +775,15 @@ __device__ inline int gang_load(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Polling loads are relaxed: an agent-scope acquire invalidates the
+// non-coherent lines of the XCD's L2 (and its dirty lines go back to
+// memory), which, repeated by every spinning workgroup, would evict the
+// working sets of the workgroups still solving.  Data is acquired once,
+// after the awaited value has been seen.
+__device__ inline int poll_load(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ inline void release_all_waves() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
@@ -812,7 +821,7 @@ __device__ void jacobi_tiled_shared(GangCtl* c, int cfg, float* Bg, float* Rg, i
     int sweeps = 0;
     int helped = 0;  // pairs run by helpers so far in this decomposition
     int base_done = 0;
-    if (tid == 0) sh_v = gang_load(&c->done);
+    if (tid == 0) sh_v = poll_load(&c->done);
     __syncthreads();
     base_done = sh_v;
     __syncthreads();
@@ -820,7 +829,7 @@ __device__ void jacobi_tiled_shared(GangCtl* c, int cfg, float* Bg, float* Rg, i
         int any = 0;
         int first_id = 0;  // id of this sweep's first published round (0: none)
         for (int r = 0; r < Nb; ++r) {
-            if (tid == 0) sh_v = (Pb > 1 && gang_load(&fc->idle) > 0) ? 1 : 0;
+            if (tid == 0) sh_v = (Pb > 1 && poll_load(&fc->idle) > 0) ? 1 : 0;
             __syncthreads();
             const int publish = sh_v;
             __syncthreads();
@@ -883,7 +892,7 @@ __device__ void jacobi_tiled_shared(GangCtl* c, int cfg, float* Bg, float* Rg, i
             }
             helped += Pb - mine;
             if (tid == 0)
-                while (gang_load(&c->done) < base_done + helped) __builtin_amdgcn_s_sleep(1);
+                while (poll_load(&c->done) < base_done + helped) __builtin_amdgcn_s_sleep(1);
             acquire_all_waves();
         }
         ++sweeps;
@@ -902,16 +911,16 @@ __device__ void jacobi_tiled_shared(GangCtl* c, int cfg, float* Bg, float* Rg, i
     }
 }
 
-// Helper: find a published round with an unclaimed pair among the
-// registered leaders, claim it and run it; returns 0 when nothing was open.
-__device__ int help_once(FusedCtl* fc, float* mini) {
-    __shared__ int sh_g, sh_k;
-    __shared__ unsigned sh_id;
-    __shared__ GangCtl sh_job;
+// Helper, first half (inlined into the kernel's idle loop, no call): wave
+// 0 looks for a published round with an unclaimed pair among the
+// registered leaders and thread 0 tries to claim it.  On success the
+// round's parameters, id and pair are left in *job, *id and the return
+// value is the leader's index; else -1.
+__device__ __forceinline__ int help_find(FusedCtl* fc, GangCtl* job, unsigned* id, int* pair) {
+    __shared__ int sh_g;
     const int tid = threadIdx.x;
     if (tid < 64) {
-        // wave 0 scans the slots, 64 at a time, from a start that differs
-        // between workgroups
+        // 64 slots at a time, from a start that differs between workgroups
         const int start = (int)((blockIdx.x * 97u) & (HELP_SLOTS - 1));
         int found = -1;
         for (int base = 0; base < HELP_SLOTS && found < 0; base += 64) {
@@ -930,48 +939,50 @@ __device__ int help_once(FusedCtl* fc, float* mini) {
             }
         }
         if (tid == 0) {
-            sh_g = found;
-            sh_k = -1;
+            sh_g = -1;
             if (found >= 0) {
                 GangCtl* c = fc->gangs + found;
-                const unsigned long long w = __hip_atomic_load(&c->word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long w = __hip_atomic_load(&c->word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 // parameters of the round named by w: valid if the claim below
                 // succeeds (a newer round is published only after every pair
-                // of this one was claimed and finished)
-                sh_job.Bg = c->Bg;
-                sh_job.Rg = c->Rg;
-                sh_job.sb = c->sb;
-                sh_job.nsb = c->nsb;
-                sh_job.ldg = c->ldg;
-                sh_job.ld = c->ld;
-                sh_job.cfg = c->cfg;
-                sh_job.r = c->r;
-                sh_job.tol = c->tol;
-                sh_id = (unsigned)(w >> kRoundIdShift);
-                sh_k = gang_try_claim(c, w);
+                // of this one was claimed and finished; the claim acquires)
+                job->Bg = c->Bg;
+                job->Rg = c->Rg;
+                job->sb = c->sb;
+                job->nsb = c->nsb;
+                job->ldg = c->ldg;
+                job->ld = c->ld;
+                job->cfg = c->cfg;
+                job->r = c->r;
+                job->tol = c->tol;
+                *id = (unsigned)(w >> kRoundIdShift);
+                *pair = gang_try_claim(c, w);
+                if (*pair >= 0) sh_g = found;
             }
         }
     }
     __syncthreads();
-    const int g = sh_g, k = sh_k;
-    if (g < 0 || k < 0) {
-        __syncthreads();
-        return 0;
-    }
+    const int g = sh_g;
+    __syncthreads();
+    return g;
+}
+
+// Helper, second half (out of line; called only with a claimed pair): run
+// pair k of the round described by *job of leader g and report it done.
+__device__ __noinline__ void help_run(FusedCtl* fc, int g, const GangCtl* job, unsigned id, int k, float* mini) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     GangCtl* c = fc->gangs + g;
     JacobiStats jr{0, 0, 0};
-    const int rot = superblock_task(sh_job.cfg, sh_job.Bg, sh_job.Rg, sh_job.sb, sh_job.nsb, sh_job.ldg, sh_job.ld,
-                                    mini, sh_job.tol, sh_job.r, k, jr);
+    const int rot =
+        superblock_task(job->cfg, job->Bg, job->Rg, job->sb, job->nsb, job->ldg, job->ld, mini, job->tol, job->r, k, jr);
     release_all_waves();
-    if (tid == 0) {
-        if (rot) atomicMax(&c->rot, (int)sh_id);
+    if (threadIdx.x == 0) {
+        if (rot) atomicMax(&c->rot, (int)id);
         if (jr.pairs) atomicAdd(&c->pairs, (unsigned long long)jr.pairs);
         if (jr.rotations) atomicAdd(&c->rotations, (unsigned long long)jr.rotations);
         __hip_atomic_fetch_add(&c->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    return 1;
 }
 
 // The tiled Jacobi of the ncp rows of Bg (with the rotation rows Rg when
@@ -2021,6 +2032,36 @@ __device__ void svt_finish(const PatchDesc& d, PatchState* st, const SvtLds& L, 
     __syncthreads();
 }
 
+// Warm-started SVT of a tiled window (rare: only windows beyond LDS with
+// svt_mode 1), kept out of line so that dev_svt's common paths keep their
+// registers.
+__device__ __noinline__ void svt_tiled_warm(const PatchDesc& d, PatchState* st, const SolverParams& prm,
+                                            const SvtLds& L, float tol, JacobiStats& js) {
+    const int nc = d.nc, ldg = d.ldg, ld = d.ld;
+    const size_t np = (size_t)nc * ldg;
+    float* M = d.ws + PL_M * np;
+    float* Bg = d.ws + NPLANES * np;
+    // The rotation lives in its own working plane (ncp rows, so that it
+    // is staged by super-blocks with the Jacobi rows).
+    float* Rg = Bg + (size_t)d.ncp * ldg;
+    const bool saved = st->warm_ok != 0;
+    __syncthreads();
+    if (!saved) rotation_identity_global(Rg, nc, d.ncp, ldg);
+    else if (prm.ns_every > 0 && st->warm_count % prm.ns_every == 0)
+        newton_schulz_global(Rg, nc, ldg, d.ws + (PL_Q + 6) * np, d.ws + (PL_Q + 7) * np, Bg);
+    // B = R M into the Jacobi rows (rows nc.. of Bg stay zero)
+    mfma_gemm<false>(Rg, ldg, nc, M, ldg, ldg, nc, Bg, ldg);
+    for (int e = threadIdx.x; e < (d.ncp - nc) * ldg; e += NT) Bg[(size_t)nc * ldg + e] = 0.f;
+    __syncthreads();
+    jacobi_tiled(d.svt_cfg, Bg, Rg, d.sb, d.nsb, ldg, ld, L.B, tol, prm.max_sweeps, js, d.gang);
+    row_norms_global(Bg, nc, ldg, L.s2);
+    if (threadIdx.x == 0) {
+        st->warm_ok = 1;
+        st->warm_count += 1;
+    }
+}
+
+
 __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& prm, float* lds) {
     const int nc = d.nc, ldg = d.ldg, ld = d.ld;
     const size_t np = (size_t)nc * ldg;
@@ -2035,24 +2076,7 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
     const float tol = svt_tolerance(prm.jacobi_tol, prm.eps2, st->mu);
     JacobiStats js{0, 0, 0};
     if (warm && tiled) {
-        // The rotation lives in its own working plane (ncp rows, so that it
-        // is staged by super-blocks with the Jacobi rows).
-        float* Rg = Bg + (size_t)d.ncp * ldg;
-        const bool saved = st->warm_ok != 0;
-        __syncthreads();
-        if (!saved) rotation_identity_global(Rg, nc, d.ncp, ldg);
-        else if (prm.ns_every > 0 && st->warm_count % prm.ns_every == 0)
-            newton_schulz_global(Rg, nc, ldg, d.ws + (PL_Q + 6) * np, d.ws + (PL_Q + 7) * np, Bg);
-        // B = R M into the Jacobi rows (rows nc.. of Bg stay zero)
-        mfma_gemm<false>(Rg, ldg, nc, M, ldg, ldg, nc, Bg, ldg);
-        for (int e = threadIdx.x; e < (d.ncp - nc) * ldg; e += NT) Bg[(size_t)nc * ldg + e] = 0.f;
-        __syncthreads();
-        jacobi_tiled(d.svt_cfg, Bg, Rg, d.sb, d.nsb, ldg, ld, L.B, tol, prm.max_sweeps, js, d.gang);
-        row_norms_global(Bg, nc, ldg, L.s2);
-        if (threadIdx.x == 0) {
-            st->warm_ok = 1;
-            st->warm_count += 1;
-        }
+        svt_tiled_warm(d, st, prm, L, tol, js);
     } else if (warm) {
         float* V = d.ws + PL_V * np;
         const bool saved = st->warm_ok != 0;
@@ -2473,7 +2497,7 @@ __device__ void solve_request(const PatchDesc* dl, int levels, PatchState* st, c
 // level descriptors at descs[i * levels ...].
 __global__ void __launch_bounds__(NT) k_fused(const PatchDesc* __restrict__ descs, PatchState* states,
                                                SolverParams prm, int count, int levels,
-                                               const int* __restrict__ order, FusedCtl* fc) {
+                                               const int* __restrict__ order, FusedCtl* fc, int help) {
     __shared__ int sh_idx;
     float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
     for (;;) {
@@ -2494,15 +2518,23 @@ __global__ void __launch_bounds__(NT) k_fused(const PatchDesc* __restrict__ desc
             __hip_atomic_fetch_add(&fc->remaining, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+    if (!help) return;  // no window of this launch is tiled
+    __shared__ GangCtl sh_job;
+    __shared__ unsigned sh_id;
+    __shared__ int sh_pair;
     if (threadIdx.x == 0) __hip_atomic_fetch_add(&fc->idle, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
-        if (help_once(fc, lds)) continue;
-        if (threadIdx.x == 0) sh_idx = gang_load(&fc->remaining);
+        const int g = help_find(fc, &sh_job, &sh_id, &sh_pair);
+        if (g >= 0) {
+            help_run(fc, g, &sh_job, sh_id, sh_pair, lds);
+            continue;
+        }
+        if (threadIdx.x == 0) sh_idx = poll_load(&fc->remaining);
         __syncthreads();
         const int left = sh_idx;
         __syncthreads();
         if (left <= 0) break;
-        __builtin_amdgcn_s_sleep(8);
+        __builtin_amdgcn_s_sleep(32);
     }
 }
 
@@ -2540,10 +2572,13 @@ __global__ void __launch_bounds__(NT) k_serve(ServeCtl* ctl, ServeSlot* slots, P
             unsigned long long* closing = ctr + 2;
             unsigned long long* last_done = ctr + 3;
             long long seq = -1;
-            const bool closed = __hip_atomic_load(closing, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0ull;
+            // polls are relaxed (an acquire would invalidate the L2 lines the
+            // solving workgroups of this XCD work from); a claimed request's
+            // slot is acquired below
+            const bool closed = __hip_atomic_load(closing, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull;
             if (!closed) {
                 const unsigned long long tail =
-                    __hip_atomic_load(&ctl->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                    __hip_atomic_load(&ctl->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 unsigned long long h = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (h < tail) {
                     // counted as busy before the claim, so that no workgroup
@@ -2557,6 +2592,9 @@ __global__ void __launch_bounds__(NT) k_serve(ServeCtl* ctl, ServeSlot* slots, P
                         }
                     }
                     if (seq < 0) __hip_atomic_fetch_add(busy, ~0ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                    // pairs with the host's release of `tail`: the slot's
+                    // contents are visible from here on
+                    if (seq >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
                 }
             }
             if (seq < 0) {
@@ -3015,10 +3053,10 @@ static hipError_t set_lds(const void* fn, size_t lds) {
 }
 
 hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& prm, int count, int levels,
-                        const int* order, FusedCtl* fc, int grid, size_t lds, hipStream_t s) {
+                        const int* order, FusedCtl* fc, int help, int grid, size_t lds, hipStream_t s) {
     hipError_t e = set_lds((const void*)k_fused, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(NT), lds, s, d, st, prm, count, levels, order, fc);
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(NT), lds, s, d, st, prm, count, levels, order, fc, help);
     return hipGetLastError();
 }
 

@@ -102,3 +102,35 @@ def test_helped_tiled_window_matches_oracle(tilt, ctx, device, svt_mode):
     assert np.linalg.norm(r["A"] - ref.A) <= 1e-4 * np.linalg.norm(ref.A)
     assert np.linalg.norm(r["E"] - ref.E) <= 1e-3 * max(np.linalg.norm(ref.E), 1e-12)
     assert O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n) <= 1e-5
+
+
+def test_full_uneven_batch_one_launch_against_oracle(tilt, ctx, device):
+    """All 1024 windows of the uneven warm-started workload in one fused
+    launch (svt_mode 1, idle workgroups helping the tiled windows), for a
+    fixed 2 outer x 15 inner iterations so that the oracle can follow:
+    every window returns TILT_OK, and sampled windows -- the two largest
+    tiled ones, one each of the other SVT kinds (in LDS cold, in LDS warm)
+    and the smallest -- match the FP64 oracle (fixed-count tolerances: A
+    within 1e-4, tau within 1e-5)."""
+    patches = ts.make_config(2)
+    assert len(patches) == 1024
+    tp = tilt.default_params(svt_mode=1, fixed_iters=1, max_outer=2, max_inner=15)
+    _, res = solve_on_device(tilt, ctx, patches, device, tp)
+    assert all(r["status"] == 0 for r in res)
+
+    def cells(p):
+        return min(p.m, p.n) * ((max(p.m, p.n) + 3) // 4 * 4)
+
+    order = sorted(range(1024), key=lambda i: -cells(patches[i]))
+    tiled = order[:2]
+    mid = next(i for i in order if 20000 < cells(patches[i]) < 30000)       # in LDS, cold (rotation does not fit)
+    warm = next(i for i in order if 8000 < cells(patches[i]) < 12000)       # in LDS, warm
+    small = order[-1]
+    for i in tiled + [mid, warm, small]:
+        p, r = patches[i], res[i]
+        ref = O.tilt_solve(p.image, p.tau0, p.m, p.n, p.model, oracle_params(O, tp), lam=p.lam)
+        err_a = np.linalg.norm(r["A"] - ref.A) / np.linalg.norm(ref.A)
+        err_t = O.tau_rel_err(r["tau"], ref.tau_px, p.m, p.n)
+        print(f"window {i} ({p.m}x{p.n}): A {err_a:.1e} tau {err_t:.1e}", flush=True)
+        assert err_a <= 1e-4 and err_t <= 1e-5, (i, err_a, err_t)
+
