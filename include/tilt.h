@@ -297,6 +297,29 @@ int tilt_svt_batch_noalloc(const float* M, float* A, float* sigma, int count, in
                            const float* eps, const tilt_params* prm, int* ranks, tilt_counters* counters,
                            void* hip_stream);
 
+/* SVD with warm start (Sec. 5, Alg. 2, with the derivatives of Appendix A):
+ * one Cayley step per matrix, for `count` matrices of one shape m x n
+ * (m >= n, n <= 256, m <= 4096), DEVICE arrays back to back, row-major:
+ * the previous decomposition U (m x n, orthonormal columns), S (n), V
+ * (n x n, orthogonal; M ~ U diag(S) V^T) and the next matrix M (m x n).
+ * The step searches U(t) = (I + t/2 P_U)^{-1} (I - t/2 P_U) U, S(t) =
+ * S - t P_S, V(t) = (I + t/2 P_V)^{-1} (I - t/2 P_V) V along the projected
+ * gradients of 1/2 ||M - U S V^T||_F^2 (Eqs. projected_gradient1-3) and
+ * takes t = -f'(0)/f''(0) of the model of Eq. ft.  P_U (m x m, rank <= 2n)
+ * is never formed; its Cayley factor goes through the Woodbury identity
+ * (a 2n x 2n solve).  Outputs U_out, S_out, V_out (DEVICE, the input
+ * shapes) and, unless A_out is NULL, A_out = U(t) T_eps(S(t)) V(t)^T with
+ * the signed soft threshold eps[i] (HOST array).  HOST arrays t_out, f0_out
+ * (f(0)), ft_out (f(t)) and status may be NULL.  status[i]: 0 = step taken;
+ * 1 = f''(0) <= 0, no step (outputs = inputs; Alg. 2's caller computes a
+ * full SVD instead, as it does when ||M - M_prev|| >= eps_svd); -4 = a
+ * singular system.  Alg. 2's switch between this step and a full SVD is the
+ * caller's.  Synchronous; returns the worst error status (warnings are not
+ * reported in the return value). */
+int tilt_svdws_batch(tilt_ctx* ctx, int count, int m, int n, const float* U, const float* S, const float* V,
+                     const float* M, float* U_out, float* S_out, float* V_out, float* A_out, const float* eps,
+                     double* t_out, double* f0_out, double* ft_out, int* status, void* hip_stream);
+
 /* Alg. 1 Step 1 on its own: the normalised warp D o tau / ||D o tau||_F
  * (I_out: count x m x n) and the Jacobian of the normalised warp w.r.t.
  * the p entries of tau in scaled coordinates (J_out: count x p x m x n,

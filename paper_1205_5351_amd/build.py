@@ -19,8 +19,8 @@ INCLUDE = os.path.join(REPO_DIR, "include")
 LIB_NAME = "libtilt.so"
 LIB_PATH = os.path.join(PKG_DIR, LIB_NAME)
 
-SOURCES = ["tilt_kernels.hip", "tilt_peaks.hip", "tilt_noalloc.hip", "tilt_api.cpp", "tilt_serve.cpp",
-           "tilt_rasl.cpp"]
+SOURCES = ["tilt_kernels.hip", "tilt_peaks.hip", "tilt_noalloc.hip", "tilt_svdws.hip", "tilt_api.cpp",
+           "tilt_serve.cpp", "tilt_rasl.cpp"]
 ARCH = "gfx950"
 
 

@@ -222,6 +222,26 @@ struct SvtJob {
     int pad;
 };
 
+// One step of the SVD with warm start (component entry point): the
+// previous decomposition (U m x n, S n, V n x n), the next matrix M (m x n,
+// m >= n), the outputs, the threshold of the optional shrinkage A_out, and
+// the step size, f(0), f(t) and status written back.
+struct SvdwsJob {
+    const float* U;
+    const float* S;
+    const float* V;
+    const float* M;
+    float* U_out;
+    float* S_out;
+    float* V_out;
+    float* A_out;
+    float eps;
+    int status;
+    double t, f0, ft;
+};
+size_t svdws_scratch_bytes(int m, int n);
+hipError_t launch_svdws(SvdwsJob* jobs, int count, int m, int n, float* scratch, hipStream_t s);
+
 // LDS layout helpers (host and device).
 // cfg = TL * 256 + (BS - 1) * 128 + log2(LPP / 4) * 16 + (NCH - 1): blocks of
 // BS rows, LPP lanes per block pair, NCH float4 chunks per lane and row,

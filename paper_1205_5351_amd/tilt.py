@@ -193,6 +193,10 @@ _lib.tilt_svt_batch_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_
                                         C.POINTER(C.c_float), C.POINTER(Params), C.POINTER(C.c_int),
                                         C.POINTER(Counters), C.c_void_p]
 _lib.tilt_svt_batch_noalloc.restype = C.c_int
+_lib.tilt_svdws_batch.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int] + [C.c_void_p] * 8 + [
+    C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+    C.POINTER(C.c_int), C.c_void_p]
+_lib.tilt_svdws_batch.restype = C.c_int
 _lib.tilt_warp_jacobian.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(C.c_double), C.c_int,
                                     C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.tilt_warp_jacobian.restype = C.c_int
@@ -227,7 +231,7 @@ _lib.tilt_rasl_solve_batch.restype = C.c_int
 EXPORTS = [
     "tilt_default_params", "tilt_status_string", "tilt_version", "tilt_tau_from_quad", "tilt_solve",
     "tilt_ctx_create", "tilt_ctx_destroy", "tilt_workspace_bytes", "tilt_solve_batch",
-    "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_svt_batch_noalloc", "tilt_warp_jacobian", "tilt_last_error",
+    "tilt_solve_batch_plain", "tilt_svt_batch", "tilt_svt_batch_noalloc", "tilt_svdws_batch", "tilt_warp_jacobian", "tilt_last_error",
     "tilt_ctx_last_kernel_ms", "tilt_ctx_progress", "tilt_submit", "tilt_poll", "tilt_serve_stop", "tilt_pyramid",
     "tilt_inner_batch", "tilt_svt_layouts", "tilt_svt_layout", "tilt_tune_set", "tilt_tune_clear",
     "tilt_rasl_solve_batch", "tilt_peak_probe",
@@ -484,6 +488,26 @@ class Context:
         if rc != TILT_OK:
             raise TiltError(rc, "tilt_ctx_progress")
         return f.value, t.value
+
+    def svdws_batch(self, count: int, m: int, n: int, U_ptr: int, S_ptr: int, V_ptr: int, M_ptr: int,
+                    U_out: int, S_out: int, V_out: int, A_out: int = 0, eps=None, stream=None):
+        """One warm-start Cayley step per matrix (tilt_svdws_batch), DEVICE
+        pointers.  Returns (rc, t, f0, ft, status) with the per-matrix arrays
+        as numpy arrays."""
+        t = (C.c_double * count)()
+        f0 = (C.c_double * count)()
+        ft = (C.c_double * count)()
+        st = (C.c_int * count)()
+        earr = None
+        if A_out:
+            e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.float32), (count,)))
+            earr = (C.c_float * count)(*e.tolist())
+        ptrs = [C.c_void_p(int(x)) if x else None for x in (U_ptr, S_ptr, V_ptr, M_ptr, U_out, S_out, V_out, A_out)]
+        rc = _lib.tilt_svdws_batch(self._h, int(count), int(m), int(n), *ptrs, earr, t, f0, ft, st,
+                                   C.c_void_p(_stream_ptr(stream)))
+        if rc < 0:
+            raise TiltError(rc, "tilt_svdws_batch")
+        return rc, np.array(list(t)), np.array(list(f0)), np.array(list(ft)), np.array(list(st))
 
     def solve_batch(self, problems, params=None, outs_A=None, outs_E=None, stream=None):
         """Fused persistent kernel over all problems (device images/outputs)."""
