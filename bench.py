@@ -240,6 +240,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="patches solved by the CPU oracle (default: one per host core)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--per-patch", default=None, metavar="FILE",
+                    help="write one JSON line per patch of the last timed launch (shape, iterations, solve time, "
+                         "SVT calls and sweeps) to FILE")
     ap.add_argument("--svt-mode", type=int, default=None, choices=(0, 1),
                     help="0: cold Jacobi SVT every iteration; 1: warm start (default: the workload's definition, "
                          "cold for workload 1, warm for workload 2)")
@@ -399,6 +402,23 @@ def main():
     lds_tbs = jac_lds / (k_ms * 1e-3) / 1e12
     outer = np.array(outer_all)
     inner = np.array([r["inner_iters_total"] for r in res])
+    # the slowest patches of the launch (they set its length when few are
+    # left running)
+    tail = []
+    for i in np.argsort(-solve_ms)[:5]:
+        r, p = res[int(i)], patches[int(i)]
+        tail.append({"idx": int(i), "m": p.m, "n": p.n, "outer": int(r["outer_iters"]),
+                     "inner": int(r["inner_iters_total"]), "solve_ms": round(float(solve_ms[i]), 1),
+                     "ms_per_inner": round(float(solve_ms[i]) / max(int(r["inner_iters_total"]), 1), 3),
+                     "sweeps_per_svd": round(r["counters"]["jacobi_sweeps"] / max(r["counters"]["svt_calls"], 1), 2)})
+    if args.per_patch:
+        with open(args.per_patch, "w") as f:
+            for i, (r, p) in enumerate(zip(res, patches)):
+                f.write(json.dumps({"idx": i, "m": p.m, "n": p.n, "model": p.model, "status": int(r["status"]),
+                                    "outer": int(r["outer_iters"]), "inner": int(r["inner_iters_total"]),
+                                    "solve_ms": round(float(solve_ms[i]), 2), "done_ms": round(float(done_ms[i]), 2),
+                                    "svt_calls": int(r["counters"]["svt_calls"]),
+                                    "sweeps": int(r["counters"]["jacobi_sweeps"])}) + "\n")
     sweeps = sum(r["counters"]["jacobi_sweeps"] for r in res) / max(sum(r["counters"]["svt_calls"] for r in res), 1)
 
     cpu = None
@@ -495,7 +515,8 @@ def main():
                  "rectified": n_ok, "status_ok": sum(1 for s in statuses if s == 0),
                  "status_maxiter": sum(1 for s in statuses if s == 1),
                  "outer_at_max": int(np.sum(outer >= prm.max_outer)),
-                 "errors": sum(1 for s in statuses if s < 0)},
+                 "errors": sum(1 for s in statuses if s < 0),
+                 "slowest": tail},
         "roofline": {
             "kernel": "k_fused (whole solves; one workgroup per patch, idle workgroups help tiled windows)",
             "bound": "alu",

@@ -190,7 +190,18 @@ int choose_svt_cfg(int nc, int nr4) {
     return t >= 0 ? t : pick_svt_cfg(nc, nr4, true);
 }
 
-int shape_config(int m, int n, ShapeCfg* out) {
+// Workgroups the tiled super-block size is planned for: kHelpPlan, or
+// TILT_HELP_PLAN (1..16) from the environment, read once.
+int help_plan() {
+    static const int v = [] {
+        const char* e = std::getenv("TILT_HELP_PLAN");
+        const int k = e ? std::atoi(e) : 0;
+        return k >= 1 && k <= 16 ? k : kHelpPlan;
+    }();
+    return v;
+}
+
+int shape_config(int m, int n, ShapeCfg* out, bool warm) {
     ShapeCfg c;
     c.colmajor = m >= n ? 1 : 0;
     c.nc = std::min(m, n);
@@ -224,13 +235,28 @@ int shape_config(int m, int n, ShapeCfg* out) {
                         }
                     }
                     *out = c;
+                    // a warm-started solve whose rotation does not fit
+                    // beside the rows takes the tiled layout when that one
+                    // can carry the rotation (fewer sweeps per SVT than
+                    // the cold SVT in LDS, and idle workgroups can help)
+                    if (!warm || c.warm_lds > 0) return TILT_OK;
+                    ShapeCfg t;
+                    if (tiled_config(c, &t, true) == TILT_OK) *out = t;
                     return TILT_OK;
                 }
             }
         }
     }
+    return tiled_config(c, out);
+}
+
+// Tiled layout of a window (the fields set from the window's sides in c);
+// need_warm: only layouts that can carry the rotation of the warm start.
+int tiled_config(const ShapeCfg& c, ShapeCfg* out, bool need_warm) {
+    const int nc4 = (c.nc + 3) & ~3;
+    const size_t budget = (size_t)LDS_LIMIT - kStaticLdsMargin;
     if (c.nr > SVT_MAX_COLS) return TILT_ERR_TOO_LARGE;
-    // Tiled: the super-block size is chosen for up to kHelpPlan
+    // Tiled: the super-block size is chosen for up to help_plan()
     // workgroups on one window (the fused kernel lets idle workgroups take
     // pairs of a round): the modelled time of a sweep is (rounds) x (pairs
     // per workgroup) x (one staged sweep over 2 sb rows, plus staging the
@@ -251,8 +277,22 @@ int shape_config(int m, int n, ShapeCfg* out) {
         const int ld = pick_ld(cfg);
         task += 8.0 * (2.0 * sb) * (c.ldg / 4);  // staging both blocks in and out
         const int pairs = nsb / 2;
-        const int members = std::min(pairs, kHelpPlan);
+        const int members = std::min(pairs, help_plan());
         const double t = (nsb - 1) * (double)((pairs + members - 1) / members) * task;
+        // warm start: the staged rotation rows double the staged pair
+        // (chunks per lane up to 4, as in LDS)
+        int wtb_fit = 0;
+        size_t wl_fit = 0;
+        if (svt_nch(cfg) <= 4 && svt_lpp(cfg) <= 16)
+            for (int wtb = 32; wtb >= 16; wtb -= 16) {
+                const size_t wl = lds_bytes_tiled(sb, ncp, ld, c.ldg, wtb, true);
+                if (wl <= budget) {
+                    wtb_fit = wtb;
+                    wl_fit = wl;
+                    break;
+                }
+            }
+        if (need_warm && !wtb_fit) continue;
         for (int tb = 32; tb >= 16; tb -= 16) {
             const size_t lds = lds_bytes_tiled(sb, ncp, ld, c.ldg, tb);
             if (lds <= budget) {
@@ -268,19 +308,8 @@ int shape_config(int m, int n, ShapeCfg* out) {
                     best.ws_floats = (size_t)NPLANES * c.nc * c.ldg + 2 * (size_t)ncp * c.ldg;
                     best_t = t;
                     found = true;
-                    // warm start: the staged rotation rows double the
-                    // staged pair (chunks per lane up to 4, as in LDS)
-                    best.warm_tb = 0;
-                    best.warm_lds = 0;
-                    if (svt_nch(cfg) <= 4 && svt_lpp(cfg) <= 16)
-                        for (int wtb = 32; wtb >= 16; wtb -= 16) {
-                            const size_t wl = lds_bytes_tiled(sb, ncp, ld, c.ldg, wtb, true);
-                            if (wl <= budget) {
-                                best.warm_tb = wtb;
-                                best.warm_lds = wl;
-                                break;
-                            }
-                        }
+                    best.warm_tb = wtb_fit;
+                    best.warm_lds = wl_fit;
                 }
                 break;
             }
@@ -415,7 +444,7 @@ int plan_request(const tilt_problem& pr, const tilt_params* prm, float* A_out, f
         hl[l] = l == 0 ? pr.height : (hl[l - 1] + 1) / 2;
         wl[l] = l == 0 ? pr.width : (wl[l - 1] + 1) / 2;
         if (ml[l] < 2 || nl[l] < 2 || hl[l] < 2 || wl[l] < 2) return TILT_ERR_ARG;
-        st = shape_config(ml[l], nl[l], &sc[l]);
+        st = shape_config(ml[l], nl[l], &sc[l], prm->svt_mode == 1);
         if (st != TILT_OK) return st;
         planes = std::max(planes, sc[l].ws_floats);
         P.lds = std::max(P.lds, warm_level(prm, sc[l]) ? sc[l].warm_lds : sc[l].lds);
@@ -1185,9 +1214,11 @@ int tilt_ctx_last_kernel_ms(tilt_ctx* ctx, double* ms) {
 
 size_t tilt_workspace_bytes(const tilt_problem* prob) {
     if (!prob) return 0;
-    ShapeCfg sc{};
-    if (shape_config(prob->m, prob->n, &sc) != TILT_OK) return 0;
-    return sc.ws_floats * sizeof(float) + sizeof(PatchDesc) + sizeof(PatchState);
+    // the larger of the cold and the warm-started layout
+    ShapeCfg sc{}, sw{};
+    if (shape_config(prob->m, prob->n, &sc) != TILT_OK || shape_config(prob->m, prob->n, &sw, true) != TILT_OK)
+        return 0;
+    return std::max(sc.ws_floats, sw.ws_floats) * sizeof(float) + sizeof(PatchDesc) + sizeof(PatchState);
 }
 
 int tilt_solve_batch(tilt_ctx* ctx, const tilt_problem* probs, int count, const tilt_params* prm,

@@ -38,7 +38,11 @@ struct ShapeCfg {
     size_t warm_lds;   // warm-started SVT: dynamic LDS bytes
 };
 
-int shape_config(int m, int n, ShapeCfg* out);
+// warm: the layout of a warm-started solve (svt_mode 1), which takes the
+// tiled layout where the rotation fits only there.
+int shape_config(int m, int n, ShapeCfg* out, bool warm = false);
+int tiled_config(const ShapeCfg& c, ShapeCfg* out, bool need_warm = false);
+int help_plan();
 double predicted_cost(const PatchDesc& d);
 
 int validate_params(const tilt_params* p);

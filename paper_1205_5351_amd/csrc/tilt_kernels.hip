@@ -401,22 +401,11 @@ __device__ void row_norms(const float* B, int nrows, int ld, float* s2) {
 // Squared row norms during the sweeps: one LDS array for every variant.
 __shared__ float tilt_jacobi_nrm[SVT_MAX_ROWS];
 
-// One round of the circle ordering: every lane group takes block pairs
-// k = g, g + G, ... of round r.  FIRST (round 0 of a sweep) also rotates
-// the pairs inside each block of two rows; it is a separate instance so the
-// other rounds carry no conditional stage.
-template <int BS, int LPP, int NCH, int TL, bool WARM, bool FIRST>
-__device__ inline void jacobi_round(float* B, float* Rm, float* nrm, int ld, int r, int Nb, int Pb, int g, int q,
-                                    float tol, int& any, long long& rots) {
-    constexpr int G = NT / LPP;
-    // WARM: the rotation rows of the block pair (same layout as the Jacobi
-    // rows) stay in registers for the round and take the same rotations.
-    constexpr int RN = WARM ? NCH : 1;
-    constexpr int RT = WARM ? TL : 0;
-    using Row = RowPart<NCH, TL>;
-    using RRow = RowPart<RN, RT>;
-    for (int k = g; k < Pb; k += G) {
-        int I, J;
+// Block pair k of round r of the circle ordering over Nb + 1 blocks (Nb
+// odd): block Nb meets block r, and blocks r + k and r - k (mod Nb) meet.
+struct CirclePairs {
+    int r, Nb;
+    __device__ inline void operator()(int k, int& I, int& J) const {
         if (k == 0) {
             I = Nb;
             J = r;
@@ -426,6 +415,26 @@ __device__ inline void jacobi_round(float* B, float* Rm, float* nrm, int ld, int
             J = r - k;
             if (J < 0) J += Nb;
         }
+    }
+};
+
+// One round of block pairs: every lane group takes pairs k = g, g + G, ...
+// of the Pb pairs that `pairs` maps to block indices.  FIRST also rotates
+// the pairs inside each block of two rows; it is a separate instance so the
+// other rounds carry no conditional stage.
+template <int BS, int LPP, int NCH, int TL, bool WARM, bool FIRST, class Pairs>
+__device__ inline void jacobi_round_of(float* B, float* Rm, float* nrm, int ld, const Pairs& pairs, int Pb, int g,
+                                       int q, float tol, int& any, long long& rots) {
+    constexpr int G = NT / LPP;
+    // WARM: the rotation rows of the block pair (same layout as the Jacobi
+    // rows) stay in registers for the round and take the same rotations.
+    constexpr int RN = WARM ? NCH : 1;
+    constexpr int RT = WARM ? TL : 0;
+    using Row = RowPart<NCH, TL>;
+    using RRow = RowPart<RN, RT>;
+    for (int k = g; k < Pb; k += G) {
+        int I, J;
+        pairs(k, I, J);
         float* pa = B + (BS * I) * ld;
         float* pb = B + (BS * J) * ld;
         if (BS == 1) {
@@ -516,6 +525,14 @@ __device__ inline void jacobi_round(float* B, float* Rm, float* nrm, int ld, int
     }
 }
 
+// Round r of the circle ordering over the Nb + 1 blocks of B; FIRST in
+// round 0 of a sweep.
+template <int BS, int LPP, int NCH, int TL, bool WARM, bool FIRST>
+__device__ inline void jacobi_round(float* B, float* Rm, float* nrm, int ld, int r, int Nb, int Pb, int g, int q,
+                                    float tol, int& any, long long& rots) {
+    jacobi_round_of<BS, LPP, NCH, TL, WARM, FIRST>(B, Rm, nrm, ld, CirclePairs{r, Nb}, Pb, g, q, tol, any, rots);
+}
+
 // Returns 1 (uniform over the workgroup) if any pair was rotated.  WARM:
 // every rotation is also applied to the rows of Rm (same layout), which
 // accumulates the product of the rotations.
@@ -557,6 +574,62 @@ __device__ void jacobi_svd_rows(float* B, float* Rm, int nc, int ld, float tol, 
     row_norms<LPP, NCH, TL>(B, nc, ld, s2);
 }
 
+// Staged super-block pair of the tiled Jacobi: rows 0..sb-1 of B are
+// super-block I, rows sb..2sb-1 super-block J, h = sb / BS blocks each (h
+// even).  The pairs inside the two super-blocks (when `inner`: the circle
+// ordering run in both at once, h - 1 rounds of h block pairs) and then
+// every cross pair (h rounds; round s joins block a of I with block
+// (a + s) mod h of J).
+struct InnerPairs {
+    int r, Nb, Pb, h;  // circle round r over the h = Nb + 1 blocks of each super-block, Pb = h / 2
+    __device__ inline void operator()(int k, int& I, int& J) const {
+        const int half = k >= Pb ? 1 : 0;
+        CirclePairs{r, Nb}(k - half * Pb, I, J);
+        I += half * h;
+        J += half * h;
+    }
+};
+
+struct CrossPairs {
+    int s, h;
+    __device__ inline void operator()(int k, int& I, int& J) const {
+        I = k;
+        J = k + s;
+        if (J >= h) J -= h;
+        J += h;
+    }
+};
+
+template <int BS, int LPP, int NCH, int TL, bool WARM>
+__device__ int jacobi_pair_rows(float* B, float* Rm, int sb, int ld, float tol, bool inner, JacobiStats& js) {
+    float* nrm = tilt_jacobi_nrm;
+    const int tid = threadIdx.x;
+    const int g = tid / LPP, q = tid % LPP;
+    const int h = sb / BS;
+    long long rots = 0;
+    int any = 0;
+    row_norms<LPP, NCH, TL>(B, 2 * sb, ld, nrm);
+    if (inner) {
+        const int Nb = h - 1, Pb = h >> 1;
+        jacobi_round_of<BS, LPP, NCH, TL, WARM, true>(B, Rm, nrm, ld, InnerPairs{0, Nb, Pb, h}, h, g, q, tol, any,
+                                                      rots);
+        __syncthreads();
+        for (int r = 1; r < Nb; ++r) {
+            jacobi_round_of<BS, LPP, NCH, TL, WARM, false>(B, Rm, nrm, ld, InnerPairs{r, Nb, Pb, h}, h, g, q, tol,
+                                                           any, rots);
+            __syncthreads();
+        }
+    }
+    for (int s = 0; s < h; ++s) {
+        jacobi_round_of<BS, LPP, NCH, TL, WARM, false>(B, Rm, nrm, ld, CrossPairs{s, h}, h, g, q, tol, any, rots);
+        __syncthreads();
+    }
+    const int a = __syncthreads_or(any);
+    js.pairs += (long long)sb * sb + (inner ? (long long)sb * (sb - 1) : 0);
+    js.rotations += block_sum_ll(q == 0 ? rots : 0);
+    return a;
+}
+
 // Layout codes from svt_make_cfg(BS, LPP, NCH, TL).
 #define TILT_SVT_CASE_T(S, L, C, T)                                                       \
     case svt_make_cfg(S, L, C, T):                                                        \
@@ -574,7 +647,10 @@ __device__ void jacobi_svd_rows(float* B, float* Rm, int nc, int ld, float tol, 
     TILT_SVT_CASE_T(S, L, 1, 1) TILT_SVT_CASE_T(S, L, 2, 1) TILT_SVT_CASE_T(S, L, 3, 1)           \
     TILT_SVT_CASE_T(S, L, 1, 2) TILT_SVT_CASE_T(S, L, 2, 2) TILT_SVT_CASE_T(S, L, 3, 2)
 
-__device__ __forceinline__ void jacobi_dispatch(int cfg, float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js,
+// Kept out of line (as is the warm variant): inlined into dev_svt, its
+// switch made the 256 x 100x100 batch 30 % slower, with the same code for
+// the Jacobi itself.
+__device__ void jacobi_dispatch(int cfg, float* B, int nc, int ld, float tol, int max_sweeps, JacobiStats& js,
                                 float* s2) {
     switch (cfg) {
         TILT_SVT_CASES8(1, 4) TILT_SVT_CASES8(1, 8) TILT_SVT_CASES8(1, 16)
@@ -602,7 +678,7 @@ __device__ __forceinline__ void jacobi_dispatch(int cfg, float* B, int nc, int l
     TILT_WARM_CASE_T(S, L, 1, 1) TILT_WARM_CASE_T(S, L, 2, 1) TILT_WARM_CASE_T(S, L, 3, 1)          \
     TILT_WARM_CASE_T(S, L, 1, 2) TILT_WARM_CASE_T(S, L, 2, 2) TILT_WARM_CASE_T(S, L, 3, 2)
 
-__device__ __forceinline__ void jacobi_dispatch_warm(int cfg, float* B, float* Rm, int nc, int ld, float tol, int max_sweeps,
+__device__ void jacobi_dispatch_warm(int cfg, float* B, float* Rm, int nc, int ld, float tol, int max_sweeps,
                                      JacobiStats& js, float* s2) {
     switch (cfg) {
         TILT_WARM_CASES4(1, 4) TILT_WARM_CASES4(1, 8) TILT_WARM_CASES4(1, 16)
@@ -622,53 +698,52 @@ __device__ __forceinline__ void jacobi_dispatch_warm(int cfg, float* B, float* R
 #undef TILT_SVT_CASE
 #undef TILT_SVT_CASE_T
 
-// One sweep over all pairs of the nrows rows of B (LDS); 1 if any rotated.
-// The tiled paths use layouts without single floats.
-#define TILT_SWEEP_CASE(S, L, C)                                                          \
-    case svt_make_cfg(S, L, C):                  \
-        return jacobi_rows<S, L, C, 0, false>(B, nullptr, nrows, ld, tol, 1, js);
-#define TILT_SWEEP_CASES8(S, L)                                                                    \
-    TILT_SWEEP_CASE(S, L, 1) TILT_SWEEP_CASE(S, L, 2) TILT_SWEEP_CASE(S, L, 3) TILT_SWEEP_CASE(S, L, 4) \
-    TILT_SWEEP_CASE(S, L, 5) TILT_SWEEP_CASE(S, L, 6) TILT_SWEEP_CASE(S, L, 7) TILT_SWEEP_CASE(S, L, 8)
-#define TILT_SWEEP_CASES4(S, L) \
-    TILT_SWEEP_CASE(S, L, 1) TILT_SWEEP_CASE(S, L, 2) TILT_SWEEP_CASE(S, L, 3) TILT_SWEEP_CASE(S, L, 4)
+// The rounds of one staged super-block pair (jacobi_pair_rows) for the
+// layout code cfg, with the rotation rows Rm (same layout as B; chunks per
+// lane up to 4) in the _warm variant; 1 if any pair rotated.  The tiled
+// paths use layouts without single floats.
+#define TILT_PAIR_CASE(S, L, C) \
+    case svt_make_cfg(S, L, C): \
+        return jacobi_pair_rows<S, L, C, 0, false>(B, nullptr, sb, ld, tol, inner, js);
+#define TILT_PAIR_CASES8(S, L)                                                                  \
+    TILT_PAIR_CASE(S, L, 1) TILT_PAIR_CASE(S, L, 2) TILT_PAIR_CASE(S, L, 3) TILT_PAIR_CASE(S, L, 4) \
+    TILT_PAIR_CASE(S, L, 5) TILT_PAIR_CASE(S, L, 6) TILT_PAIR_CASE(S, L, 7) TILT_PAIR_CASE(S, L, 8)
+#define TILT_PAIR_CASES4(S, L) \
+    TILT_PAIR_CASE(S, L, 1) TILT_PAIR_CASE(S, L, 2) TILT_PAIR_CASE(S, L, 3) TILT_PAIR_CASE(S, L, 4)
+#define TILT_WPAIR_CASE(S, L, C) \
+    case svt_make_cfg(S, L, C):  \
+        return jacobi_pair_rows<S, L, C, 0, true>(B, Rm, sb, ld, tol, inner, js);
+#define TILT_WPAIR_CASES4(S, L) \
+    TILT_WPAIR_CASE(S, L, 1) TILT_WPAIR_CASE(S, L, 2) TILT_WPAIR_CASE(S, L, 3) TILT_WPAIR_CASE(S, L, 4)
 
-__device__ int jacobi_sweep_dispatch(int cfg, float* B, int nrows, int ld, float tol, JacobiStats& js) {
+__device__ int jacobi_pair_dispatch(int cfg, float* B, int sb, int ld, float tol, bool inner, JacobiStats& js) {
     switch (cfg) {
-        TILT_SWEEP_CASES8(1, 4) TILT_SWEEP_CASES8(1, 8) TILT_SWEEP_CASES8(1, 16)
-        TILT_SWEEP_CASES4(2, 4) TILT_SWEEP_CASES4(2, 8) TILT_SWEEP_CASES4(2, 16)
-        TILT_SWEEP_CASE(1, 32, 5) TILT_SWEEP_CASE(1, 32, 6) TILT_SWEEP_CASE(1, 32, 7) TILT_SWEEP_CASE(1, 32, 8)
-        TILT_SWEEP_CASE(1, 64, 3) TILT_SWEEP_CASE(1, 64, 4) TILT_SWEEP_CASE(1, 64, 5) TILT_SWEEP_CASE(1, 64, 6)
-        TILT_SWEEP_CASE(1, 64, 7) TILT_SWEEP_CASE(1, 64, 8) TILT_SWEEP_CASE(2, 64, 3) TILT_SWEEP_CASE(2, 64, 4)
+        TILT_PAIR_CASES8(1, 4) TILT_PAIR_CASES8(1, 8) TILT_PAIR_CASES8(1, 16)
+        TILT_PAIR_CASES4(2, 4) TILT_PAIR_CASES4(2, 8) TILT_PAIR_CASES4(2, 16)
+        TILT_PAIR_CASE(1, 32, 5) TILT_PAIR_CASE(1, 32, 6) TILT_PAIR_CASE(1, 32, 7) TILT_PAIR_CASE(1, 32, 8)
+        TILT_PAIR_CASE(1, 64, 3) TILT_PAIR_CASE(1, 64, 4) TILT_PAIR_CASE(1, 64, 5) TILT_PAIR_CASE(1, 64, 6)
+        TILT_PAIR_CASE(1, 64, 7) TILT_PAIR_CASE(1, 64, 8) TILT_PAIR_CASE(2, 64, 3) TILT_PAIR_CASE(2, 64, 4)
         default:
             break;
     }
     return 0;
 }
-#undef TILT_SWEEP_CASES4
-#undef TILT_SWEEP_CASES8
-#undef TILT_SWEEP_CASE
 
-// One sweep of the warm-started tiled Jacobi: the rotations are applied to
-// the rotation rows Rm as well (same layout as B; chunks per lane up to 4).
-#define TILT_WSWEEP_CASE(S, L, C) \
-    case svt_make_cfg(S, L, C):   \
-        return jacobi_rows<S, L, C, 0, true>(B, Rm, nrows, ld, tol, 1, js);
-#define TILT_WSWEEP_CASES4(S, L) \
-    TILT_WSWEEP_CASE(S, L, 1) TILT_WSWEEP_CASE(S, L, 2) TILT_WSWEEP_CASE(S, L, 3) TILT_WSWEEP_CASE(S, L, 4)
-
-__device__ int jacobi_sweep_dispatch_warm(int cfg, float* B, float* Rm, int nrows, int ld, float tol,
-                                          JacobiStats& js) {
+__device__ int jacobi_pair_dispatch_warm(int cfg, float* B, float* Rm, int sb, int ld, float tol, bool inner,
+                                         JacobiStats& js) {
     switch (cfg) {
-        TILT_WSWEEP_CASES4(1, 4) TILT_WSWEEP_CASES4(1, 8) TILT_WSWEEP_CASES4(1, 16)
-        TILT_WSWEEP_CASES4(2, 4) TILT_WSWEEP_CASES4(2, 8) TILT_WSWEEP_CASES4(2, 16)
+        TILT_WPAIR_CASES4(1, 4) TILT_WPAIR_CASES4(1, 8) TILT_WPAIR_CASES4(1, 16)
+        TILT_WPAIR_CASES4(2, 4) TILT_WPAIR_CASES4(2, 8) TILT_WPAIR_CASES4(2, 16)
         default:
             break;
     }
     return 0;
 }
-#undef TILT_WSWEEP_CASES4
-#undef TILT_WSWEEP_CASE
+#undef TILT_WPAIR_CASES4
+#undef TILT_WPAIR_CASE
+#undef TILT_PAIR_CASES4
+#undef TILT_PAIR_CASES8
+#undef TILT_PAIR_CASE
 
 // ---------------------------------------------------------------------------
 // Tiled one-sided Jacobi for matrices that do not fit in LDS.
@@ -676,12 +751,14 @@ __device__ int jacobi_sweep_dispatch_warm(int cfg, float* B, float* Rm, int nrow
 // The ncp rows (nc real rows, then zero rows) live in a device plane with
 // stride ldg and are split into nsb super-blocks of sb rows.  A sweep runs
 // the circle method over super-blocks; for each super-block pair both
-// blocks are staged into LDS as one 2 sb-row matrix, one full Jacobi sweep
-// over its rows is applied (cross pairs and the pairs inside each block),
-// and the blocks are written back if anything rotated.  Every pair of rows
-// is examined at least once per sweep; a sweep in which no pair rotates
-// leaves every row unchanged, so all pairs were tested against the final
-// rows, and the iteration stops.  Zero rows are never rotated (a.b = 0).
+// blocks are staged into LDS as one 2 sb-row matrix, every cross pair (one
+// row from each block) is examined, and the blocks are written back if
+// anything rotated.  In the first round of a sweep, where every super-block
+// takes part once, the pairs inside both blocks are examined first.  So
+// every pair of rows is examined exactly once per sweep; a sweep in which
+// no pair rotates leaves every row unchanged, so all pairs were tested
+// against the final rows, and the iteration stops.  Zero rows are never
+// rotated (a.b = 0).
 // ---------------------------------------------------------------------------
 
 __device__ void clear_lds_padding(float* B, int nc, int ldg, int ld);
@@ -706,24 +783,13 @@ __device__ void store_block(float* Bg, int r0, int cnt, int ldg, const float* mi
 
 // Pair k of round r of the circle ordering over nsb super-blocks: the
 // super-blocks I and J it joins.
-__device__ inline void superblock_pair(int nsb, int r, int k, int& I, int& J) {
-    const int Nb = nsb - 1;
-    if (k == 0) {
-        I = Nb;
-        J = r;
-    } else {
-        I = r + k;
-        if (I >= Nb) I -= Nb;
-        J = r - k;
-        if (J < 0) J += Nb;
-    }
-}
+__device__ inline void superblock_pair(int nsb, int r, int k, int& I, int& J) { CirclePairs{r, nsb - 1}(k, I, J); }
 
-// One super-block pair: stage both blocks into LDS, one full Jacobi sweep
-// over their 2 sb rows, write them back if anything rotated.  With Rg (the
-// warm start) the matching rows of the rotation are staged after them and
-// take the same rotations.  Returns 1 if a pair rotated (uniform over the
-// workgroup).
+// One super-block pair: stage both blocks into LDS, examine their pairs
+// (the cross pairs, and in round 0 the pairs inside each block first),
+// write them back if anything rotated.  With Rg (the warm start) the
+// matching rows of the rotation are staged after them and take the same
+// rotations.  Returns 1 if a pair rotated (uniform over the workgroup).
 __device__ int superblock_task(int cfg, float* Bg, float* Rg, int sb, int nsb, int ldg, int ld, float* mini,
                                float tol, int r, int k, JacobiStats& js) {
     int I, J;
@@ -738,8 +804,8 @@ __device__ int superblock_task(int cfg, float* Bg, float* Rg, int sb, int nsb, i
         clear_lds_padding(rmini, 2 * sb, ldg, ld);
     }
     __syncthreads();
-    const int rot = Rg ? jacobi_sweep_dispatch_warm(cfg, mini, rmini, 2 * sb, ld, tol, js)
-                       : jacobi_sweep_dispatch(cfg, mini, 2 * sb, ld, tol, js);
+    const int rot = Rg ? jacobi_pair_dispatch_warm(cfg, mini, rmini, sb, ld, tol, r == 0, js)
+                       : jacobi_pair_dispatch(cfg, mini, sb, ld, tol, r == 0, js);
     if (rot) {
         store_block(Bg, I * sb, sb, ldg, mini, 0, ld);
         store_block(Bg, J * sb, sb, ldg, mini, sb, ld);
@@ -2783,24 +2849,16 @@ __global__ void __launch_bounds__(NT) k_wide_round(const PatchDesc* descs, Patch
     // inner-loop SVTs (eps2 > 0) follow mu as in dev_svt; the decomposition
     // of I for mu_0 uses tol_max
     const float tol = eps2 > 0.0 ? svt_tolerance(tol_max, eps2, st->mu) : tol_max;
-    const int Nb = d.nsb - 1, sb = d.sb;
+    const int sb = d.sb;
     int I, J;
-    if (k == 0) {
-        I = Nb;
-        J = r;
-    } else {
-        I = r + k;
-        if (I >= Nb) I -= Nb;
-        J = r - k;
-        if (J < 0) J += Nb;
-    }
+    superblock_pair(d.nsb, r, k, I, J);
     float* Bg = d.ws + NPLANES * (size_t)d.nc * d.ldg;
     load_block(Bg, I * sb, sb, d.ldg, mini, 0, d.ld);
     load_block(Bg, J * sb, sb, d.ldg, mini, sb, d.ld);
     clear_lds_padding(mini, 2 * sb, d.ldg, d.ld);
     __syncthreads();
     JacobiStats js{0, 0, 0};
-    const int rot = jacobi_sweep_dispatch(d.svt_cfg, mini, 2 * sb, d.ld, tol, js);
+    const int rot = jacobi_pair_dispatch(d.svt_cfg, mini, sb, d.ld, tol, r == 0, js);
     if (rot) {
         store_block(Bg, I * sb, sb, d.ldg, mini, 0, d.ld);
         store_block(Bg, J * sb, sb, d.ldg, mini, sb, d.ld);
