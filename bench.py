@@ -270,6 +270,10 @@ def main():
                          "every inner loop to max_inner, so its single launch is long")
     ap.add_argument("--inner", action="store_true",
                     help="inner-loop-only mode (random I and J, the setting of Table 1)")
+    ap.add_argument("--svdws", action="store_true",
+                    help="SVD with warm start (svt_mode 4) against the warm-started Jacobi (svt_mode 1) on the "
+                         "inner loop alone: time, iterations, Cayley steps, objective")
+    ap.add_argument("--eps-svd", type=float, default=1e-3, help="switch threshold of --svdws")
     ap.add_argument("--rasl", action="store_true",
                     help="RASL variant: a batch of image sets (one window per image as the columns of the data "
                          "matrix), one fused launch; sets/s, images/s, latency, roofline, CPU oracle on a sample")
@@ -297,6 +301,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.serve:
         return serve_main(args)
+    if args.svdws:
+        return svdws_main(args)
     if args.inner:
         return inner_main(args)
     if args.rasl:
@@ -857,6 +863,88 @@ def inner_main(args):
         "config": {"workload": "inner-loop-only-table1", "value_at": "256 problems of 100x100",
                    "svt": "cold" if args.svt_mode == 0 else "warm", "eps1": prm.eps1, "eps2": prm.eps2},
         "sizes": rows,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def svdws_main(args):
+    """Alg. 2 (SVD with warm start, svt_mode 4) against the warm-started
+    Jacobi (svt_mode 1) on the inner loop alone (random I ~ U(0,1), J ~
+    N(0,1), p = 5, batches of 256): kernel time, iterations, the share of
+    SVTs done by a Cayley step and the objective against svt_mode 1, for the
+    eps_svd switch and for the fixed schedule svdws_every = 2; the FP64
+    oracle runs problem 0 of each size with the exact SVT and with Alg. 2."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    import paper_1205_5351_amd as T
+    import tilt_synth as ts
+
+    dev = torch.device("cuda:0")
+    ctx = T.Context(0)
+    p, count = 5, 256
+    modes = [("warm Jacobi (svt_mode 1)", dict(svt_mode=1)),
+             (f"SVDWS, eps_svd {args.eps_svd:g}", dict(svt_mode=4, eps_svd=args.eps_svd)),
+             ("SVDWS, every 2nd SVT", dict(svt_mode=4, svdws_every=2))]
+    rows = []
+    for size in (10, 50, 100):
+        Is, Js = zip(*[ts.inner_problem(k, size, size, p) for k in range(count)])
+        dI = torch.from_numpy(np.stack(Is)).to(dev)
+        dJ = torch.from_numpy(np.stack(Js)).to(dev)
+        base_obj = None
+        for name, kw in modes:
+            prm = T.default_params(**kw)
+            ctx.inner_batch(dI.data_ptr(), dJ.data_ptr(), 8, size, size, p, prm)  # warm-up
+            torch.cuda.synchronize()
+            rc, res = ctx.inner_batch(dI.data_ptr(), dJ.data_ptr(), count, size, size, p, prm)
+            kms = ctx.last_kernel_ms()
+            iters = np.array([r["inner_iters_total"] for r in res])
+            objs = np.array([r["objective"] for r in res])
+            steps = np.array([r["counters"]["svdws_steps"] for r in res])
+            svts = np.array([r["counters"]["svt_calls"] for r in res])
+            if base_obj is None:
+                base_obj = objs
+            rel = np.abs(objs - base_obj) / base_obj
+            row = {"size": size, "svt": name, "kernel_ms": round(kms, 2),
+                   "solves_per_s": round(count / (kms * 1e-3), 1), "iters_mean": round(float(iters.mean()), 1),
+                   "iters_max": int(iters.max()), "cayley_share": round(float(steps.sum() / max(svts.sum(), 1)), 3),
+                   "obj_vs_mode1_mean": float(rel.mean()), "obj_vs_mode1_max": float(rel.max()),
+                   "status_maxiter": int(sum(1 for r in res if r["status"] == 1))}
+            rows.append(row)
+            log(f"svdws {size}x{size}: {row}")
+        # the oracle on problem 0: exact SVT and Alg. 2 with the same switch
+        lam = 1.0 / math.sqrt(size)
+        Jm = np.asarray(Js[0], np.float64).reshape(p, size * size).T
+        I64 = np.asarray(Is[0], np.float64)
+        Z = np.zeros_like(I64)
+        opr = O.Params()
+        ex = O.ladmap_inner(I64, O.Annihilator(Jm), lam, I64, Z, Z, opr)
+        op = O.svdws.SvdwsSvt(eps_svd=args.eps_svd)
+        ws = O.ladmap_inner(I64, O.Annihilator(Jm), lam, I64, Z, Z, opr, svt_op=op)
+        oe, ow = O.objective(ex.A, ex.E, lam), O.objective(ws.A, ws.E, lam)
+        rows.append({"size": size, "svt": "oracle (FP64), problem 0", "iters_exact": ex.iters,
+                     "iters_svdws": ws.iters, "cayley_steps": op.steps, "obj_rel_diff": abs(ow - oe) / oe})
+        log(f"svdws {size}x{size} oracle: {rows[-1]}")
+    head = next(r for r in rows if r["size"] == 100 and r["svt"].startswith("SVDWS, eps"))
+    out = {
+        "metric": "LADMAP inner loop alone with the SVD with warm start: solves/s",
+        "value": head["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": head["kernel_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (I ~ U(0,1), J ~ N(0,1), p = 5)",
+        "config": {"workload": "inner-loop-svdws", "value_at": "256 problems of 100x100", "eps_svd": args.eps_svd},
+        "rows": rows,
         "roofline": None,
         "cpu_baseline": None,
     }

@@ -86,7 +86,14 @@ typedef struct {
                            recomputed in FP32 with the accumulated rotation
                            and the Jacobi continues (FP32 accuracy).
                            3: bfloat16 start without refinement (precision
-                           study; errors of order 1e-3).                      */
+                           study; errors of order 1e-3).
+                           4: SVD with warm start (Sec. 5, Alg. 2): where
+                           mode 1 runs, an SVT may instead take one Cayley
+                           step from the previous decomposition (see
+                           eps_svd, svdws_every) and shrink its result; the
+                           other SVTs are mode 1's, whose decomposition the
+                           next step starts from.  An approximation: the
+                           shrinkage is not exact after a step.           */
     float jacobi_tol;   /* rotate a pair when |a.b| > tol ||a|| ||b||, with
                            tol = min(jacobi_tol, max(1e-7, eps2 / (10 mu)))
                            in the inner loop (the SVT's rounding enters Cond2
@@ -110,6 +117,17 @@ typedef struct {
                            f = ||A||_* + lambda ||E||_1.  0 (default): off,
                            only ||Delta tau|| < eps_outer and max_outer stop.
                            Not applied by the RASL entry point.              */
+    double eps_svd;     /* svt_mode 4: take the Cayley step when
+                           ||M_k - M_prev||_F < eps_svd ||M_k||_F (M_prev:
+                           the matrix of the previous SVT; the norm and the
+                           relative scale are readings), default 1e-3      */
+    int svdws_every;    /* svt_mode 4: 0 (default) uses the eps_svd rule;
+                           K > 0 replaces it by a fixed schedule: a full SVD
+                           in inner iterations 0, K, 2K, ... of each inner
+                           loop, the Cayley step in the others (a step with
+                           f''(0) <= 0 or a singular system falls back to
+                           the full SVD in either rule)                     */
+    int reserved_params;
 } tilt_params;
 
 /* One window of one image.  The window is given by an initial transform
@@ -137,6 +155,7 @@ typedef struct {
     long long jacobi_pairs;     /* column pairs examined                      */
     long long jacobi_rotations; /* column pairs rotated                       */
     long long recon_rows;       /* sum over SVDs of singular values kept      */
+    long long svdws_steps;      /* svt_mode 4: SVTs done by a Cayley step     */
 } tilt_counters;
 
 typedef struct {

@@ -119,3 +119,39 @@ def shrink(dec: WarmSVD, eps: float):
     """U T_eps(Sigma) V^T with the signed soft threshold."""
     T = np.sign(dec.S) * np.maximum(np.abs(dec.S) - eps, 0.0)
     return (dec.U * T) @ dec.V.T
+
+
+class SvdwsSvt:
+    """Alg. 2 as the SVT of the LADMAP inner loop (``ladmap_inner``'s
+    ``svt_op``): the decomposition of the previous call is kept, and each
+    call either takes the Cayley step from it or computes a full SVD, then
+    shrinks the result with the signed soft threshold.  The switch is
+    Alg. 2's, ||M - M_prev||_F < eps_svd ||M||_F, or, with every > 0, a
+    fixed schedule: a full SVD at iterations 0, every, 2 every, ... and the
+    step at the others.  A step with f''(0) <= 0 falls back to the full SVD.
+    ``steps`` counts the calls done by a step."""
+
+    def __init__(self, eps_svd: float = 1e-3, every: int = 0):
+        self.eps_svd = eps_svd
+        self.every = every
+        self.prev: Optional[WarmSVD] = None
+        self.steps = 0
+
+    def __call__(self, M, eps, k):
+        use = self.prev is not None and (
+            (k % self.every != 0) if self.every > 0
+            else np.linalg.norm(M - self.prev.M) < self.eps_svd * np.linalg.norm(M))
+        dec = None
+        if use:
+            U, S, V = self.prev.U, self.prev.S, self.prev.V
+            PU, PS, PV = projected_gradients(U, S, V, M)
+            f1, f2 = derivatives(U, S, V, M, PU, PS, PV)
+            if f2 > 0.0:
+                Ut, St, Vt = curve(U, S, V, PU, PS, PV, -f1 / f2)
+                dec = WarmSVD(Ut, St, Vt, M.copy())
+                self.steps += 1
+        if dec is None:
+            dec = svd_full(M)
+        self.prev = dec
+        return shrink(dec, eps), np.sort(np.abs(dec.S))[::-1]
+

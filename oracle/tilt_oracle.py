@@ -377,7 +377,8 @@ def spectral_norm(X):
     return float(np.linalg.svd(X, compute_uv=False)[0])
 
 
-def ladmap_inner(I, Jp: Annihilator, lam, A0, E0, Y0, prm: Params, mu0=None, trace=None) -> InnerResult:
+def ladmap_inner(I, Jp: Annihilator, lam, A0, E0, Y0, prm: Params, mu0=None, trace=None,
+                 svt_op=None) -> InnerResult:
     """LADMAP for min ||A||_* + lam ||E||_1 s.t. J_perp(A + E) = J_perp I.
 
     Updates (Sec. 4.2):
@@ -391,6 +392,9 @@ def ladmap_inner(I, Jp: Annihilator, lam, A0, E0, Y0, prm: Params, mu0=None, tra
     ``trace`` (a list, optional) receives one (A_k, E_k, mu_k) tuple per
     iteration and the final (A, E, mu), so tests can check the penalty
     schedule against the iterates; it changes nothing in the iteration.
+    ``svt_op`` (optional) replaces the exact SVT: called as svt_op(M, eps, k)
+    with k the iteration index, it returns (A, singular values), e.g. the
+    SVD with warm start of Sec. 5 (``svdws.SvdwsSvt``).
     """
     A = A0.copy()
     E = E0.copy()
@@ -408,7 +412,7 @@ def ladmap_inner(I, Jp: Annihilator, lam, A0, E0, Y0, prm: Params, mu0=None, tra
         if trace is not None:
             trace.append((A, E, mu))
         M = A - R - Y / mu
-        A1, sv = svt(M, 1.0 / mu)
+        A1, sv = svt(M, 1.0 / mu) if svt_op is None else svt_op(M, 1.0 / mu, k)
         svt_count = int(np.sum(sv > 1.0 / mu))
         N = E - Jp(A1 + E - I) - Y / mu
         E1 = soft_threshold(N, lam / mu)
@@ -511,8 +515,11 @@ def numerical_rank(A, rel=1e-3):
     return int(np.sum(sv > rel * sv[0]))
 
 
-def tilt_solve(image, tau0_px, m, n, model, prm: Optional[Params] = None, lam=None) -> SolveResult:
-    """Alg. 1 (TILT via LADMAP+VWS) on one window, in FP64."""
+def tilt_solve(image, tau0_px, m, n, model, prm: Optional[Params] = None, lam=None,
+               svt_op_factory=None) -> SolveResult:
+    """Alg. 1 (TILT via LADMAP+VWS) on one window, in FP64.
+    ``svt_op_factory`` (optional): called once per outer iteration, it gives
+    the ``svt_op`` of that iteration's inner loop (see ``ladmap_inner``)."""
     prm = prm or Params()
     if model not in (AFFINE, PROJECTIVE):
         raise ValueError("model must be 6 (affine) or 8 (projective)")
@@ -541,7 +548,8 @@ def tilt_solve(image, tau0_px, m, n, model, prm: Optional[Params] = None, lam=No
         NQ = null_basis(Q)
         Jt = J @ NQ
         Jp = Annihilator(Jt)
-        res = ladmap_inner(I, Jp, lam, A, E, Y, prm)          # Step 2
+        res = ladmap_inner(I, Jp, lam, A, E, Y, prm,          # Step 2
+                           svt_op=svt_op_factory() if svt_op_factory else None)
         A, E, Y = res.A, res.E, res.Y
         svt_count = res.svt_count
         inner_counts.append(res.iters)

@@ -360,7 +360,8 @@ int validate_params(const tilt_params* p) {
     if (!(p->rho0 >= 1.0) || !(p->mu_max > 0)) return TILT_ERR_ARG;
     if (p->max_inner < 1 || p->max_outer < 1 || p->max_sweeps < 1) return TILT_ERR_ARG;
     if (!(p->jacobi_tol > 0.f) || !(p->jacobi_tol < 1.f)) return TILT_ERR_ARG;
-    if (p->svt_mode < 0 || p->svt_mode > 3) return TILT_ERR_ARG;
+    if (p->svt_mode < 0 || p->svt_mode > 4) return TILT_ERR_ARG;
+    if (!(p->eps_svd >= 0) || !std::isfinite(p->eps_svd) || p->svdws_every < 0) return TILT_ERR_ARG;
     if (p->pyramid_levels < 0 || p->pyramid_levels > MAX_LEVELS) return TILT_ERR_ARG;
     if (p->graph_inner < 0 || p->graph_inner > 256) return TILT_ERR_ARG;
     if (!std::isfinite(p->lambda) || !std::isfinite(p->mu0)) return TILT_ERR_ARG;
@@ -400,6 +401,8 @@ SolverParams to_solver(const tilt_params* p) {
     s.max_sweeps = p->max_sweeps;
     s.jacobi_tol = p->jacobi_tol;
     s.ns_every = 4;
+    s.eps_svd = p->eps_svd;
+    s.svdws_every = p->svdws_every;
     return s;
 }
 
@@ -424,6 +427,15 @@ bool warm_level(const tilt_params* prm, const ShapeCfg& sc) {
     return prm->svt_mode >= 1 && sc.warm_lds > 0 && (sc.sb == 0 || prm->svt_mode == 1);
 }
 
+// Workspace floats of one window: the solver planes (and the tiled working
+// planes), plus the region of the SVD with warm start (svt_mode 4 on a
+// window whose SVT is warm-started in LDS).
+size_t level_ws_floats(const tilt_params* prm, const ShapeCfg& sc) {
+    if (prm->svt_mode == 4 && warm_level(prm, sc) && sc.sb == 0)
+        return (size_t)NPLANES * sc.nc * sc.ldg + svdws_region_words(sc.nr, sc.nc);
+    return sc.ws_floats;
+}
+
 // Level l of a request: window ceil(m/2^l) x ceil(n/2^l) in an image of
 // ceil(H/2^l) x ceil(W/2^l) pixels.  The workspace holds the solver planes
 // (sized for the largest level) followed by the images of levels 1.. .
@@ -446,7 +458,7 @@ int plan_request(const tilt_problem& pr, const tilt_params* prm, float* A_out, f
         if (ml[l] < 2 || nl[l] < 2 || hl[l] < 2 || wl[l] < 2) return TILT_ERR_ARG;
         st = shape_config(ml[l], nl[l], &sc[l], prm->svt_mode == 1);
         if (st != TILT_OK) return st;
-        planes = std::max(planes, sc[l].ws_floats);
+        planes = std::max(planes, level_ws_floats(prm, sc[l]));
         P.lds = std::max(P.lds, warm_level(prm, sc[l]) ? sc[l].warm_lds : sc[l].lds);
     }
     size_t off = (planes + 63) & ~(size_t)63;
@@ -529,6 +541,7 @@ void fill_result(const PatchDesc& d0, const PatchState& s, tilt_result* r, doubl
     r->counters.jacobi_pairs = s.pairs;
     r->counters.jacobi_rotations = s.rotations;
     r->counters.recon_rows = s.recon_rows;
+    r->counters.svdws_steps = s.svdws_steps;
 }
 
 }  // namespace host
@@ -1065,6 +1078,8 @@ void tilt_default_params(tilt_params* p) {
     p->max_sweeps = 40;
     p->pyramid_levels = 1;
     p->eps_obj = 0.0;
+    p->eps_svd = 1e-3;
+    p->svdws_every = 0;
 }
 
 const char* tilt_status_string(int s) {
@@ -1450,7 +1465,7 @@ int tilt_inner_batch(tilt_ctx* ctx, const float* I, const float* J, int count, i
     WideTiling wt;
     if (sc.sb > 0 && !warm && count * 8 <= ctx->num_cus && wide_tiling(sc.nc, sc.ldg, &wt))
         return inner_wide(ctx, I, J, count, m, n, p, prm, A, E, results, stream, sc, wt);
-    const size_t per = (sc.ws_floats + 63) & ~(size_t)63;
+    const size_t per = (level_ws_floats(prm, sc) + 63) & ~(size_t)63;
     if (per * count * sizeof(float) > ctx->budget) return TILT_ERR_NOMEM;
     if (ctx->ws.reserve(per * count * sizeof(float)) != hipSuccess ||
         ctx->descs.reserve(sizeof(PatchDesc) * count) != hipSuccess ||

@@ -109,6 +109,9 @@ struct PatchState {
     double geo[3];             // cx, cy, s of the level being solved
     int warm_ok;               // PL_V holds a rotation for this level's shape
     int warm_count;            // warm-started SVTs since the rotation was reset
+    int svdws_ok;              // svt_mode 4: the region holds the previous decomposition
+    int pad_svdws;
+    long long svdws_steps;     // svt_mode 4: SVTs taken by a Cayley step
 };
 
 struct SolverParams {
@@ -117,7 +120,23 @@ struct SolverParams {
     int max_inner, max_outer, fixed_iters, max_sweeps;
     float jacobi_tol;
     int ns_every;  // warm SVT: Newton-Schulz re-orthonormalisation of the rotation every ns_every SVTs
+    double eps_svd;   // svt_mode 4: Cayley step when ||M_k - M_prev||_F < eps_svd ||M_k||_F
+    int svdws_every;  // svt_mode 4: > 0 replaces that rule by a fixed one (full SVD when inner % svdws_every == 0)
 };
+
+// SVD with warm start (svt_mode 4): words of the Cayley step's scratch for
+// an m x n matrix (m >= n), and of the per-window region that follows the
+// solver planes: the decomposition (U m x n, V n x n, Sigma n), the previous
+// and the current matrix, the step's outputs and scratch, each rounded up
+// to 64 words.
+__host__ __device__ inline size_t svdws_scratch_words(int m, int n) {
+    return (size_t)8 * m * n + (size_t)12 * n * n + (size_t)2 * n;
+}
+__host__ __device__ inline size_t svdws_round64(size_t w) { return (w + 63) & ~(size_t)63; }
+__host__ __device__ inline size_t svdws_region_words(int m, int n) {
+    const size_t mn = svdws_round64((size_t)m * n), nn = svdws_round64((size_t)n * n), s = svdws_round64(n);
+    return 5 * mn + 2 * nn + 2 * s + svdws_round64(svdws_scratch_words(m, n));
+}
 
 // Jacobi tolerance of an inner-loop SVT.  The SVT's rounding (of the order
 // of the tolerance, relative to ||M|| ~ 1 for the normalised window) enters

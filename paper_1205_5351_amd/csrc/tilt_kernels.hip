@@ -2128,6 +2128,136 @@ __device__ __noinline__ void svt_tiled_warm(const PatchDesc& d, PatchState* st, 
 }
 
 
+// ---------------------------------------------------------------------------
+// SVD with warm start inside the loop (svt_mode 4; Sec. 5, Alg. 2).  The
+// row layout holds X = M (nc x nr); the step works on the m = nr by n = nc
+// matrix X^T, whose SVD after a full decomposition by the warm-started
+// Jacobi is U = the normalised Jacobi rows (transposed), Sigma = their
+// norms and V = the accumulated rotation (transposed), since B = R X with
+// orthogonal rows.
+// ---------------------------------------------------------------------------
+
+#include "tilt_svdws.inc"
+
+// A window's region after its solver planes (layout of svdws_region_words).
+struct SvdwsRegion {
+    float *U, *Mp, *Mn, *Uo, *Ao, *V, *Vo, *S, *So, *W;
+};
+
+__device__ inline SvdwsRegion svdws_region(const PatchDesc& d) {
+    const size_t mn = svdws_round64((size_t)d.nr * d.nc), nn = svdws_round64((size_t)d.nc * d.nc);
+    const size_t sv = svdws_round64(d.nc);
+    float* p = d.ws + NPLANES * (size_t)d.nc * d.ldg;
+    SvdwsRegion r;
+    r.U = p;
+    r.Mp = r.U + mn;
+    r.Mn = r.Mp + mn;
+    r.Uo = r.Mn + mn;
+    r.Ao = r.Uo + mn;
+    r.V = r.Ao + mn;
+    r.Vo = r.V + nn;
+    r.S = r.Vo + nn;
+    r.So = r.S + sv;
+    r.W = r.So + sv;
+    return r;
+}
+
+// Before the Jacobi: X^T into the region, then Alg. 2's choice.  With a
+// previous decomposition, the Cayley step is taken when ||X - X_prev||_F <
+// eps_svd ||X||_F (or, with svdws_every > 0, in every inner iteration not
+// divisible by it); if it succeeds, A (row layout) = U(t) T_eps(Sigma(t))
+// V(t)^T, the decomposition moves on and the state's SVT statistics are
+// set.  Returns 1 (uniform) if A was formed this way, 0 if a full SVD is
+// needed.
+__device__ __noinline__ int svdws_try(const PatchDesc& d, PatchState* st, const SolverParams& prm) {
+    const int m = d.nr, n = d.nc, ldg = d.ldg;
+    const int mn = m * n;
+    const size_t np = (size_t)d.nc * ldg;
+    const float* M = d.ws + PL_M * np;
+    float* A = d.ws + PL_A * np;
+    const SvdwsRegion R = svdws_region(d);
+    const int have = st->svdws_ok;
+    double sums[2] = {0.0, 0.0};
+    for (int e = threadIdx.x; e < mn; e += NT) {
+        const int i = e / n, j = e - i * n;
+        const float v = M[(size_t)j * ldg + i];
+        R.Mn[e] = v;
+        if (have) {
+            const double dv = (double)v - (double)R.Mp[e];
+            sums[0] += dv * dv;
+            sums[1] += (double)v * (double)v;
+        }
+    }
+    block_sum_d<2>(sums);
+    int use = 0;
+    if (have) use = prm.svdws_every > 0 ? (st->inner % prm.svdws_every) != 0 : sqrt(sums[0]) < prm.eps_svd * sqrt(sums[1]);
+    if (!use) return 0;
+    const float eps = (float)(1.0 / st->mu);
+    double t, f0, ft;
+    if (svdws_step(m, n, R.U, R.S, R.V, R.Mn, R.Uo, R.So, R.Vo, R.Ao, eps, R.W, t, f0, ft) != 0) return 0;
+    float dA[1] = {0.f};
+    for (int e = threadIdx.x; e < mn; e += NT) {
+        const int i = e / n, j = e - i * n;
+        const size_t o = (size_t)j * ldg + i;
+        const float v = R.Ao[e];
+        const float diff = v - A[o];
+        dA[0] = fmaf(diff, diff, dA[0]);
+        A[o] = v;
+        R.U[e] = R.Uo[e];
+        R.Mp[e] = R.Mn[e];
+    }
+    for (int e = threadIdx.x; e < n * n; e += NT) R.V[e] = R.Vo[e];
+    for (int j = threadIdx.x; j < n; j += NT) R.S[j] = R.So[j];
+    block_sum_f<1>(dA);
+    if (threadIdx.x == 0) {
+        // A's singular values are |Sigma_j(t)| - eps for the kept ones
+        int k = 0;
+        double nuc = 0.0, top = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double a = fabs((double)R.So[j]) - (double)eps;
+            if (a > 0.0) {
+                k += 1;
+                nuc += a;
+                top = fmax(top, a);
+            }
+        }
+        int nr_rank = 0;
+        for (int j = 0; j < n; ++j) nr_rank += (fabs((double)R.So[j]) - (double)eps) > 1e-3 * top ? 1 : 0;
+        st->num_rank = top > 0.0 ? nr_rank : 0;
+        st->dA2 = (double)dA[0];
+        st->nuc = nuc;
+        st->svt_rank = k;
+        st->svt_calls += 1;
+        st->recon_rows += k;
+        st->svdws_steps += 1;
+    }
+    __syncthreads();
+    return 1;
+}
+
+// After a full SVD by the warm-started Jacobi (rows B and rotation Rl in
+// LDS, squared row norms s2): its decomposition of X^T and X^T itself into
+// the region for the next step.
+__device__ __noinline__ void svdws_save(const PatchDesc& d, PatchState* st, const float* B, const float* Rl,
+                                        const float* s2) {
+    const int m = d.nr, n = d.nc, ld = d.ld;
+    const SvdwsRegion R = svdws_region(d);
+    for (int j = threadIdx.x; j < n; j += NT) R.S[j] = sqrtf(s2[j]);
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * n; e += NT) {
+        const int i = e / n, j = e - i * n;
+        const float sj = R.S[j];
+        R.U[e] = sj > 0.f ? B[j * ld + i] / sj : 0.f;
+        R.Mp[e] = R.Mn[e];
+    }
+    for (int e = threadIdx.x; e < n * n; e += NT) {
+        const int i = e / n, j = e - i * n;
+        R.V[e] = Rl[j * ld + i];
+    }
+    if (threadIdx.x == 0) st->svdws_ok = 1;
+    __syncthreads();
+}
+
 __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& prm, float* lds) {
     const int nc = d.nc, ldg = d.ldg, ld = d.ld;
     const size_t np = (size_t)nc * ldg;
@@ -2144,19 +2274,20 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
     if (warm && tiled) {
         svt_tiled_warm(d, st, prm, L, tol, js);
     } else if (warm) {
+        if (d.warm == 4 && svdws_try(d, st, prm)) return;  // A formed by the Cayley step
         float* V = d.ws + PL_V * np;
         const bool saved = st->warm_ok != 0;
         load_rotation(Rl, ld, nc, V, ldg, saved);
         if (saved && prm.ns_every > 0 && st->warm_count % prm.ns_every == 0)
             newton_schulz_rows(Rl, ld, nc, L.B, d.ws + (PL_Q + 6) * np, ldg);
-        // B = R M (nc4 x ldg; rows of R beyond nc are zero).  warm = 1: FP32
-        // products.  warm = 2, 3: the start is formed from bfloat16 operands
+        // B = R M (nc4 x ldg; rows of R beyond nc are zero).  warm = 1, 4:
+        // FP32 products.  warm = 2, 3: the start is formed from bfloat16 operands
         // (FP32 accumulation); 2 then refines: B = R' M again in FP32 with
         // the accumulated rotation R' and the Jacobi continues from there,
         // so the result has FP32 accuracy; 3 keeps the bfloat16 start
         // (precision study).
         const int nc4 = (nc + 3) & ~3;
-        if (d.warm == 1)
+        if (d.warm == 1 || d.warm == 4)
             mfma_gemm<false>(Rl, ld, nc4, M, ldg, ldg, nc, L.B, ld);
         else
             mfma_gemm_bf16(Rl, ld, nc4, M, ldg, ldg, nc, L.B, ld);
@@ -2169,6 +2300,7 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
             __syncthreads();
             jacobi_dispatch_warm(d.svt_cfg, L.B, Rl, nc, ld, tol, prm.max_sweeps, js, L.s2);
         }
+        if (d.warm == 4) svdws_save(d, st, L.B, Rl, L.s2);
         save_rotation(Rl, ld, nc, V, ldg);
         if (threadIdx.x == 0) {
             st->warm_ok = 1;
@@ -2530,6 +2662,7 @@ __device__ void level_transition(const PatchDesc& d, PatchState* st) {
         st->done_outer = 0;
         st->warm_ok = 0;
         st->warm_count = 0;
+        st->svdws_ok = 0;
     }
     __syncthreads();
 }

@@ -77,6 +77,9 @@ class Params(C.Structure):
         ("pyramid_levels", C.c_int),
         ("graph_inner", C.c_int),
         ("eps_obj", C.c_double),
+        ("eps_svd", C.c_double),
+        ("svdws_every", C.c_int),
+        ("reserved_params", C.c_int),
     ]
 
 
@@ -103,6 +106,7 @@ class Counters(C.Structure):
         ("jacobi_pairs", C.c_longlong),
         ("jacobi_rotations", C.c_longlong),
         ("recon_rows", C.c_longlong),
+        ("svdws_steps", C.c_longlong),
     ]
 
 
@@ -378,7 +382,7 @@ def result_dict(r: Result) -> dict:
         done_ms=r.done_ms,
         counters=dict(inner_iters=c.inner_iters, svt_calls=c.svt_calls, jacobi_sweeps=c.jacobi_sweeps,
                       jacobi_pairs=c.jacobi_pairs, jacobi_rotations=c.jacobi_rotations,
-                      recon_rows=c.recon_rows),
+                      recon_rows=c.recon_rows, svdws_steps=c.svdws_steps),
     )
 
 

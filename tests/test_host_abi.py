@@ -39,6 +39,7 @@ def test_default_params(tilt):
     assert p.eps1 == 1e-5 and p.eps2 == 1e-3 and p.rho0 == 1.5 and p.mu_max == 1e10
     assert p.max_inner == 2000 and p.max_outer == 50 and p.lambda_ < 0 and p.mu0 < 0
     assert abs(p.jacobi_tol - 1e-6) < 1e-12 and p.max_sweeps == 40 and p.pyramid_levels == 1 and p.graph_inner == 0
+    assert p.eps_obj == 0.0 and p.eps_svd == 1e-3 and p.svdws_every == 0
 
 
 def test_status_strings(tilt):
@@ -132,7 +133,8 @@ def test_struct_layouts_match_the_header(tilt, tmp_path):
               "tilt_result": ["tau", "A", "E", "outer_iters", "svt_rank", "status", "rank", "objective", "mu",
                               "solve_ms", "done_ms", "counters"],
               "tilt_params": ["lambda", "eps1", "max_inner", "svt_mode", "jacobi_tol", "max_sweeps",
-                              "pyramid_levels", "graph_inner"]}
+                              "pyramid_levels", "graph_inner", "eps_obj", "eps_svd", "svdws_every"],
+              "tilt_counters": ["inner_iters", "recon_rows", "svdws_steps"]}
     src = ["#include <stdio.h>", "#include <stddef.h>", '#include "tilt.h"', "int main(void) {"]
     for st, fs in fields.items():
         src.append(f'  printf("{st} %zu\\n", sizeof({st}));')
@@ -146,7 +148,7 @@ def test_struct_layouts_match_the_header(tilt, tmp_path):
     got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
                                                           check=True).stdout.splitlines())
     T = tilt.tilt
-    py = {"tilt_problem": T.Problem, "tilt_result": T.Result, "tilt_params": T.Params}
+    py = {"tilt_problem": T.Problem, "tilt_result": T.Result, "tilt_params": T.Params, "tilt_counters": T.Counters}
     for st, cls in py.items():
         assert int(got[st]) == C_sizeof(cls), st
         for f in fields[st]:

@@ -74,6 +74,14 @@ def test_switches_to_full_svd_beyond_threshold():
     assert np.allclose(dec.S, S)
 
 
+def _inner_case():
+    rng = np.random.default_rng(8)
+    m, n, p = 30, 24, 3
+    I = rng.uniform(0, 1, (m, n))
+    J = rng.standard_normal((m * n, p))
+    return I, O.Annihilator(J), 1.0 / np.sqrt(max(m, n))
+
+
 def test_inner_loop_with_svdws_reaches_the_same_optimum():
     """The LADMAP inner loop with the warm-started decomposition in place of
     the full SVD (switch at eps_svd = 1e-3 relative) reaches the exact
@@ -81,31 +89,43 @@ def test_inner_loop_with_svdws_reaches_the_same_optimum():
     -- every increase of the penalty moves M -- so the warm step is taken in
     a minority of the iterations; with a looser switch the approximate
     shrinkage stalls the loop.)"""
-    rng = np.random.default_rng(8)
-    m, n, p = 30, 24, 3
-    I = rng.uniform(0, 1, (m, n))
-    J = rng.standard_normal((m * n, p))
-    Jp = O.Annihilator(J)
-    lam = 1.0 / np.sqrt(max(m, n))
+    I, Jp, lam = _inner_case()
     prm = O.Params()
     Z = np.zeros_like(I)
     exact = O.ladmap_inner(I, Jp, lam, I, Z, Z, prm)
-    state = {"prev": None, "warm": 0, "calls": 0}
-    orig = O.tilt_oracle.svt
-
-    def svt_ws(Mk, eps):
-        dec, info = W.svdws(state["prev"], Mk, eps_svd=1e-3)
-        state["prev"] = dec
-        state["warm"] += int(info.warm)
-        state["calls"] += 1
-        return W.shrink(dec, eps), np.sort(np.abs(dec.S))[::-1]
-
-    O.tilt_oracle.svt = svt_ws
-    try:
-        ws = O.ladmap_inner(I, Jp, lam, I, Z, Z, prm)
-    finally:
-        O.tilt_oracle.svt = orig
-    assert state["warm"] > 0
+    op = W.SvdwsSvt(eps_svd=1e-3)
+    ws = O.ladmap_inner(I, Jp, lam, I, Z, Z, prm, svt_op=op)
+    assert op.steps > 0
     oe = O.objective(exact.A, exact.E, lam)
     ow = O.objective(ws.A, ws.E, lam)
-    assert abs(ow - oe) <= 1e-4 * oe, (ow, oe, state)
+    assert abs(ow - oe) <= 1e-4 * oe, (ow, oe, op.steps)
+
+
+def test_fixed_schedule_svt():
+    """The fixed schedule: every = 1 is the exact loop bit for bit; with
+    every = 2 the odd iterations are one Cayley step from the previous full
+    SVD (the step the pinned curve functions give), and the loop still
+    reaches the exact objective to 1e-4 (76 instead of 57 iterations)."""
+    I, Jp, lam = _inner_case()
+    prm = O.Params()
+    Z = np.zeros_like(I)
+    exact = O.ladmap_inner(I, Jp, lam, I, Z, Z, prm)
+    one = O.ladmap_inner(I, Jp, lam, I, Z, Z, prm, svt_op=W.SvdwsSvt(every=1))
+    assert one.iters == exact.iters and np.array_equal(one.A, exact.A) and np.array_equal(one.E, exact.E)
+    rng = np.random.default_rng(3)
+    M0 = rng.standard_normal((9, 6))
+    M1 = M0 + 1e-2 * rng.standard_normal((9, 6))
+    op = W.SvdwsSvt(every=2)
+    A0, _ = op(M0, 0.1, 0)
+    assert np.allclose(A0, O.svt(M0, 0.1)[0], atol=1e-12)
+    A1, _ = op(M1, 0.1, 1)
+    prev = W.svd_full(M0)
+    PU, PS, PV = W.projected_gradients(prev.U, prev.S, prev.V, M1)
+    f1, f2 = W.derivatives(prev.U, prev.S, prev.V, M1, PU, PS, PV)
+    Ut, St, Vt = W.curve(prev.U, prev.S, prev.V, PU, PS, PV, -f1 / f2)
+    assert op.steps == 1 and np.allclose(A1, W.shrink(W.WarmSVD(Ut, St, Vt, M1), 0.1), atol=1e-12)
+    two_op = W.SvdwsSvt(every=2)
+    two = O.ladmap_inner(I, Jp, lam, I, Z, Z, prm, svt_op=two_op)
+    oe = O.objective(exact.A, exact.E, lam)
+    assert two_op.steps == two.iters // 2 and two.iters < prm.max_inner
+    assert abs(O.objective(two.A, two.E, lam) - oe) <= 1e-4 * oe
