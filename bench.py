@@ -120,7 +120,10 @@ def solve_flops(res, p, warm=False):
     return f
 
 
-def kernel_source_sha(sources=("tilt_kernels.hip",)) -> str:
+KERNEL_SOURCES = ("tilt_kernels.hip", "tilt_svdws.inc", "tilt_rasl.inc")  # one translation unit
+
+
+def kernel_source_sha(sources=KERNEL_SOURCES) -> str:
     import hashlib
 
     h = hashlib.sha256()
@@ -129,7 +132,7 @@ def kernel_source_sha(sources=("tilt_kernels.hip",)) -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(profile: str, sources=("tilt_kernels.hip",)):
+def profiled_traffic(profile: str, sources=KERNEL_SOURCES):
     """HBM bytes per launch of a kernel from its committed rocprofv3 summary
     (profiles/<profile>), or None when the kernel source has changed since
     the counters were taken (or no summary exists)."""
@@ -1038,7 +1041,7 @@ def rasl_main(args):
     roofline = {"kernel": "k_rasl (whole RASL solves, one workgroup per set)", "bound": "alu",
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-                "traffic": (profiled_traffic("k_rasl_rasl256x32x16x24.md", ("tilt_kernels.hip", "tilt_rasl.inc"))
+                "traffic": (profiled_traffic("k_rasl_rasl256x32x16x24.md")
                             if nsets == 256 and args.rasl_max_outer == 10 else None),
                 "kernel_ms": round(kernel_ms, 2), "flops_per_launch": flops,
                 "peak_measured": round(fma_peak, 2), "frac_of_measured": round(achieved / fma_peak, 4)}
