@@ -121,6 +121,9 @@ def solve_flops(res, p, warm=False):
 
 
 KERNEL_SOURCES = ("tilt_kernels.hip", "tilt_svdws.inc", "tilt_rasl.inc")  # one translation unit
+# committed rocprofv3 summaries of the fused kernel: (workload, svt_mode) -> file under profiles/
+PROFILES = {("batch-256x100x100-projective", 0): "k_fused_batch256x100x100.md",
+            ("uneven-1024-32to256-mixed", 1): "k_fused_uneven1024.md"}
 
 
 def kernel_source_sha(sources=KERNEL_SOURCES) -> str:
@@ -533,9 +536,9 @@ def main():
             "peak": PEAK_FP32_VECTOR_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-            "traffic": (profiled_traffic("k_fused_batch256x100x100.md")
-                        if names[args.workload] == "batch-256x100x100-projective" and args.svt_mode == 0
-                        and args.pyramid == 1 and args.patches in (None, 256) else None),
+            "traffic": profiled_traffic(PROFILES[(names[args.workload], args.svt_mode)])
+                       if (names[args.workload], args.svt_mode) in PROFILES and args.pyramid == 1
+                       and args.patches is None else None,
             "work_model": "cold one-sided Jacobi, 6 S m n^2 flops and 8 S m n^2 LDS bytes per SVD (S: measured "
                           "sweeps, n = min side)",
             "kernel_ms": round(k_ms, 2),
