@@ -254,3 +254,21 @@ def test_svdws_fused_solve_matches_oracle(tilt, ctx, device):
     assert r["status"] >= 0 and r["counters"]["svdws_steps"] == steps and steps >= 10
     assert terr <= 1e-4
     assert abs(r["objective"] - ref.objective) <= 1e-4 * ref.objective
+
+
+def test_svdws_mode_outside_the_warm_layout_runs_the_cold_svt(tilt, ctx, device):
+    """svt_mode 4 needs the warm-started Jacobi in LDS; on a shape whose
+    rotation does not fit beside the rows (175 x 158) the SVT is the cold
+    one: the inner loop equals svt_mode 0 bit for bit and takes no step."""
+    m, n, p, count = 175, 158, 3, 2
+    _, _, dI, dJ, dA0, dE0 = _inner_inputs(tilt, m, n, p, count, device)
+    import torch
+
+    dA4, dE4 = torch.zeros_like(dA0), torch.zeros_like(dE0)
+    t0 = tilt.default_params(svt_mode=0, fixed_iters=1, max_inner=6)
+    t4 = tilt.default_params(svt_mode=4, svdws_every=2, fixed_iters=1, max_inner=6)
+    print(f"svt_mode 0 and 4 on {count} x {m}x{n}", flush=True)
+    _, r0 = ctx.inner_batch(dI.data_ptr(), dJ.data_ptr(), count, m, n, p, t0, dA0.data_ptr(), dE0.data_ptr())
+    _, r4 = ctx.inner_batch(dI.data_ptr(), dJ.data_ptr(), count, m, n, p, t4, dA4.data_ptr(), dE4.data_ptr())
+    assert torch.equal(dA0, dA4) and torch.equal(dE0, dE4)
+    assert all(r["counters"]["svdws_steps"] == 0 for r in r4)
