@@ -77,9 +77,13 @@ typedef struct {
                            SVT's accumulated rotation applied to the new
                            iterate (re-orthonormalised by a Newton-Schulz
                            step every 4 calls); same result to rounding,
-                           fewer sweeps.  Used where the Jacobi rows and the
-                           rotation fit in LDS together (about
-                           min(m,n) * max(m,n) <= 18k); cold elsewhere.
+                           fewer sweeps.  Windows whose rows and rotation
+                           fit in LDS together (about min(m,n) * max(m,n)
+                           <= 18k) run it in LDS; larger ones run the tiled
+                           Jacobi through device memory with the rotation
+                           rows staged beside the Jacobi rows (windows that
+                           would fit LDS without the rotation take the tiled
+                           layout for this).
                            2: as 1, with the start product formed from
                            bfloat16 operands on the matrix cores (FP32
                            accumulation), then refined: the product is
