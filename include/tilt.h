@@ -234,7 +234,8 @@ int tilt_ctx_last_kernel_ms(tilt_ctx* ctx, double* ms);
  * neither waits for nor delays the batch. */
 int tilt_ctx_progress(tilt_ctx* ctx, int* finished, int* total);
 
-/* Bytes of device workspace one problem needs (for admission control). */
+/* Bytes of device workspace one problem needs (for admission control): an
+ * upper bound over the SVT modes, for a single pyramid level. */
 size_t tilt_workspace_bytes(const tilt_problem* prob);
 
 /* Batched path: `count` problems whose image pointers are DEVICE pointers

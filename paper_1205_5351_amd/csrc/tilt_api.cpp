@@ -1229,11 +1229,15 @@ int tilt_ctx_last_kernel_ms(tilt_ctx* ctx, double* ms) {
 
 size_t tilt_workspace_bytes(const tilt_problem* prob) {
     if (!prob) return 0;
-    // the larger of the cold and the warm-started layout
+    // the largest of the cold and the warm-started layouts (with the region
+    // of the SVD with warm start where svt_mode 4 can use it)
     ShapeCfg sc{}, sw{};
     if (shape_config(prob->m, prob->n, &sc) != TILT_OK || shape_config(prob->m, prob->n, &sw, true) != TILT_OK)
         return 0;
-    return std::max(sc.ws_floats, sw.ws_floats) * sizeof(float) + sizeof(PatchDesc) + sizeof(PatchState);
+    size_t w = std::max(sc.ws_floats, sw.ws_floats);
+    if (sc.sb == 0 && sc.warm_lds > 0)
+        w = std::max(w, (size_t)NPLANES * sc.nc * sc.ldg + svdws_region_words(sc.nr, sc.nc));
+    return w * sizeof(float) + sizeof(PatchDesc) + sizeof(PatchState);
 }
 
 int tilt_solve_batch(tilt_ctx* ctx, const tilt_problem* probs, int count, const tilt_params* prm,

@@ -272,3 +272,22 @@ def test_svdws_mode_outside_the_warm_layout_runs_the_cold_svt(tilt, ctx, device)
     _, r4 = ctx.inner_batch(dI.data_ptr(), dJ.data_ptr(), count, m, n, p, t4, dA4.data_ptr(), dE4.data_ptr())
     assert torch.equal(dA0, dA4) and torch.equal(dE0, dE4)
     assert all(r["counters"]["svdws_steps"] == 0 for r in r4)
+
+
+def test_svdws_mode_served_equals_batched_over_pyramid_levels(tilt, device):
+    """svt_mode 4 (fixed schedule) through the serving kernel, three pyramid
+    levels per request (the decomposition is dropped at each level change):
+    the same bits as the batched fused launch, and Cayley steps taken."""
+    import tilt_synth as ts
+    from gpu_util import solve_on_device
+    from test_gpu_serving import _same, _serve
+
+    ps = ts.make_batch(4, [20, 15, 7, 3])
+    tp = tilt.default_params(svt_mode=4, svdws_every=2, pyramid_levels=3, max_outer=4, max_inner=40)
+    print("svt_mode 4 served vs batched, 4 requests x 3 levels", flush=True)
+    with tilt.Context(0) as c:
+        served = _serve(tilt, c, device, ps, tp)
+        _, batched = solve_on_device(tilt, c, ps, device, tp)
+    for a, b in zip(served, batched):
+        assert a["status"] == b["status"] and _same(a, b)
+    assert sum(b["counters"]["svdws_steps"] for b in batched) > 0
