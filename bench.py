@@ -305,6 +305,9 @@ def main():
     import tilt_synth as ts
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.svt_mode is None:
+        # the uneven workload is defined with warm starts; the others cold
+        args.svt_mode = 1 if args.workload == 2 else 0
     if args.serve:
         return serve_main(args)
     if args.svdws:
@@ -323,8 +326,6 @@ def main():
         return convergence_main(args)
     dev = torch.device("cuda:0")
     names = ts.config_names()
-    if args.svt_mode is None:
-        args.svt_mode = 1 if args.workload == 2 else 0
     t_gen = time.perf_counter()
     patches = ts.make_config(args.workload, count=args.patches)
     log(f"generated {len(patches)} patches of '{names[args.workload]}' in {time.perf_counter() - t_gen:.1f}s")

@@ -234,8 +234,11 @@ int tilt_ctx_last_kernel_ms(tilt_ctx* ctx, double* ms);
  * neither waits for nor delays the batch. */
 int tilt_ctx_progress(tilt_ctx* ctx, int* finished, int* total);
 
-/* Bytes of device workspace one problem needs (for admission control): an
- * upper bound over the SVT modes, for a single pyramid level. */
+/* Bytes of device workspace one problem needs (for admission control), for
+ * a single pyramid level and svt_mode 0-3: the larger of the cold and the
+ * warm-started layout.  svt_mode 4 adds, where it runs (windows whose
+ * warm-started SVT fits LDS), the region of the SVD with warm start: about
+ * 4 (13 m n + 14 min(m,n)^2) bytes. */
 size_t tilt_workspace_bytes(const tilt_problem* prob);
 
 /* Batched path: `count` problems whose image pointers are DEVICE pointers

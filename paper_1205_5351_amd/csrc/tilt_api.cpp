@@ -544,6 +544,15 @@ void fill_result(const PatchDesc& d0, const PatchState& s, tilt_result* r, doubl
     r->counters.svdws_steps = s.svdws_steps;
 }
 
+// Whether idle workgroups of the fused and serving kernels help windows
+// beyond LDS with their Jacobi rounds: on unless TILT_HELPERS=0 in the
+// environment.  Only who runs which super-block pair depends on it, not the
+// results.
+bool helpers_enabled() {
+    const char* e = std::getenv("TILT_HELPERS");
+    return !(e && e[0] == '0');
+}
+
 }  // namespace host
 }  // namespace tilt
 
@@ -739,13 +748,6 @@ int run_plain_request(tilt_ctx* ctx, size_t lds, const SolverParams& sp, int L, 
     return TILT_OK;
 }
 
-// Whether idle workgroups of the fused kernel help windows beyond LDS with
-// their Jacobi rounds: on unless TILT_HELPERS=0 in the environment.  Only
-// who runs which super-block pair depends on it, not the results.
-bool helpers_enabled() {
-    const char* e = std::getenv("TILT_HELPERS");
-    return !(e && e[0] == '0');
-}
 
 int solve_batch_impl(tilt_ctx* ctx, const tilt_problem* probs, int count, const tilt_params* prm,
                      tilt_result* results, void* hip_stream, bool plain) {
@@ -1229,15 +1231,11 @@ int tilt_ctx_last_kernel_ms(tilt_ctx* ctx, double* ms) {
 
 size_t tilt_workspace_bytes(const tilt_problem* prob) {
     if (!prob) return 0;
-    // the largest of the cold and the warm-started layouts (with the region
-    // of the SVD with warm start where svt_mode 4 can use it)
+    // the larger of the cold and the warm-started layout (svt_mode 0-3)
     ShapeCfg sc{}, sw{};
     if (shape_config(prob->m, prob->n, &sc) != TILT_OK || shape_config(prob->m, prob->n, &sw, true) != TILT_OK)
         return 0;
-    size_t w = std::max(sc.ws_floats, sw.ws_floats);
-    if (sc.sb == 0 && sc.warm_lds > 0)
-        w = std::max(w, (size_t)NPLANES * sc.nc * sc.ldg + svdws_region_words(sc.nr, sc.nc));
-    return w * sizeof(float) + sizeof(PatchDesc) + sizeof(PatchState);
+    return std::max(sc.ws_floats, sw.ws_floats) * sizeof(float) + sizeof(PatchDesc) + sizeof(PatchState);
 }
 
 int tilt_solve_batch(tilt_ctx* ctx, const tilt_problem* probs, int count, const tilt_params* prm,

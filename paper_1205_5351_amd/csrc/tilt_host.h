@@ -43,6 +43,8 @@ struct ShapeCfg {
 int shape_config(int m, int n, ShapeCfg* out, bool warm = false);
 int tiled_config(const ShapeCfg& c, ShapeCfg* out, bool need_warm = false);
 int help_plan();
+// Whether idle workgroups help windows beyond LDS (TILT_HELPERS != 0).
+bool helpers_enabled();
 double predicted_cost(const PatchDesc& d);
 
 int validate_params(const tilt_params* p);

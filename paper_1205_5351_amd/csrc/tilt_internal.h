@@ -315,9 +315,11 @@ hipError_t launch_wide_update(const PatchDesc* d, PatchState* st, const int* act
 hipError_t launch_wide_end(const PatchDesc* d, PatchState* st, int count, hipStream_t s);
 hipError_t launch_rasl(const RaslDesc* d, PatchState* st, const SolverParams& prm, int count, int* queue, int grid,
                        size_t lds, hipStream_t s);
+// fc, help: the helpers' control block (FusedCtl with a GangCtl per ring
+// slot) and whether idle workgroups help the leaders of tiled requests.
 hipError_t launch_serve(ServeCtl* ctl, ServeSlot* slots, PatchDesc* ddesc, PatchState* dstates,
-                        unsigned long long* ctr, int ring, long long idle_ticks, int grid, size_t lds,
-                        hipStream_t s);
+                        unsigned long long* ctr, int ring, long long idle_ticks, FusedCtl* fc, int help, int grid,
+                        size_t lds, hipStream_t s);
 hipError_t launch_pyramid_build(const PatchDesc* d, int levels, hipStream_t s);
 hipError_t launch_level_begin(const PatchDesc* d, PatchState* st, int first, hipStream_t s);
 hipError_t launch_pyramid_jobs(const float* image, int H, int W, long long stride, float* out, int levels,

@@ -2177,6 +2177,7 @@ __device__ __noinline__ int svdws_try(const PatchDesc& d, PatchState* st, const 
     float* A = d.ws + PL_A * np;
     const SvdwsRegion R = svdws_region(d);
     const int have = st->svdws_ok;
+    __syncthreads();  // M was written by every thread of the workgroup (svt_form_m)
     double sums[2] = {0.0, 0.0};
     for (int e = threadIdx.x; e < mn; e += NT) {
         const int i = e / n, j = e - i * n;
@@ -2759,11 +2760,18 @@ __global__ void __launch_bounds__(NT) k_fused(const PatchDesc* __restrict__ desc
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(NT) k_serve(ServeCtl* ctl, ServeSlot* slots, PatchDesc* ddesc, PatchState* dstates,
-                                               unsigned long long* ctr, int ring, long long idle_ticks) {
+                                               unsigned long long* ctr, int ring, long long idle_ticks, FusedCtl* fc,
+                                               int help) {
     __shared__ long long sh_seq;
+    __shared__ GangCtl sh_job;
+    __shared__ unsigned sh_id;
+    __shared__ int sh_pair;
     float* lds = reinterpret_cast<float*>(tilt_dyn_lds);
     const int tid = threadIdx.x;
     long long idle_since = (long long)wall_clock64();
+    // counted in fc->idle while it has no request (help = 1): leaders of
+    // tiled requests publish their rounds while idle workgroups exist
+    bool counted_idle = false;
     for (;;) {
         if (tid == 0) {
             unsigned long long* head = ctr;
@@ -2817,13 +2825,37 @@ __global__ void __launch_bounds__(NT) k_serve(ServeCtl* ctl, ServeSlot* slots, P
         __syncthreads();
         const long long seq = sh_seq;
         __syncthreads();
-        if (seq == -2) break;
+        if (seq == -2) {
+            if (counted_idle && tid == 0) __hip_atomic_fetch_add(&fc->idle, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
         if (seq < 0) {
-            if (tid == 0) {
-                for (int k = 0; k < 8; ++k) __builtin_amdgcn_s_sleep(127);
+            if (help) {
+                // between two polls of the ring (~30 us apart), help the
+                // leaders of tiled requests (helpers as in the fused kernel)
+                if (!counted_idle && tid == 0)
+                    __hip_atomic_fetch_add(&fc->idle, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                counted_idle = true;
+                for (int k = 0; k < 16; ++k) {
+                    const int g = help_find(fc, &sh_job, &sh_id, &sh_pair);
+                    if (g >= 0) {
+                        help_run(fc, g, &sh_job, sh_id, sh_pair, lds);
+                        k = 0;
+                        continue;
+                    }
+                    __builtin_amdgcn_s_sleep(64);
+                }
+            } else {
+                if (tid == 0) {
+                    for (int k = 0; k < 8; ++k) __builtin_amdgcn_s_sleep(127);
+                }
+                __syncthreads();
             }
-            __syncthreads();
             continue;
+        }
+        if (counted_idle) {
+            if (tid == 0) __hip_atomic_fetch_add(&fc->idle, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            counted_idle = false;
         }
         const int slot = (int)(seq % ring);
         ServeSlot* sl = slots + slot;
@@ -2845,6 +2877,17 @@ __global__ void __launch_bounds__(NT) k_serve(ServeCtl* ctl, ServeSlot* slots, P
         __syncthreads();
         const SolverParams prm = sh_prm;
         solve_request(dl, levels, st, prm, lds);
+        if (tid == 0) {
+            // a tiled request's leader leaves the helpers' registry; the
+            // slot's control block is reused by the next request in it
+            // (its round ids and counters run on, so no stale claim of
+            // this request can match a round of the next)
+            GangCtl* c = dl[0].gang;
+            if (c && c->slot >= 0) {
+                __hip_atomic_store(&fc->slots[c->slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                c->slot = -1;
+            }
+        }
         __syncthreads();
         {
             const unsigned long long* s0 = reinterpret_cast<const unsigned long long*>(st);
@@ -3252,11 +3295,12 @@ hipError_t launch_fused(const PatchDesc* d, PatchState* st, const SolverParams& 
 }
 
 hipError_t launch_serve(ServeCtl* ctl, ServeSlot* slots, PatchDesc* ddesc, PatchState* dstates,
-                        unsigned long long* ctr, int ring, long long idle_ticks, int grid, size_t lds,
-                        hipStream_t s) {
+                        unsigned long long* ctr, int ring, long long idle_ticks, FusedCtl* fc, int help, int grid,
+                        size_t lds, hipStream_t s) {
     hipError_t e = set_lds((const void*)k_serve, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_serve, dim3(grid), dim3(NT), lds, s, ctl, slots, ddesc, dstates, ctr, ring, idle_ticks);
+    hipLaunchKernelGGL(k_serve, dim3(grid), dim3(NT), lds, s, ctl, slots, ddesc, dstates, ctr, ring, idle_ticks, fc,
+                       help);
     return hipGetLastError();
 }
 

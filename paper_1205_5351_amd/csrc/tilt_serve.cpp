@@ -98,6 +98,7 @@ struct ServeState {
     ServeCtl* ctl = nullptr;      // pinned, coherent
     ServeSlot* slots = nullptr;   // pinned, coherent
     DevBuf head, ddesc, dstates, arena_buf;
+    DevBuf help;                  // FusedCtl, then one GangCtl per ring slot (helpers)
     Arena arena;
     size_t arena_bytes = 0;
     hipStream_t stream = nullptr;
@@ -132,6 +133,24 @@ int serve_init(tilt_ctx* ctx) {
         S->arena_buf.reserve(S->arena_bytes) != hipSuccess)
         return fail(TILT_ERR_NOMEM);
     S->arena.reset(S->arena_bytes);
+    // helpers' control blocks: a FusedCtl (idle count, registry) and the
+    // GangCtl of each ring slot, unregistered; round ids and counters run
+    // on across the requests of a slot
+    {
+        const size_t bytes = sizeof(FusedCtl) + sizeof(GangCtl) * kRing;
+        if (S->help.reserve(bytes) != hipSuccess) return fail(TILT_ERR_NOMEM);
+        std::vector<unsigned char> blob(bytes, 0);
+        FusedCtl* dfc = reinterpret_cast<FusedCtl*>(S->help.p);
+        GangCtl* dgang = reinterpret_cast<GangCtl*>(reinterpret_cast<unsigned char*>(S->help.p) + sizeof(FusedCtl));
+        reinterpret_cast<FusedCtl*>(blob.data())->gangs = dgang;
+        GangCtl* hgang = reinterpret_cast<GangCtl*>(blob.data() + sizeof(FusedCtl));
+        for (int k = 0; k < kRing; ++k) {
+            hgang[k].slot = -1;
+            hgang[k].fc = dfc;
+        }
+        if (hipMemcpy(S->help.p, blob.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(TILT_ERR_DEVICE);
+    }
     if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&S->done_ev, hipEventDisableTiming) != hipSuccess)
         return fail(TILT_ERR_DEVICE);
@@ -183,7 +202,8 @@ int ensure_kernel(tilt_ctx* ctx, ServeState* S) {
     const long long idle_ticks = (long long)(kIdleMs * ctx->wall_rate_khz);
     HIP_TRY(launch_serve(S->ctl, S->slots, reinterpret_cast<PatchDesc*>(S->ddesc.p),
                          reinterpret_cast<PatchState*>(S->dstates.p),
-                         reinterpret_cast<unsigned long long*>(S->head.p), kRing, idle_ticks, ctx->num_cus, S->lds,
+                         reinterpret_cast<unsigned long long*>(S->head.p), kRing, idle_ticks,
+                         reinterpret_cast<FusedCtl*>(S->help.p), helpers_enabled() ? 1 : 0, ctx->num_cus, S->lds,
                          S->stream));
     HIP_TRY(hipEventRecord(S->done_ev, S->stream));
     S->launched = true;
@@ -205,6 +225,14 @@ int publish(tilt_ctx* ctx, ServeState* S) {
         R.ws_bytes = bytes;
         RequestPlan plan = R.plan;
         rebase_plan(&plan, base + off / sizeof(float));
+        // a request with a tiled level names its slot's control block, so
+        // that idle workgroups can help its Jacobi rounds
+        bool tiled = false;
+        for (int l = 0; l < plan.levels; ++l) tiled |= plan.d[l].sb > 0;
+        GangCtl* gang = tiled && helpers_enabled()
+                            ? reinterpret_cast<GangCtl*>(reinterpret_cast<unsigned char*>(S->help.p) + sizeof(FusedCtl)) + slot
+                            : nullptr;
+        for (int l = 0; l < plan.levels; ++l) plan.d[l].gang = gang;
         ServeSlot& sl = S->slots[slot];
         for (int l = 0; l < MAX_LEVELS; ++l) sl.d[l] = plan.d[l];
         sl.prm = R.prm;
@@ -236,6 +264,7 @@ void serve_release(ServeState* S) {
     S->ddesc.release();
     S->dstates.release();
     S->arena_buf.release();
+    S->help.release();
     if (S->slots) (void)hipHostFree(S->slots);
     if (S->ctl) (void)hipHostFree(S->ctl);
     delete S;

@@ -146,6 +146,30 @@ def test_serving_equals_batched(tilt, device):
         assert _same(a, b)
 
 
+def test_serving_helps_tiled_requests(tilt, device):
+    """Requests whose SVT is tiled (windows beyond LDS) are helped by the
+    serving kernel's idle workgroups, which take super-block pairs of the
+    leaders' Jacobi rounds; who runs a pair does not change the result, so
+    the served results equal a batch solved with no helpers at all
+    (TILT_HELPERS=0), bit for bit.  Twice in a row, so the second pair of
+    tiled requests reuses control blocks of the ring."""
+    import os
+
+    ps = ts.make_batch(4, [8, 32, 23, 15])          # two tiled windows, two in LDS
+    assert sum(1 for p in ps if tilt.svt_layout(p.m, p.n)[4]) == 2
+    tp = tilt.default_params(fixed_iters=1, max_outer=2, max_inner=40)
+    with tilt.Context(0) as c:
+        served = _serve(tilt, c, device, ps, tp)
+        served2 = _serve(tilt, c, device, ps, tp)
+        os.environ["TILT_HELPERS"] = "0"
+        try:
+            _, alone = solve_on_device(tilt, c, ps, device, tp)
+        finally:
+            del os.environ["TILT_HELPERS"]
+    for a, a2, b in zip(served, served2, alone):
+        assert a["status"] == b["status"] and _same(a, b) and _same(a2, b)
+
+
 def test_serving_admits_requests_while_others_run(tilt, device):
     ps = ts.make_batch(4, [23, 20, 15, 7, 30, 35])
     tp = tilt.default_params(max_outer=6)
