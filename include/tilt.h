@@ -369,7 +369,8 @@ int tilt_warp_jacobian(tilt_ctx* ctx, const tilt_problem* probs, const double* t
  * zero.  max(m, n) <= 2048, min(m, n) <= 1024; pyramid_levels must be 1.
  * When the SVT does not fit LDS and count <= (compute units) / 8, each
  * Jacobi round of a problem runs on many workgroups (one per super-block
- * pair, one launch per round) instead of one workgroup per problem. */
+ * pair, one launch per round) instead of one workgroup per problem.  For
+ * min(m, n) > 256 the cap jacobi_tol is scaled by sqrt(256 / min(m, n)). */
 int tilt_inner_batch(tilt_ctx* ctx, const float* I, const float* J, int count, int m, int n, int p,
                      const tilt_params* prm, float* A, float* E, tilt_result* results, void* hip_stream);
 
