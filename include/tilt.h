@@ -99,10 +99,13 @@ typedef struct {
                            next step starts from.  An approximation: the
                            shrinkage is not exact after a step.           */
     float jacobi_tol;   /* rotate a pair when |a.b| > tol ||a|| ||b||, with
-                           tol = min(jacobi_tol, max(1e-7, eps2 / (10 mu)))
-                           in the inner loop (the SVT's rounding enters Cond2
+                           tol = min(cap, max(1e-7, eps2 / (10 mu))) in the
+                           inner loop (the SVT's rounding enters Cond2
                            multiplied by mu, up to ~1e3 on large windows) and
-                           tol = jacobi_tol elsewhere; default 1e-6          */
+                           tol = cap elsewhere; cap = jacobi_tol for rows of
+                           up to 256 floats (max(m, n)), jacobi_tol
+                           sqrt(256 / max(m, n)) for longer rows; default
+                           1e-6                                              */
     int max_sweeps;     /* Jacobi sweep cap, default 40                       */
     int pyramid_levels; /* 1 (default): solve the window as given.  L in 2..4:
                            solve coarse to fine over L levels; level l has the
@@ -369,8 +372,7 @@ int tilt_warp_jacobian(tilt_ctx* ctx, const tilt_problem* probs, const double* t
  * zero.  max(m, n) <= 2048, min(m, n) <= 1024; pyramid_levels must be 1.
  * When the SVT does not fit LDS and count <= (compute units) / 8, each
  * Jacobi round of a problem runs on many workgroups (one per super-block
- * pair, one launch per round) instead of one workgroup per problem.  For
- * min(m, n) > 256 the cap jacobi_tol is scaled by sqrt(256 / min(m, n)). */
+ * pair, one launch per round) instead of one workgroup per problem. */
 int tilt_inner_batch(tilt_ctx* ctx, const float* I, const float* J, int count, int m, int n, int p,
                      const tilt_params* prm, float* A, float* E, tilt_result* results, void* hip_stream);
 

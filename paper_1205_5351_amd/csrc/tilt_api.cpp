@@ -1453,13 +1453,7 @@ int tilt_inner_batch(tilt_ctx* ctx, const float* I, const float* J, int count, i
         return TILT_ERR_ARG;
     int st = validate_params(prm_in);
     if (st != TILT_OK) return st;
-    // One shape per call: beyond 256 Jacobi rows (min(m, n)) the tolerance
-    // cap shrinks like 1/sqrt(rows), as the FP32 rounding of the rows' inner
-    // products grows like sqrt(length) (reading R17).
-    tilt_params prm_local = *prm_in;
-    const int rows = std::min(m, n);
-    if (rows > 256) prm_local.jacobi_tol = (float)(prm_in->jacobi_tol * std::sqrt(256.0 / rows));
-    const tilt_params* prm = &prm_local;
+    const tilt_params* prm = prm_in;
     if (prm->pyramid_levels > 1) return TILT_ERR_ARG;
     if (count == 0) return TILT_OK;
     ShapeCfg sc{};

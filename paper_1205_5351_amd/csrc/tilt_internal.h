@@ -142,11 +142,18 @@ __host__ __device__ inline size_t svdws_region_words(int m, int n) {
 // of the tolerance, relative to ||M|| ~ 1 for the normalised window) enters
 // the Cond2 quantity multiplied by mu, so the tolerance follows a tenth of
 // the resolution Cond2 needs, eps2 / (10 mu), between the FP32 floor 1e-7
-// and the configured tolerance.
-__host__ __device__ inline float svt_tolerance(float tol_max, double eps2, double mu) {
+// and the cap.  The cap is tol_max for rows of up to 256 floats and
+// tol_max sqrt(256 / len) for longer rows (len: the row length, the larger
+// side), as the FP32 rounding of a row inner product grows like the
+// square root of its length.
+__host__ __device__ inline float svt_tolerance_cap(float tol_max, int len) {
+    return len > 256 ? (float)((double)tol_max * sqrt(256.0 / (double)len)) : tol_max;
+}
+__host__ __device__ inline float svt_tolerance(float tol_max, double eps2, double mu, int len) {
+    const double cap = (double)svt_tolerance_cap(tol_max, len);
     double t = 0.1 * eps2 / mu;
     if (!(t >= 1e-7)) t = 1e-7;
-    if (t > (double)tol_max) t = (double)tol_max;
+    if (t > cap) t = cap;
     return (float)t;
 }
 

@@ -1770,7 +1770,7 @@ __device__ void dev_factor(const PatchDesc& d, PatchState* st, const SolverParam
     if (!(mu0 > 0.0)) {
         const SvtLds L = carve_for(d, lds);
         JacobiStats js{0, 0, 0};
-        svd_rows(d, I, d.ws + NPLANES * np, L, prm.jacobi_tol, prm.max_sweeps, js);
+        svd_rows(d, I, d.ws + NPLANES * np, L, svt_tolerance_cap(prm.jacobi_tol, d.nr), prm.max_sweeps, js);
         __shared__ float sh_smax;
         if (tid == 0) {
             float mx = 0.f;
@@ -2270,7 +2270,7 @@ __device__ void dev_svt(const PatchDesc& d, PatchState* st, const SolverParams& 
     const SvtLds L = (warm && !tiled) ? carve_lds_warm(lds, nc, ld, d.tb, &Rl) : carve_for(d, lds);
 
     svt_form_m(d, st, (!tiled && !warm) ? L.B : nullptr);
-    const float tol = svt_tolerance(prm.jacobi_tol, prm.eps2, st->mu);
+    const float tol = svt_tolerance(prm.jacobi_tol, prm.eps2, st->mu, d.nr);
     JacobiStats js{0, 0, 0};
     if (warm && tiled) {
         svt_tiled_warm(d, st, prm, L, tol, js);
@@ -3024,7 +3024,7 @@ __global__ void __launch_bounds__(NT) k_wide_round(const PatchDesc* descs, Patch
     const PatchDesc& d = descs[idx];
     // inner-loop SVTs (eps2 > 0) follow mu as in dev_svt; the decomposition
     // of I for mu_0 uses tol_max
-    const float tol = eps2 > 0.0 ? svt_tolerance(tol_max, eps2, st->mu) : tol_max;
+    const float tol = eps2 > 0.0 ? svt_tolerance(tol_max, eps2, st->mu, d.nr) : svt_tolerance_cap(tol_max, d.nr);
     const int sb = d.sb;
     int I, J;
     superblock_pair(d.nsb, r, k, I, J);
