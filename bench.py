@@ -123,6 +123,7 @@ def solve_flops(res, p, warm=False):
 KERNEL_SOURCES = ("tilt_kernels.hip", "tilt_svdws.inc", "tilt_rasl.inc")  # one translation unit
 # committed rocprofv3 summaries of the fused kernel: (workload, svt_mode) -> file under profiles/
 PROFILES = {("batch-256x100x100-projective", 0): "k_fused_batch256x100x100.md",
+            ("batch-256x100x100-projective", 1): "k_fused_warm_batch256x100x100.md",
             ("uneven-1024-32to256-mixed", 1): "k_fused_uneven1024.md"}
 
 

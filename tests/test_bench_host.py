@@ -33,6 +33,18 @@ def test_profiled_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
     assert bench.profiled_traffic("no_such_profile.md") is None
 
 
+def test_every_registered_profile_names_its_source_and_traffic():
+    """Each committed summary the bench lines read carries the kernel source
+    hash it was taken on and the HBM bytes per launch, in the fields
+    profiled_traffic parses."""
+    for name in list(bench.PROFILES.values()) + ["k_rasl_rasl256x32x16x24.md"]:
+        text = open(os.path.join(ROOT, "profiles", name)).read()
+        fields = dict(line.strip().lstrip("- ").split(":", 1) for line in text.splitlines()
+                      if line.strip().lstrip("- ").startswith(("kernel_source_sha256_16:", "traffic_bytes:")))
+        assert len(fields["kernel_source_sha256_16"].strip()) == 16, name
+        assert int(fields["traffic_bytes"]) > 0, name
+
+
 def test_cold_jacobi_work_is_the_stated_model():
     """6 S m n^2 flops and 8 S m n^2 LDS bytes (n = min side), S summed
     over the patch's sweeps."""
