@@ -270,10 +270,14 @@ int tilt_solve_batch_plain(tilt_ctx* ctx, const tilt_problem* probs, int count,
  * must stay valid until the request is finished).  A_out / E_out: DEVICE
  * pointers (m x n row-major) or NULL, written when the request finishes.
  * On success *ticket identifies the request.  Argument errors (including
- * TILT_ERR_TOO_LARGE) are returned here and no ticket is issued.
+ * TILT_ERR_TOO_LARGE) are returned here and no ticket is issued; a device
+ * error while admitting queued requests (TILT_ERR_DEVICE) comes after the
+ * request was queued: *ticket is then set and the request can be polled.
  *
  * tilt_poll: TILT_PENDING while the request runs; otherwise fills *res
- * (A/E fields untouched), releases the request and returns its status.
+ * (A/E fields untouched), releases the request and returns its status (a
+ * device error while then admitting queued requests is left in
+ * tilt_last_error and reported by the next submit or poll).
  * Polling also admits queued requests and restarts the kernel when it has
  * exited after being idle (100 ms without work), so a caller waiting for
  * results must keep polling.  TILT_ERR_NOT_FOUND for unknown or already

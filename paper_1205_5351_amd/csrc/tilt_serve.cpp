@@ -322,8 +322,11 @@ int tilt_poll(tilt_ctx* ctx, unsigned long long ticket, tilt_result* res) {
             S->arena.release(R.ws_off);
             S->slot_ticket[slot] = 0;
             S->reqs.erase(it);
-            const int p = publish(ctx, S);
-            return p == TILT_OK ? status : p;
+            // the result is delivered: a device error while admitting the
+            // queued requests is left in tilt_last_error; they stay queued
+            // and the next submit or poll admits them again
+            (void)publish(ctx, S);
+            return status;
         }
     }
     const int p = publish(ctx, S);
