@@ -80,14 +80,16 @@ int tilt_svdws_batch(tilt_ctx* ctx, int count, int m, int n, const float* U, con
                          reinterpret_cast<float*>(ctx->scratch.p), stream));
     HIP_TRY(hipMemcpyAsync(jobs.data(), ctx->jobs.p, sizeof(SvdwsJob) * count, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    // status 1 (no step: f''(0) <= 0) is the caller's cue for a full SVD,
+    // reported per matrix only; the return value carries the worst error
     int worst = TILT_OK;
     for (int i = 0; i < count; ++i) {
         if (t_out) t_out[i] = jobs[i].t;
         if (f0_out) f0_out[i] = jobs[i].f0;
         if (ft_out) ft_out[i] = jobs[i].ft;
         if (status) status[i] = jobs[i].status;
-        worst = worse(worst, jobs[i].status == 1 ? TILT_WARN_MAXITER : jobs[i].status);
+        if (jobs[i].status < 0) worst = worse(worst, jobs[i].status);
     }
-    return worst < 0 ? worst : TILT_OK;
+    return worst;
 }
 
